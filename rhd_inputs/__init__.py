@@ -1,0 +1,328 @@
+"""Seeded synthetic inputs for the gray M1 radiation-hydrodynamics step.
+
+This module only builds problem descriptions and initial arrays: it holds none of
+the method's arithmetic (no closure, no fluxes, no time-step rule). Both the
+oracle and the GPU library are fed from here.
+
+A problem is a dict:
+
+  spec   -- grid, constants, switches (see ``default_spec``);
+  state  -- float64 arrays of shape (nz, ny, nx), C order, so that the flat cell
+            index is i + nx*(j + ny*k): rho, mx, my, mz, E, Er, Fx, Fy, Fz,
+            kP, kF (specific opacities) and optionally j (emissivity);
+  chat   -- reduced speed of light used by the steps;
+  dt, nsub, steps -- time stepping when the recipe fixes it (dt None means
+            "take the CFL step of the current state").
+
+Nondimensional code units throughout; r_gas = k_B/mu and a_R are part of spec.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+FIELDS = ("rho", "mx", "my", "mz", "E", "Er", "Fx", "Fy", "Fz")
+BASE_SEED = 20130601
+
+
+def default_spec(**over):
+    spec = dict(
+        nx=1, ny=1, nz=1,
+        dx=1.0, dy=1.0, dz=1.0,
+        gamma=5.0 / 3.0,
+        c_light=1.0, a_rad=1.0, r_gas=1.0,
+        iso_cs=1.0,
+        cfl=0.4,
+        theta_E=1.0, theta_F=0.51,
+        newton_rtol=1e-10, newton_maxit=50,
+        rho_floor=1e-10, p_floor=1e-14, er_floor=1e-30,
+        bc=("periodic",) * 6,
+        isothermal=False,
+        exchange="full",          # "full" | "absorb_only" | "none"
+        beta_tau=False,
+        rad_only=False,
+        precision="fp64",         # "fp64" | "mixed"
+    )
+    for k, v in over.items():
+        if k not in spec:
+            raise KeyError(f"unknown spec key {k!r}")
+        spec[k] = v
+    if isinstance(spec["bc"], str):
+        spec["bc"] = (spec["bc"],) * 6
+    return spec
+
+
+def _zeros(spec):
+    return np.zeros((spec["nz"], spec["ny"], spec["nx"]), dtype=np.float64)
+
+
+def cell_centres(spec, origin=(0.0, 0.0, 0.0)):
+    """Cell-centre coordinates (x, y, z) broadcast to shape (nz, ny, nx)."""
+    x = origin[0] + (np.arange(spec["nx"]) + 0.5) * spec["dx"]
+    y = origin[1] + (np.arange(spec["ny"]) + 0.5) * spec["dy"]
+    z = origin[2] + (np.arange(spec["nz"]) + 0.5) * spec["dz"]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def uniform_state(spec, rho=1.0, P=1.0, v=(0.0, 0.0, 0.0), Er=1.0, F=(0.0, 0.0, 0.0),
+                  kP=1.0, kF=1.0):
+    """Uniform gas and radiation; E is the ideal-gas total energy for pressure P."""
+    s = {k: _zeros(spec) for k in FIELDS}
+    s["rho"][:] = rho
+    s["mx"][:] = rho * v[0]
+    s["my"][:] = rho * v[1]
+    s["mz"][:] = rho * v[2]
+    ke = 0.5 * rho * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    s["E"][:] = (P / (spec["gamma"] - 1.0) if not spec["isothermal"] else 0.0) + ke
+    s["Er"][:] = Er
+    s["Fx"][:] = F[0]
+    s["Fy"][:] = F[1]
+    s["Fz"][:] = F[2]
+    s["kP"] = np.full_like(s["rho"], kP)
+    s["kF"] = np.full_like(s["rho"], kF)
+    return s
+
+
+def copy_state(state):
+    return {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v)
+            for k, v in state.items()}
+
+
+def random_phase_field(shape, kmin, kmax, rms, rng):
+    """Real periodic field: unit-amplitude Fourier modes with integer wavevectors
+    kmin <= |k| <= kmax and uniform random phases, scaled to the given RMS."""
+    nz, ny, nx = shape
+    kz = np.fft.fftfreq(nz, 1.0 / nz)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    kk = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    mask = (kk >= kmin) & (kk <= kmax)
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=kk.shape)
+    coef = np.where(mask, np.exp(1j * phase), 0.0)
+    field = np.fft.irfftn(coef, s=shape, axes=(0, 1, 2))
+    cur = float(np.sqrt(np.mean(field ** 2)))
+    return field * (rms / cur) if cur > 0 else field
+
+
+# --------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------
+
+def c1_diffusion(n=256):
+    """1D radiation-only M1 diffusion in a periodic unit box: scattering-dominated
+    static gas (rho kappa_F = 100, no absorption), chat = c = 1, Gaussian pulse
+    E_r = 1e-6 + exp(-(x-1/2)^2 / (2 0.05^2)), F = 0, CFL 0.4, to t = 0.05."""
+    spec = default_spec(nx=n, dx=1.0 / n, c_light=1.0, exchange="none", rad_only=True,
+                        theta_F=0.51, bc="periodic")
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=0.0, kP=0.0, kF=100.0)
+    X, _, _ = cell_centres(spec)
+    st["Er"][:] = 1e-6 + np.exp(-((X - 0.5) ** 2) / (2 * 0.05 ** 2))
+    dt = 0.4 * spec["dx"] / 1.0
+    steps = int(round(0.05 / dt))
+    return dict(name="c1_diffusion_1d", spec=spec, state=st, chat=1.0, dt=dt, nsub=1,
+                steps=steps, t_end=0.05, sigma0=0.05, D=1.0 / 300.0)
+
+
+def c2_linear_box(n=128, seed=BASE_SEED + 1, precision="mixed", beta_tau=False):
+    """3D RHD linear-perturbation box: periodic n^3 on [0,1)^3, rho = 1, P = 1,
+    gamma = 5/3, E_r = a_R T^4 = 1, kappa_P = kappa_F = 10, a0 = sqrt(5/3),
+    chat = 20 a0, c = 1e4 a0; random-phase perturbations of RMS 1e-4 in rho and E_r
+    over integer wavenumbers 1..8; 10 gas steps with chat-limited subcycles."""
+    a0 = math.sqrt(5.0 / 3.0)
+    spec = default_spec(nx=n, ny=n, nz=n, dx=1.0 / n, dy=1.0 / n, dz=1.0 / n,
+                        gamma=5.0 / 3.0, c_light=1e4 * a0, a_rad=1.0, r_gas=1.0,
+                        exchange="full", beta_tau=beta_tau, precision=precision,
+                        theta_E=1.0, theta_F=0.51, bc="periodic")
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=10.0, kF=10.0)
+    rng = np.random.default_rng(seed)
+    shape = st["rho"].shape
+    drho = random_phase_field(shape, 1, 8, 1e-4, rng)
+    dEr = random_phase_field(shape, 1, 8, 1e-4, rng)
+    st["rho"] += drho
+    st["Er"] += dEr
+    return dict(name=f"c2_rhd_linear_box_{n}cubed", spec=spec, state=st, chat=20.0 * a0,
+                dt=None, nsub=None, steps=10)
+
+
+def c3_point_source(n=256, precision="mixed"):
+    """3D concentrated source: n^3 on [0,1)^3 with outflow faces, static gas,
+    rho = 1 + 1e3 exp(-r^2/(2 sigma^2)) with sigma = 8 cells about the centre,
+    emissivity j = 1 in the central 4^3 cells, kappa_P = 0 (no exchange),
+    kappa_F = 1.2766 (core column ~ 50), c = chat = 1, E_r = 1e-10, F = 0,
+    theta_F = 1, 200 radiation subcycles of CFL 0.4."""
+    h = 1.0 / n
+    spec = default_spec(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, c_light=1.0,
+                        exchange="none", rad_only=True, theta_F=1.0, bc="outflow",
+                        precision=precision)
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1e-10, kP=0.0, kF=1.2766)
+    X, Y, Z = cell_centres(spec)
+    sig = 8.0 * h
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2
+    st["rho"][:] = 1.0 + 1e3 * np.exp(-r2 / (2 * sig ** 2))
+    st["mx"][:] = 0.0
+    jj = np.zeros_like(st["rho"])
+    c0 = n // 2 - 2
+    jj[c0:c0 + 4, c0:c0 + 4, c0:c0 + 4] = 1.0
+    st["j"] = jj
+    return dict(name=f"c3_point_source_{n}cubed", spec=spec, state=st, chat=1.0,
+                dt=0.4 * h, nsub=1, steps=200)
+
+
+def c4_dusty_shell(n=256, seed=BASE_SEED + 4, precision="mixed"):
+    """3D dusty shell: n^3 on [-1/2,1/2)^3 with outflow faces, isothermal gas
+    (c_s = 1), radiative equilibrium (no exchange). Gaussian shell of radius 0.3
+    and FWHM 0.05 with seeded lognormal density (sigma_ln rho = 1) so that the shell
+    column gives tau ~ 20 at kappa = 1; central Gaussian source j of width 2 cells
+    and luminosity set so that L kappa / (4 pi 0.3^2 c) = 20; c = 1e4; chat is 20x
+    the initial signal speed and stays fixed."""
+    h = 1.0 / n
+    spec = default_spec(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, c_light=1e4, iso_cs=1.0,
+                        isothermal=True, exchange="none", theta_F=1.0, bc="outflow",
+                        precision=precision)
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1e-10, kP=1.0, kF=1.0)
+    X, Y, Z = cell_centres(spec, origin=(-0.5, -0.5, -0.5))
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    sig_sh = 0.05 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    smooth = 1.0 + 375.8 * np.exp(-((r - 0.3) ** 2) / (2 * sig_sh ** 2))
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(smooth.shape)
+    lognorm = np.exp(1.0 * g - 0.5)
+    rho = np.where(smooth > 2.0, smooth * lognorm, smooth)
+    st["rho"][:] = rho
+    st["E"][:] = 0.0
+    sig_s = 2.0 * h
+    L = 20.0 * 4.0 * math.pi * 0.3 ** 2 * spec["c_light"] / 1.0
+    st["j"] = L * np.exp(-(r ** 2) / (2 * sig_s ** 2)) / ((2 * math.pi) ** 1.5 * sig_s ** 3)
+    return dict(name=f"c4_dusty_shell_{n}cubed", spec=spec, state=st, chat=None,
+                dt=None, nsub=None, steps=100, chat_over_vmax=20.0)
+
+
+def c5_requests(count=512, seed=BASE_SEED + 5, sizes=tuple(range(32, 193, 16)),
+                load=1.2):
+    """Served batch: a Poisson stream of independent periodic linear-perturbation
+    boxes (as in the 3D box above) with nx, ny, nz iid uniform over 32..192 step 16,
+    kappa_P = kappa_F log-uniform in [1, 1e3], chat/a0 uniform in [5, 50] and 20 gas
+    steps each. Returns per-request recipes; arrival times are in units of the
+    caller's measured single-stream service time times 1/load."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for r in range(count):
+        nx, ny, nz = (int(rng.choice(sizes)) for _ in range(3))
+        kappa = float(10.0 ** rng.uniform(0.0, 3.0))
+        chat_over_a0 = float(rng.uniform(5.0, 50.0))
+        t += float(rng.exponential(1.0 / load))
+        reqs.append(dict(id=r, nx=nx, ny=ny, nz=nz, kappa=kappa,
+                         chat_over_a0=chat_over_a0, steps=20, arrival=t,
+                         seed=int(rng.integers(0, 2 ** 31 - 1))))
+    return reqs
+
+
+def c5_problem(req, precision="mixed"):
+    """The initial state of one served request (see ``c5_requests``)."""
+    a0 = math.sqrt(5.0 / 3.0)
+    nx, ny, nz = req["nx"], req["ny"], req["nz"]
+    spec = default_spec(nx=nx, ny=ny, nz=nz, dx=1.0 / nx, dy=1.0 / ny, dz=1.0 / nz,
+                        gamma=5.0 / 3.0, c_light=1e4 * a0, exchange="full",
+                        precision=precision, bc="periodic")
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=req["kappa"], kF=req["kappa"])
+    rng = np.random.default_rng(req["seed"])
+    shape = st["rho"].shape
+    st["rho"] += random_phase_field(shape, 1, 8, 1e-4, rng)
+    st["Er"] += random_phase_field(shape, 1, 8, 1e-4, rng)
+    return dict(name=f"c5_request_{req['id']}", spec=spec, state=st,
+                chat=req["chat_over_a0"] * a0, dt=None, nsub=None, steps=req["steps"])
+
+
+# --------------------------------------------------------------------------
+# small problems for the checks
+# --------------------------------------------------------------------------
+
+def smooth_random_state(spec, seed, amp=0.1, Er0=1.0, f_amp=0.3, kappa=(1.0, 1.0),
+                        v_amp=0.0, with_j=False):
+    """A smooth, positive, sub-luminal random state for parity checks: each field is
+    a background plus a few random-phase low modes."""
+    rng = np.random.default_rng(seed)
+    shape = (spec["nz"], spec["ny"], spec["nx"])
+    kmax = max(2, min(shape) // 4) if min(shape) > 1 else 2
+
+    def pert(a):
+        if max(shape) == 1:
+            return np.zeros(shape)
+        return random_phase_field(shape, 1, kmax, a, rng)
+
+    st = {}
+    st["rho"] = 1.0 + pert(amp)
+    v = [v_amp * pert(1.0) for _ in range(3)]
+    P = 1.0 + pert(amp)
+    st["mx"], st["my"], st["mz"] = (st["rho"] * vv for vv in v)
+    ke = 0.5 * st["rho"] * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    st["E"] = (P / (spec["gamma"] - 1.0) if not spec["isothermal"] else 0.0) + ke
+    st["Er"] = Er0 * (1.0 + pert(amp))
+    c = spec["c_light"]
+    for q in ("Fx", "Fy", "Fz"):
+        st[q] = f_amp * c * st["Er"] * pert(1.0) / math.sqrt(3.0)
+    st["kP"] = kappa[0] * (1.0 + pert(0.5 * amp))
+    st["kF"] = kappa[1] * (1.0 + pert(0.5 * amp))
+    if with_j:
+        st["j"] = np.abs(pert(1.0))
+    for k in st:
+        st[k] = np.ascontiguousarray(st[k], dtype=np.float64)
+    return st
+
+
+def radiation_wave(dim, N, eps=1e-6, tau_lambda=0.1, theta_F=0.5):
+    """Free-streaming damped radiation plane wave (streaming limit, f = 1) in a
+    purely absorbing medium: 1D along x on [0, lambda); 2D on 2L x L with the wave
+    vector at atan(2) in the xy-plane; 3D on 2L x L x L at atan(2) in-plane and
+    atan(2/sqrt5) out of plane. lambda = 1, c = chat = 1, rho = 1,
+    kappa = tau_lambda. Background E = 1 with F = c E n, perturbation eps (1, c n)."""
+    lam = 1.0
+    if dim == 1:
+        alpha, beta, L = 0.0, 0.0, lam
+        n3 = (N, 1, 1)
+        ext = (L, 1.0, 1.0)
+    elif dim == 2:
+        alpha, beta, L = 0.0, math.atan(2.0), math.sqrt(5.0) / 2.0 * lam
+        n3 = (2 * N, N, 1)
+        ext = (2 * L, L, 1.0)
+    else:
+        alpha, beta, L = math.atan(2.0 / math.sqrt(5.0)), math.atan(2.0), 1.5 * lam
+        n3 = (2 * N, N, N)
+        ext = (2 * L, L, L)
+    spec = default_spec(nx=n3[0], ny=n3[1], nz=n3[2], dx=ext[0] / n3[0],
+                        dy=ext[1] / n3[1], dz=ext[2] / n3[2], c_light=1.0,
+                        exchange="absorb_only", rad_only=True, theta_F=theta_F,
+                        bc="periodic")
+    nhat = np.array([math.cos(alpha) * math.cos(beta), math.cos(alpha) * math.sin(beta),
+                     math.sin(alpha)])
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=tau_lambda / lam,
+                       kF=tau_lambda / lam)
+    X, Y, Z = cell_centres(spec)
+    xp = X * nhat[0] + Y * nhat[1] + Z * nhat[2]
+    E = 1.0 + eps * np.sin(2 * math.pi * xp / lam)
+    st["Er"] = E
+    st["Fx"] = E * nhat[0]
+    st["Fy"] = E * nhat[1]
+    st["Fz"] = E * nhat[2]
+    widths = [spec["dx"], spec["dy"], spec["dz"]][:dim]
+    return dict(name=f"radiation_wave_{dim}d_{N}", spec=spec, state=st, chat=1.0,
+                nhat=nhat, lam=lam, eps=eps, tau_lambda=tau_lambda,
+                t_end=lam / 1.0, dt=0.4 * min(widths))
+
+
+def sod_tube(N=200, gamma=1.4):
+    """Sod shock tube on [0,1) with outflow ends, radiation decoupled (kappa = 0,
+    no exchange, negligible E_r): left rho = 1, P = 1; right rho = 0.125, P = 0.1."""
+    spec = default_spec(nx=N, dx=1.0 / N, gamma=gamma, c_light=1.0, exchange="none",
+                        bc="outflow", theta_F=1.0)
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1e-20, kP=0.0, kF=0.0)
+    X, _, _ = cell_centres(spec)
+    left = X < 0.5
+    st["rho"] = np.where(left, 1.0, 0.125)
+    P = np.where(left, 1.0, 0.1)
+    st["E"] = P / (gamma - 1.0)
+    return dict(name=f"sod_{N}", spec=spec, state=st, chat=1.0, t_end=0.2)
