@@ -1,0 +1,212 @@
+/*
+ * rhd.h -- C interface of the MI355X (gfx950) library for the gray two-moment (M1)
+ * radiation-hydrodynamics method of Skinner & Ostriker (2013), "A two-moment
+ * radiation hydrodynamics module in Athena using a time-explicit Godunov method".
+ *
+ * One call of rhd_step advances one operator-split gas step of the method (Sec. 3.1,
+ * algorithm steps 2-6):
+ *   1. implicit gas-radiation energy exchange over dt_gas (Sec. 3.4,
+ *      Eqs. source:energyexchange to source:polynomial), per cell, in FP64;
+ *   2. gas Van Leer step with the explicit gas sources (Eq. algorithm:gastransport,
+ *      Eq. algorithm:source:explicit:gas);
+ *   3. nsub radiation Van Leer subcycles of dt_gas/nsub with the gas frozen
+ *      (Eq. algorithm:radtransport): M1 closure (Eqs. m1:m1tns, m1:chi), HLL fluxes
+ *      (Eq. hyperbolic:hllflux2) bounded by the M1 eigenvalues
+ *      (Eq. hyperbolic:evals13), unsplit conservative update, theta-scheme flux
+ *      absorption (Eq. source:stiff:radmomentum:soln) and explicit sources;
+ *   4. second-order correction of the gas sources with the radiation at t^{n+1}
+ *      (Sec. 3.4, last displayed equation);
+ *   5. an FP64 ledger of E + (c/chat) E_r, m + F/(c chat) and rho (Sec. 2.1) and a
+ *      non-finite check of the state.
+ *
+ * Conventions for every function:
+ *  - Status codes: RHD_OK (0) or a negative RHD_E* value; rhd_last_error() then
+ *    holds a message. A failed call leaves the state as it was unless stated.
+ *  - Host arrays belong to the caller; the library copies them in and out in FP64,
+ *    structure-of-arrays, cell (i, j, k) at flat index i + nx*(j + ny*k). Vector
+ *    fields (momentum, flux) are three consecutive blocks of nx*ny*nz values (x, y,
+ *    z components). Device memory belongs to the handle.
+ *  - Work is enqueued on the handle's HIP stream and returns before the GPU is done
+ *    unless the function says it synchronises.
+ *  - A handle is not thread-safe: use one handle per host thread and stream.
+ */
+#ifndef RHD_H
+#define RHD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RHD_OK            0
+#define RHD_EINVAL       -1   /* bad argument: sizes, dt <= 0, nsub < 0, chat <= 0, theta */
+#define RHD_ECFL         -2   /* chat * dt_gas / nsub > K0 * min(dx, dy, dz)               */
+#define RHD_ENONFINITE   -3   /* a non-finite value appeared in the state                   */
+#define RHD_ENOMEM       -4   /* device allocation failed                                   */
+#define RHD_EDEVICE      -5   /* a HIP call failed; rhd_last_error() has the HIP message    */
+#define RHD_ESTATE       -6   /* call out of order (e.g. rhd_step before rhd_set_state)     */
+
+/* boundary kinds for rhd_params.bc[6] = {x-, x+, y-, y+, z-, z+} */
+#define RHD_BC_PERIODIC   0
+#define RHD_BC_OUTFLOW    1   /* zero-gradient copy of the edge cell                        */
+#define RHD_BC_REFLECT    2   /* mirror image; the normal momentum and flux change sign     */
+
+/* rhd_params.flags */
+#define RHD_ISOTHERMAL          (1u << 0)  /* P = rho iso_cs^2, no gas energy equation     */
+#define RHD_EXCHANGE_MASK       (3u << 1)
+#define RHD_EXCHANGE_FULL       (0u << 1)  /* implicit exchange on dt_gas (Sec. 3.4)       */
+#define RHD_EXCHANGE_ABSORB_ONLY (1u << 1) /* absorption only, on each radiation stage,
+                                              Eq. source:stiff:radenergy:soln              */
+#define RHD_EXCHANGE_NONE       (2u << 1)  /* radiative equilibrium: no exchange (Sec. 3.4) */
+#define RHD_BETA_TAU            (1u << 3)  /* keep the O(beta tau) velocity terms
+                                              (Eq. m1:simplifiedsource and S_e)            */
+#define RHD_RAD_ONLY            (1u << 4)  /* gas frozen: no gas transport, no correction  */
+#define RHD_PRECISION_MIXED     (1u << 5)  /* FP32 storage and stencils, FP64 exchange and
+                                              ledger; without it everything is FP64        */
+
+typedef struct {
+  int nx, ny, nz;               /* interior cells; a dimension with n = 1 is inactive      */
+  double dx, dy, dz;            /* uniform cell widths                                      */
+  double gamma;                 /* ratio of specific heats (ignored when isothermal)        */
+  double c_light;               /* c: ratio of photon energy to momentum, used in sources   */
+  double a_rad;                 /* radiation constant a_R                                   */
+  double r_gas;                 /* k_B / mu, so that P = rho r_gas T (Eq. momenteqns:perfectgas) */
+  double iso_cs;                /* isothermal sound speed (RHD_ISOTHERMAL only)             */
+  double cfl;                   /* Courant number K0 (Eq. algorithm:gastimestep), 0 < K0 <= 1 */
+  double theta_E;               /* theta of the exchange update, in [0.5, 1] (Eq. source:energyupdate) */
+  double theta_F;               /* theta of the flux absorption, in [0.5, 1]
+                                   (Eq. source:stiff:radmomentum:soln)                      */
+  double newton_rtol;           /* relative tolerance epsilon of the root solve, (0, 1)     */
+  int newton_maxit;             /* Newton iterations before bisection takes over, >= 0      */
+  double rho_floor, p_floor, er_floor;  /* floors for rho, P and E_r, >= 0                  */
+  int bc[6];                    /* RHD_BC_* per face x-, x+, y-, y+, z-, z+; periodic faces
+                                   come in pairs; reflecting faces need n >= 3             */
+  unsigned flags;               /* RHD_* flags above                                        */
+} rhd_params;
+
+typedef struct {
+  double ledger[5];             /* after the last step or rhd_ledger: sum(E + (c/chat) E_r) dV,
+                                   sum(m_x,y,z + F_x,y,z / (c chat)) dV, sum(rho) dV (FP64)  */
+  double vmax;                  /* v_max of the last rhd_suggest_dt                         */
+  long long exch_theta1;        /* cells whose exchange was redone with theta = 1           */
+  long long exch_bisect;        /* cells whose exchange root needed bisection               */
+  long long newton_iters;       /* total Newton iterations                                  */
+  long long newton_max;         /* largest iteration count in one cell                      */
+  long long rad_fclamp;         /* interior cells whose |F| was scaled back to c E_r        */
+  long long rad_efloor;         /* interior cells raised to er_floor                        */
+  long long gas_rhofloor;       /* interior cells raised to rho_floor                       */
+  long long gas_pfloor;         /* interior cells raised to p_floor                         */
+  long long nonfinite;          /* non-finite values seen by the last ledger pass           */
+  long long first_nonfinite_cell; /* lowest flat cell index holding one, or -1              */
+  long long steps;              /* gas steps taken                                          */
+  long long subcycles;          /* radiation subcycles taken                                */
+} rhd_diag;
+
+/* Per-kernel GPU time measured with HIP events on the handle's stream (rhd_set_timing). */
+#define RHD_TIMING_MAX 12
+typedef struct {
+  int nkernels;                          /* entries used                                   */
+  char name[RHD_TIMING_MAX][24];         /* kernel names: exchange, gas_predict, ...       */
+  long long calls[RHD_TIMING_MAX];       /* launches timed                                 */
+  double total_ms[RHD_TIMING_MAX];       /* summed event-to-event duration                 */
+  long long cells[RHD_TIMING_MAX];       /* cells processed per launch (padded regions for
+                                            the predictors)                               */
+} rhd_timing;
+
+typedef struct rhd rhd_t;
+
+/* Default parameters for an nx x ny x nz grid: unit box, gamma = 5/3, c = a_R = r_gas = 1,
+   K0 = 0.4, theta_E = 1, theta_F = 0.51, epsilon = 1e-10, 50 Newton iterations, periodic
+   faces, full exchange, FP64. Never fails. */
+void rhd_default_params(rhd_params* p, int nx, int ny, int nz);
+
+/* Create a handle: validates p (RHD_EINVAL), selects the current HIP device and
+   allocates every device buffer the steps need (RHD_ENOMEM), so that rhd_step never
+   allocates. hip_stream is a hipStream_t to enqueue on, or NULL for a stream the
+   handle creates and owns. On failure *out is NULL. */
+int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out);
+
+/* Copy a state in (host FP64 arrays, layout above): rho (N), mom (3N), E (N, gas total
+   energy; ignored when isothermal), Er (N), Fr (3N). kappaP and kappaF are the
+   Planck-mean and flux-mean specific opacities: N values each, or one value each when
+   kappa_scalar is 1. kappa_P multiplies the exchange term (a_R T^4 - E_r) and kappa_F
+   every F and v term (Sec. 2.1, Eq. mixedframe:kappas). In mixed precision the values
+   are rounded to FP32. Synchronises. */
+int rhd_set_state(rhd_t* h, const double* rho, const double* mom, const double* E,
+                  const double* Er, const double* Fr, const double* kappaP,
+                  const double* kappaF, int kappa_scalar);
+
+/* Same as rhd_set_state with every pointer in device memory of the handle's device
+   (e.g. a torch tensor's data pointer). Enqueued on the stream, no synchronisation;
+   the caller keeps the arrays alive until the stream has passed this call. */
+int rhd_set_state_device(rhd_t* h, const double* rho, const double* mom, const double* E,
+                         const double* Er, const double* Fr, const double* kappaP,
+                         const double* kappaF, int kappa_scalar);
+
+/* Emissivity j per cell (N host values), or NULL to remove it. It adds (chat/c) j to
+   dE_r/dt, so that div F = j in a steady state (Sec. 4.3.6, Eq. radshell:sourceprofile).
+   Synchronises. */
+int rhd_set_emission(rhd_t* h, const double* j);
+
+/* Advance one gas step of dt_gas with nsub radiation subcycles of dt_gas/nsub each
+   (Sec. 3.1 steps 2-6, Eq. algorithm:radtimestep). chat is the reduced speed of light
+   of this step (Sec. 3.2). nsub = 0 advances the exchange and the gas only.
+   RHD_EINVAL for dt_gas <= 0, chat <= 0 or nsub < 0; RHD_ECFL when
+   chat * dt_gas / nsub > K0 * min(dx, dy, dz) (relative slack 1e-12); RHD_ESTATE
+   before rhd_set_state. Asynchronous: errors found on the GPU (non-finite values)
+   are reported by rhd_sync and rhd_get_diagnostics. */
+int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub);
+
+/* Radiation-modified CFL step of the current state (Eqs. algorithm:ceff and
+   algorithm:gastimestep): v_max = max(|v| + c_eff), dt_gas = K0 min(dx) / v_max,
+   nsub = ceil(chat / v_max) (at least 1). Synchronises. */
+int rhd_suggest_dt(rhd_t* h, double chat, double* dt_gas, int* nsub);
+
+/* Recompute the FP64 ledger of the current state with the given chat (the step does
+   this itself with its own chat). Asynchronous; read it with rhd_get_diagnostics. */
+int rhd_ledger(rhd_t* h, double chat);
+
+/* Copy the state out into host FP64 arrays laid out as for rhd_set_state. Any pointer
+   may be NULL to skip that field. Synchronises. */
+int rhd_get_state(rhd_t* h, double* rho, double* mom, double* E, double* Er, double* Fr);
+
+/* Same as rhd_get_state into device FP64 arrays. Enqueued, no synchronisation. */
+int rhd_get_state_device(rhd_t* h, double* rho, double* mom, double* E, double* Er,
+                         double* Fr);
+
+/* Counters accumulated since rhd_create or rhd_reset_diagnostics, the last ledger and
+   v_max. Synchronises. */
+int rhd_get_diagnostics(rhd_t* h, rhd_diag* out);
+
+/* Zero the counters. Asynchronous. */
+int rhd_reset_diagnostics(rhd_t* h);
+
+/* Wait for the handle's stream. Returns RHD_ENONFINITE if the last ledger pass found
+   a non-finite value, RHD_EDEVICE on a HIP error. */
+int rhd_sync(rhd_t* h);
+
+/* Start (enable = 1) or stop (0) timing every kernel launch of the handle with a pair of
+   HIP events recorded on its stream; starting also clears the totals. Events come from a
+   pool created on first use; a full pool is drained with one stream synchronisation. */
+int rhd_set_timing(rhd_t* h, int enable);
+
+/* Totals since timing was started. Synchronises. */
+int rhd_get_timing(rhd_t* h, rhd_timing* out);
+
+/* Device bytes the handle holds (state, opacities, emission and scratch). */
+long long rhd_device_bytes(const rhd_t* h);
+
+/* Device bytes a handle with these parameters would hold, without creating it. */
+long long rhd_footprint_bytes(const rhd_params* p);
+
+/* Free every device buffer and the owned stream. NULL is ignored. */
+void rhd_destroy(rhd_t* h);
+
+/* Message of the last failure on this handle (or of the last failed rhd_create when h
+   is NULL). Never NULL. */
+const char* rhd_last_error(const rhd_t* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RHD_H */

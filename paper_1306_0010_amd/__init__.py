@@ -1,0 +1,359 @@
+"""Python binding of the gfx950 library for the gray two-moment (M1)
+radiation-hydrodynamics step of Skinner & Ostriker (2013).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``librhd.so`` behind the C interface declared in ``include/rhd.h``. The functions
+here carry the same names as that interface. If the library has not been built,
+every call raises ``RhdError`` -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librhd.so")
+
+RHD_OK = 0
+RHD_EINVAL = -1
+RHD_ECFL = -2
+RHD_ENONFINITE = -3
+RHD_ENOMEM = -4
+RHD_EDEVICE = -5
+RHD_ESTATE = -6
+ERROR_NAMES = {RHD_EINVAL: "RHD_EINVAL", RHD_ECFL: "RHD_ECFL", RHD_ENONFINITE: "RHD_ENONFINITE",
+               RHD_ENOMEM: "RHD_ENOMEM", RHD_EDEVICE: "RHD_EDEVICE", RHD_ESTATE: "RHD_ESTATE"}
+
+RHD_BC_PERIODIC, RHD_BC_OUTFLOW, RHD_BC_REFLECT = 0, 1, 2
+RHD_ISOTHERMAL = 1 << 0
+RHD_EXCHANGE_MASK = 3 << 1
+RHD_EXCHANGE_FULL = 0 << 1
+RHD_EXCHANGE_ABSORB_ONLY = 1 << 1
+RHD_EXCHANGE_NONE = 2 << 1
+RHD_BETA_TAU = 1 << 3
+RHD_RAD_ONLY = 1 << 4
+RHD_PRECISION_MIXED = 1 << 5
+
+EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_device",
+            "rhd_set_emission", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
+            "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics", "rhd_sync",
+            "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
+            "rhd_set_timing", "rhd_get_timing")
+
+
+class RhdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class rhd_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("c_light", ctypes.c_double), ("a_rad", ctypes.c_double), ("r_gas", ctypes.c_double),
+        ("iso_cs", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("theta_E", ctypes.c_double), ("theta_F", ctypes.c_double),
+        ("newton_rtol", ctypes.c_double),
+        ("newton_maxit", ctypes.c_int),
+        ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+        ("er_floor", ctypes.c_double),
+        ("bc", ctypes.c_int * 6),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class rhd_diag(ctypes.Structure):
+    _fields_ = [("ledger", ctypes.c_double * 5), ("vmax", ctypes.c_double)] + [
+        (name, ctypes.c_longlong) for name in
+        ("exch_theta1", "exch_bisect", "newton_iters", "newton_max", "rad_fclamp", "rad_efloor",
+         "gas_rhofloor", "gas_pfloor", "nonfinite", "first_nonfinite_cell", "steps", "subcycles")]
+
+    def as_dict(self):
+        out = {"ledger": list(self.ledger), "vmax": self.vmax}
+        for name, _ in self._fields_[2:]:
+            out[name] = int(getattr(self, name))
+        return out
+
+
+class rhd_timing(ctypes.Structure):
+    _fields_ = [("nkernels", ctypes.c_int), ("name", (ctypes.c_char * 24) * 12),
+                ("calls", ctypes.c_longlong * 12), ("total_ms", ctypes.c_double * 12),
+                ("cells", ctypes.c_longlong * 12)]
+
+    def as_dict(self):
+        return {self.name[k].value.decode(): {"calls": int(self.calls[k]),
+                                              "total_ms": float(self.total_ms[k]),
+                                              "cells": int(self.cells[k])}
+                for k in range(self.nkernels)}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises RhdError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RhdError(RHD_EDEVICE, f"{LIB_PATH} is missing: build it with "
+                                    "`python paper_1306_0010_amd/build.py` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    P = ctypes.POINTER(rhd_params)
+    L.rhd_default_params.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rhd_default_params.restype = None
+    L.rhd_create.argtypes = [P, vp, ctypes.POINTER(vp)]
+    L.rhd_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+    L.rhd_set_state_device.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+    L.rhd_set_emission.argtypes = [vp, dp]
+    L.rhd_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    L.rhd_suggest_dt.argtypes = [vp, ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int)]
+    L.rhd_ledger.argtypes = [vp, ctypes.c_double]
+    L.rhd_get_state.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.rhd_get_state_device.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.rhd_get_diagnostics.argtypes = [vp, ctypes.POINTER(rhd_diag)]
+    L.rhd_reset_diagnostics.argtypes = [vp]
+    L.rhd_sync.argtypes = [vp]
+    L.rhd_device_bytes.argtypes = [vp]
+    L.rhd_device_bytes.restype = ctypes.c_longlong
+    L.rhd_footprint_bytes.argtypes = [P]
+    L.rhd_footprint_bytes.restype = ctypes.c_longlong
+    L.rhd_destroy.argtypes = [vp]
+    L.rhd_destroy.restype = None
+    L.rhd_set_timing.argtypes = [vp, ctypes.c_int]
+    L.rhd_get_timing.argtypes = [vp, ctypes.POINTER(rhd_timing)]
+    L.rhd_last_error.argtypes = [vp]
+    L.rhd_last_error.restype = ctypes.c_char_p
+    for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
+                 "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
+                 "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
+                 "rhd_sync", "rhd_set_timing", "rhd_get_timing"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, handle=None):
+    if rc != RHD_OK:
+        msg = lib().rhd_last_error(handle).decode(errors="replace")
+        raise RhdError(rc, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------------------
+# the C functions, same names
+# ---------------------------------------------------------------------------
+
+def rhd_default_params(nx, ny, nz):
+    p = rhd_params()
+    lib().rhd_default_params(ctypes.byref(p), int(nx), int(ny), int(nz))
+    return p
+
+
+def rhd_create(params, stream=None):
+    """Returns an opaque handle (int). ``stream`` is a hipStream_t as an int (for
+    example ``torch.cuda.current_stream().cuda_stream``) or None for an owned stream."""
+    h = ctypes.c_void_p()
+    _check(lib().rhd_create(ctypes.byref(params), ctypes.c_void_p(stream) if stream else None,
+                            ctypes.byref(h)))
+    return h.value
+
+
+def rhd_set_state(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in (rho, mom, E, Er, Fr, kappaP, kappaF)]
+    ptrs = [_dptr(a) if a is not None else None for a in arrs]
+    _check(lib().rhd_set_state(h, *ptrs, int(kappa_scalar)), h)
+
+
+def rhd_set_state_device(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar):
+    """Device pointers (ints), e.g. ``tensor.data_ptr()`` of float64 CUDA tensors."""
+    _check(lib().rhd_set_state_device(h, rho, mom, E, Er, Fr, kappaP, kappaF, int(kappa_scalar)), h)
+
+
+def rhd_set_emission(h, j):
+    if j is None:
+        _check(lib().rhd_set_emission(h, None), h)
+        return
+    a = np.ascontiguousarray(j, dtype=np.float64)
+    _check(lib().rhd_set_emission(h, _dptr(a)), h)
+
+
+def rhd_step(h, dt_gas, chat, nsub):
+    _check(lib().rhd_step(h, float(dt_gas), float(chat), int(nsub)), h)
+
+
+def rhd_suggest_dt(h, chat):
+    dt = ctypes.c_double()
+    ns = ctypes.c_int()
+    _check(lib().rhd_suggest_dt(h, float(chat), ctypes.byref(dt), ctypes.byref(ns)), h)
+    return dt.value, ns.value
+
+
+def rhd_ledger(h, chat):
+    _check(lib().rhd_ledger(h, float(chat)), h)
+
+
+def rhd_get_state(h, N):
+    out = {"rho": np.empty(N), "mom": np.empty(3 * N), "E": np.empty(N), "Er": np.empty(N),
+           "Fr": np.empty(3 * N)}
+    _check(lib().rhd_get_state(h, _dptr(out["rho"]), _dptr(out["mom"]), _dptr(out["E"]),
+                               _dptr(out["Er"]), _dptr(out["Fr"])), h)
+    return out
+
+
+def rhd_get_state_device(h, rho, mom, E, Er, Fr):
+    _check(lib().rhd_get_state_device(h, rho, mom, E, Er, Fr), h)
+
+
+def rhd_get_diagnostics(h):
+    d = rhd_diag()
+    _check(lib().rhd_get_diagnostics(h, ctypes.byref(d)), h)
+    return d.as_dict()
+
+
+def rhd_reset_diagnostics(h):
+    _check(lib().rhd_reset_diagnostics(h), h)
+
+
+def rhd_sync(h):
+    _check(lib().rhd_sync(h), h)
+
+
+def rhd_set_timing(h, enable):
+    _check(lib().rhd_set_timing(h, int(bool(enable))), h)
+
+
+def rhd_get_timing(h):
+    t = rhd_timing()
+    _check(lib().rhd_get_timing(h, ctypes.byref(t)), h)
+    return t.as_dict()
+
+
+def rhd_device_bytes(h):
+    return int(lib().rhd_device_bytes(h))
+
+
+def rhd_footprint_bytes(params):
+    return int(lib().rhd_footprint_bytes(ctypes.byref(params)))
+
+
+def rhd_destroy(h):
+    if h:
+        lib().rhd_destroy(h)
+
+
+def rhd_last_error(h=None):
+    return lib().rhd_last_error(h).decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# problem description -> parameters, and a handle wrapper
+# ---------------------------------------------------------------------------
+
+_BC = {"periodic": RHD_BC_PERIODIC, "outflow": RHD_BC_OUTFLOW, "reflect": RHD_BC_REFLECT}
+_EXCH = {"full": RHD_EXCHANGE_FULL, "absorb_only": RHD_EXCHANGE_ABSORB_ONLY,
+         "none": RHD_EXCHANGE_NONE}
+
+
+def params_from_spec(spec):
+    """rhd_params from a problem description dict (grid, constants, switches)."""
+    p = rhd_default_params(spec["nx"], spec["ny"], spec["nz"])
+    for name in ("dx", "dy", "dz", "gamma", "c_light", "a_rad", "r_gas", "iso_cs", "cfl",
+                 "theta_E", "theta_F", "newton_rtol", "rho_floor", "p_floor", "er_floor"):
+        setattr(p, name, float(spec[name]))
+    p.newton_maxit = int(spec.get("newton_maxit", 50))
+    for q in range(6):
+        p.bc[q] = _BC[spec["bc"][q]]
+    flags = _EXCH[spec["exchange"]]
+    if spec["isothermal"]:
+        flags |= RHD_ISOTHERMAL
+    if spec["beta_tau"]:
+        flags |= RHD_BETA_TAU
+    if spec["rad_only"]:
+        flags |= RHD_RAD_ONLY
+    if spec["precision"] == "mixed":
+        flags |= RHD_PRECISION_MIXED
+    p.flags = flags
+    return p
+
+
+class Solver:
+    """One handle: state in, steps, state out. ``state`` dicts hold float64 arrays of
+    shape (nz, ny, nx) named rho, mx, my, mz, E, Er, Fx, Fy, Fz, kP, kF and optionally j."""
+
+    def __init__(self, spec, stream=None):
+        self.spec = dict(spec)
+        self.shape = (spec["nz"], spec["ny"], spec["nx"])
+        self.N = int(np.prod(self.shape))
+        self.params = params_from_spec(spec)
+        self.h = rhd_create(self.params, stream)
+
+    def close(self):
+        if self.h:
+            rhd_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, st):
+        flat = lambda k: np.ascontiguousarray(np.broadcast_to(st[k], self.shape), dtype=np.float64).ravel()
+        mom = np.concatenate([flat("mx"), flat("my"), flat("mz")])
+        Fr = np.concatenate([flat("Fx"), flat("Fy"), flat("Fz")])
+        kP = np.asarray(st["kP"], dtype=np.float64)
+        kF = np.asarray(st["kF"], dtype=np.float64)
+        scalar = kP.size == 1 or (np.all(kP == kP.flat[0]) and np.all(kF == kF.flat[0]))
+        if scalar:
+            kPa, kFa = np.array([kP.flat[0]]), np.array([kF.flat[0]])
+        else:
+            kPa, kFa = flat("kP"), flat("kF")
+        rhd_set_state(self.h, flat("rho"), mom, flat("E"), flat("Er"), Fr, kPa, kFa, scalar)
+        rhd_set_emission(self.h, flat("j") if st.get("j") is not None else None)
+
+    def step(self, dt_gas, chat, nsub):
+        rhd_step(self.h, dt_gas, chat, nsub)
+
+    def suggest_dt(self, chat):
+        return rhd_suggest_dt(self.h, chat)
+
+    def get_state(self):
+        raw = rhd_get_state(self.h, self.N)
+        N, sh = self.N, self.shape
+        return {"rho": raw["rho"].reshape(sh), "mx": raw["mom"][:N].reshape(sh),
+                "my": raw["mom"][N:2 * N].reshape(sh), "mz": raw["mom"][2 * N:].reshape(sh),
+                "E": raw["E"].reshape(sh), "Er": raw["Er"].reshape(sh),
+                "Fx": raw["Fr"][:N].reshape(sh), "Fy": raw["Fr"][N:2 * N].reshape(sh),
+                "Fz": raw["Fr"][2 * N:].reshape(sh)}
+
+    def diagnostics(self):
+        return rhd_get_diagnostics(self.h)
+
+    def reset_diagnostics(self):
+        rhd_reset_diagnostics(self.h)
+
+    def ledger(self, chat):
+        rhd_ledger(self.h, chat)
+        return self.diagnostics()["ledger"]
+
+    def sync(self):
+        rhd_sync(self.h)

@@ -1,0 +1,861 @@
+// rhd.hip -- host runtime and C interface (include/rhd.h) of the gfx950 library for
+// the gray M1 radiation-hydrodynamics step of Skinner & Ostriker (2013), Sec. 3.1.
+//
+// A handle owns every device buffer it needs, allocated once in rhd_create; rhd_step
+// only enqueues kernels on the handle's stream:
+//   exchange (FP64) -> gas predictor -> gas corrector
+//   -> nsub x [radiation predictor -> radiation corrector]
+//   -> gas source correction -> FP64 ledger with non-finite check.
+#include "rhd_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/rhd.h"
+
+namespace {
+
+thread_local char g_create_error[512] = "no error";
+
+constexpr int LEDGER_BLOCKS = 1024;
+constexpr int VMAX_BLOCKS = 1024;
+
+struct Buffers {
+  void* gas[5] = {};   // rho, mx, my, mz, E
+  void* rad[4] = {};   // Er, Fx, Fy, Fz
+  void* kP = nullptr;  // per-cell opacities (null when scalar)
+  void* kF = nullptr;
+  void* j = nullptr;   // emissivity or null
+  void* gh[5] = {};    // padded gas half-step
+  void* rh[4] = {};    // padded radiation half-step
+  void* sn[4] = {};    // saved gas sources s_n
+  void* wh[4] = {};    // saved (rho, v) at the gas half step
+  double* staging = nullptr;         // N doubles for host transfers
+  double* ledger_partials = nullptr; // 5 x LEDGER_BLOCKS
+  double* ledger = nullptr;          // 5
+  void* vmax_partials = nullptr;     // VMAX_BLOCKS of T
+  double* vmax = nullptr;            // 1
+  unsigned long long* ctr = nullptr; // rhdk::CTR_COUNT
+};
+
+enum KernelClass {
+  KC_EXCHANGE = 0,
+  KC_GAS_PREDICT,
+  KC_GAS_CORRECT,
+  KC_RAD_PREDICT,
+  KC_RAD_CORRECT,
+  KC_GAS_SOURCE,
+  KC_LEDGER,
+  KC_VMAX,
+  KC_COUNT
+};
+const char* const kKernelNames[KC_COUNT] = {"exchange",    "gas_predict",        "gas_correct",
+                                            "rad_predict", "rad_correct",        "gas_source_correct",
+                                            "ledger",      "vmax"};
+
+// Event pairs around kernel launches, drained into per-kernel totals.
+struct Timer {
+  static constexpr int POOL = 2048;
+  bool on = false;
+  int used = 0;
+  hipEvent_t* start = nullptr;
+  hipEvent_t* stop = nullptr;
+  int cls[POOL] = {};
+  long long calls[KC_COUNT] = {};
+  double ms[KC_COUNT] = {};
+  long long cells[KC_COUNT] = {};
+};
+
+}  // namespace
+
+struct rhd {
+  rhd_params p;
+  bool mixed = false;
+  size_t esize = 8;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  rhdk::Geom G;
+  int N = 0;
+  int NP = 0;
+  double dxmin = 0.0;
+  Buffers b;
+  bool kappa_scalar = true;
+  double kP_s = 0.0, kF_s = 0.0;
+  bool have_state = false;
+  long long steps = 0, subcycles = 0;
+  double vmax_last = 0.0;
+  long long bytes = 0;
+  Timer timer;
+  char err[512] = "no error";
+};
+
+namespace {
+
+int fail(rhd_t* h, int code, const char* fmt, ...) {
+  char* dst = h ? h->err : g_create_error;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(h, call)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((h), RHD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+double min_width(const rhd_params* p) {
+  double w = p->dx;
+  if (p->ny > 1) w = std::min(w, p->dy);
+  if (p->nz > 1) w = std::min(w, p->dz);
+  return w;
+}
+
+int validate(const rhd_params* p) {
+  if (!p) return fail(nullptr, RHD_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(nullptr, RHD_EINVAL, "grid sizes must be >= 1 (got %d %d %d)", p->nx, p->ny, p->nz);
+  const int ns[3] = {p->nx, p->ny, p->nz};
+  long long padded = 1, cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    cells *= ns[d];
+    padded *= ns[d] > 1 ? ns[d] + 4 : 1;
+  }
+  if (padded >= (1ll << 31))
+    return fail(nullptr, RHD_EINVAL, "grid too large: %lld padded cells (limit 2^31)", padded);
+  const double ws[3] = {p->dx, p->dy, p->dz};
+  for (int d = 0; d < 3; ++d) {
+    if (ns[d] > 1 && !(ws[d] > 0.0)) return fail(nullptr, RHD_EINVAL, "cell width %d must be > 0", d);
+    if (ns[d] > 1) {
+      for (int s = 0; s < 2; ++s) {
+        const int kind = p->bc[2 * d + s];
+        if (kind < RHD_BC_PERIODIC || kind > RHD_BC_REFLECT)
+          return fail(nullptr, RHD_EINVAL, "unknown boundary kind %d on face %d", kind, 2 * d + s);
+        if (kind == RHD_BC_REFLECT && ns[d] < 3)
+          return fail(nullptr, RHD_EINVAL, "reflecting faces need at least 3 cells");
+      }
+      if ((p->bc[2 * d] == RHD_BC_PERIODIC) != (p->bc[2 * d + 1] == RHD_BC_PERIODIC))
+        return fail(nullptr, RHD_EINVAL, "periodic faces must come in pairs (dimension %d)", d);
+    }
+  }
+  if (!(p->c_light > 0.0) || !(p->a_rad >= 0.0) || !(p->r_gas > 0.0))
+    return fail(nullptr, RHD_EINVAL, "c_light and r_gas must be > 0, a_rad >= 0");
+  if (!(p->flags & RHD_ISOTHERMAL) && !(p->gamma > 1.0))
+    return fail(nullptr, RHD_EINVAL, "gamma must be > 1 for an ideal gas");
+  if ((p->flags & RHD_ISOTHERMAL) && !(p->iso_cs > 0.0))
+    return fail(nullptr, RHD_EINVAL, "iso_cs must be > 0 for an isothermal gas");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(nullptr, RHD_EINVAL, "cfl must be in (0, 1]");
+  if (!(p->theta_E >= 0.5 && p->theta_E <= 1.0) || !(p->theta_F >= 0.5 && p->theta_F <= 1.0))
+    return fail(nullptr, RHD_EINVAL, "theta_E and theta_F must be in [0.5, 1]");
+  if (!(p->newton_rtol > 0.0 && p->newton_rtol < 1.0) || p->newton_maxit < 0)
+    return fail(nullptr, RHD_EINVAL, "newton_rtol must be in (0, 1) and newton_maxit >= 0");
+  if (!(p->rho_floor >= 0.0) || !(p->p_floor >= 0.0) || !(p->er_floor >= 0.0))
+    return fail(nullptr, RHD_EINVAL, "floors must be >= 0");
+  if ((p->flags & RHD_EXCHANGE_MASK) == (3u << 1))
+    return fail(nullptr, RHD_EINVAL, "unknown exchange mode");
+  if (p->flags & ~((1u << 6) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  (void)cells;
+  return RHD_OK;
+}
+
+rhdk::Geom make_geom(const rhd_params* p) {
+  rhdk::Geom G;
+  const int ns[3] = {p->nx, p->ny, p->nz};
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = ns[d];
+    G.act[d] = ns[d] > 1;
+    G.g[d] = ns[d] > 1 ? 2 : 0;
+    G.ps[d] = ns[d] + 2 * G.g[d];
+  }
+  for (int f = 0; f < 6; ++f) G.bc[f] = p->bc[f];
+  return G;
+}
+
+long long footprint(const rhd_params* p, long long* N_out, long long* NP_out) {
+  const bool mixed = (p->flags & RHD_PRECISION_MIXED) != 0;
+  const long long es = mixed ? 4 : 8;
+  const int ns[3] = {p->nx, p->ny, p->nz};
+  long long N = 1, NP = 1;
+  for (int d = 0; d < 3; ++d) {
+    N *= ns[d];
+    NP *= ns[d] > 1 ? ns[d] + 4 : 1;
+  }
+  if (N_out) *N_out = N;
+  if (NP_out) *NP_out = NP;
+  const bool gas = !(p->flags & RHD_RAD_ONLY);
+  long long bytes = 0;
+  bytes += 9 * N * es;                  // state
+  bytes += 4 * NP * es;                 // radiation half step
+  if (gas) bytes += 5 * NP * es + 8 * N * es;  // gas half step, s_n, W_1/2
+  bytes += N * 8;                       // staging
+  bytes += 5 * LEDGER_BLOCKS * 8 + 5 * 8 + VMAX_BLOCKS * 8 + 8 + rhdk::CTR_COUNT * 8;
+  return bytes;
+}
+
+template <typename T>
+T* as(void* p) {
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+rhdk::RadPtrs<T> rad_ptrs(void* const* a) {
+  rhdk::RadPtrs<T> r;
+  r.E = as<T>(a[0]);
+  r.F[0] = as<T>(a[1]);
+  r.F[1] = as<T>(a[2]);
+  r.F[2] = as<T>(a[3]);
+  return r;
+}
+
+template <typename T>
+rhdk::GasPtrs<T> gas_ptrs(void* const* a) {
+  rhdk::GasPtrs<T> g;
+  g.rho = as<T>(a[0]);
+  g.m[0] = as<T>(a[1]);
+  g.m[1] = as<T>(a[2]);
+  g.m[2] = as<T>(a[3]);
+  g.E = as<T>(a[4]);
+  return g;
+}
+
+int blocks_for(long long n, int threads) { return int((n + threads - 1) / threads); }
+
+int timer_drain(rhd_t* h) {
+  Timer& t = h->timer;
+  if (t.used == 0) return RHD_OK;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < t.used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, t.start[i], t.stop[i]));
+    t.ms[t.cls[i]] += double(ms);
+  }
+  t.used = 0;
+  return RHD_OK;
+}
+
+// Record a start event for one launch of kernel class kc over `cells` cells; returns the
+// pool slot, or -1 when timing is off.
+int tbegin(rhd_t* h, int kc, long long cells) {
+  Timer& t = h->timer;
+  if (!t.on) return -1;
+  if (t.used == Timer::POOL && timer_drain(h) != RHD_OK) return -1;
+  const int i = t.used++;
+  t.cls[i] = kc;
+  t.calls[kc] += 1;
+  t.cells[kc] = cells;
+  if (hipEventRecord(t.start[i], h->stream) != hipSuccess) return -1;
+  return i;
+}
+
+void tend(rhd_t* h, int i) {
+  if (i >= 0) (void)hipEventRecord(h->timer.stop[i], h->stream);
+}
+
+// Launch shape for a (possibly padded) region of extents e[3]: x fastest.
+void region_launch(const int e[3], dim3& grid, dim3& block) {
+  if (e[1] == 1) {
+    block = dim3(256, 1, 1);
+  } else {
+    block = dim3(64, 4, 1);
+  }
+  grid = dim3((e[0] + block.x - 1) / block.x, (e[1] + block.y - 1) / block.y, e[2]);
+}
+
+template <typename T>
+rhdk::GasView<T> gas_view(rhd_t* h) {
+  rhdk::GasView<T> g;
+  g.rho = as<T>(h->b.gas[0]);
+  g.m[0] = as<T>(h->b.gas[1]);
+  g.m[1] = as<T>(h->b.gas[2]);
+  g.m[2] = as<T>(h->b.gas[3]);
+  g.kP = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
+  g.kF = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+  g.j = h->b.j ? as<T>(h->b.j) : nullptr;
+  g.kP_s = T(h->kP_s);
+  g.kF_s = T(h->kF_s);
+  return g;
+}
+
+template <typename T>
+int enqueue_ledger(rhd_t* h, double chat) {
+  const double c = h->p.c_light;
+  const double dV = h->p.dx * h->p.dy * h->p.dz;
+  const int ti = tbegin(h, KC_LEDGER, h->N);
+  hipLaunchKernelGGL(rhdk::k_ledger<T>, dim3(LEDGER_BLOCKS), dim3(rhdk::RED_THREADS), 0, h->stream,
+                     gas_ptrs<T>(h->b.gas), rad_ptrs<T>(h->b.rad), c / chat, 1.0 / (c * chat), h->N,
+                     h->b.ledger_partials, h->b.ctr);
+  hipLaunchKernelGGL(rhdk::k_ledger_final, dim3(1), dim3(rhdk::RED_THREADS), 0, h->stream,
+                     h->b.ledger_partials, LEDGER_BLOCKS, dV, h->b.ledger);
+  tend(h, ti);
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
+
+template <typename T>
+int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
+  const rhd_params& p = h->p;
+  const unsigned mode = p.flags & RHD_EXCHANGE_MASK;
+  const bool iso = (p.flags & RHD_ISOTHERMAL) != 0;
+  const bool rad_only = (p.flags & RHD_RAD_ONLY) != 0;
+  const bool beta = (p.flags & RHD_BETA_TAU) != 0;
+  const rhdk::Geom& G = h->G;
+  auto gas = gas_ptrs<T>(h->b.gas);
+  auto rad = rad_ptrs<T>(h->b.rad);
+  const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+  const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
+  const int threads = 256;
+
+  // 1. implicit energy exchange over dt_gas (FP64)
+  if (mode == RHD_EXCHANGE_FULL && !iso) {
+    rhdk::ExchConst X;
+    X.c = p.c_light;
+    X.chat = chat;
+    X.dt = dt;
+    X.gm1 = p.gamma - 1.0;
+    X.a_rad = p.a_rad;
+    X.r_gas = p.r_gas;
+    X.theta = p.theta_E;
+    X.rtol = p.newton_rtol;
+    X.maxit = p.newton_maxit;
+    const int ti = tbegin(h, KC_EXCHANGE, h->N);
+    hipLaunchKernelGGL(rhdk::k_exchange<T>, dim3(blocks_for(h->N, threads)), dim3(threads), 0,
+                       h->stream, gas, rad, kPp, h->kP_s, X, h->N, h->b.ctr);
+    tend(h, ti);
+  }
+
+  // 2. gas Van Leer step with S_e,gas at first order
+  rhdk::GasConst<T> GK;
+  GK.c = T(p.c_light);
+  GK.inv_c = T(1.0 / p.c_light);
+  GK.inv_w[0] = G.act[0] ? T(1.0 / p.dx) : T(0);
+  GK.inv_w[1] = G.act[1] ? T(1.0 / p.dy) : T(0);
+  GK.inv_w[2] = G.act[2] ? T(1.0 / p.dz) : T(0);
+  GK.gamma = T(p.gamma);
+  GK.gm1 = T(p.gamma - 1.0);
+  GK.cs2 = T(p.iso_cs * p.iso_cs);
+  GK.rho_floor = T(p.rho_floor);
+  GK.p_floor = T(p.p_floor);
+  GK.beta = beta;
+  GK.iso = iso;
+  if (!rad_only) {
+    dim3 grid, block;
+    region_launch(G.ps, grid, block);
+    auto gh = gas_ptrs<T>(h->b.gh);
+    int ti = tbegin(h, KC_GAS_PREDICT, h->NP);
+    hipLaunchKernelGGL(rhdk::k_gas_predict<T>, grid, block, 0, h->stream, gas, gh, rad, kFp,
+                       T(h->kF_s), G, GK, T(0.5 * dt));
+    tend(h, ti);
+    region_launch(G.n, grid, block);
+    ti = tbegin(h, KC_GAS_CORRECT, h->N);
+    hipLaunchKernelGGL(rhdk::k_gas_correct<T>, grid, block, 0, h->stream, gas, gh, rad, kFp,
+                       T(h->kF_s), G, GK, T(dt), as<T>(h->b.sn[0]), as<T>(h->b.sn[1]),
+                       as<T>(h->b.sn[2]), as<T>(h->b.sn[3]), as<T>(h->b.wh[0]), as<T>(h->b.wh[1]),
+                       as<T>(h->b.wh[2]), as<T>(h->b.wh[3]), h->b.ctr);
+    tend(h, ti);
+  }
+
+  // 3. radiation subcycles with the gas frozen
+  if (nsub > 0) {
+    rhdk::RadConst<T> RK;
+    RK.c = T(p.c_light);
+    RK.inv_c = T(1.0 / p.c_light);
+    RK.chat = T(chat);
+    RK.inv_w[0] = GK.inv_w[0];
+    RK.inv_w[1] = GK.inv_w[1];
+    RK.inv_w[2] = GK.inv_w[2];
+    RK.theta = T(p.theta_F);
+    RK.er_floor = T(p.er_floor);
+    RK.beta = beta;
+    RK.absorb = mode == RHD_EXCHANGE_ABSORB_ONLY;
+    auto view = gas_view<T>(h);
+    auto rh = rad_ptrs<T>(h->b.rh);
+    const double hr = dt / nsub;
+    dim3 gp, bp, gc, bc;
+    region_launch(G.ps, gp, bp);
+    region_launch(G.n, gc, bc);
+    for (int m = 0; m < nsub; ++m) {
+      int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
+      hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK,
+                         T(0.5 * hr));
+      tend(h, ti);
+      ti = tbegin(h, KC_RAD_CORRECT, h->N);
+      hipLaunchKernelGGL(rhdk::k_rad_correct<T>, gc, bc, 0, h->stream, rad, rh, view, G, RK, T(hr),
+                         h->b.ctr);
+      tend(h, ti);
+    }
+  }
+
+  // 4. second-order correction of the gas sources
+  if (!rad_only) {
+    const int ti = tbegin(h, KC_GAS_SOURCE, h->N);
+    hipLaunchKernelGGL(rhdk::k_gas_source_correct<T>, dim3(blocks_for(h->N, threads)), dim3(threads),
+                       0, h->stream, gas, rad, kFp, T(h->kF_s), GK, T(0.5 * dt),
+                       as<T>(h->b.sn[0]), as<T>(h->b.sn[1]), as<T>(h->b.sn[2]), as<T>(h->b.sn[3]),
+                       as<T>(h->b.wh[0]), as<T>(h->b.wh[1]), as<T>(h->b.wh[2]), as<T>(h->b.wh[3]),
+                       h->N, h->b.ctr);
+    tend(h, ti);
+  }
+  HIP_TRY(h, hipGetLastError());
+
+  // 5. FP64 ledger and non-finite check
+  return enqueue_ledger<T>(h, chat);
+}
+
+template <typename T>
+int upload_field(rhd_t* h, const double* src, void* dst, int n, bool from_host) {
+  const double* dsrc = src;
+  if (from_host) {
+    HIP_TRY(h, hipMemcpyAsync(h->b.staging, src, size_t(n) * sizeof(double), hipMemcpyHostToDevice,
+                              h->stream));
+    dsrc = h->b.staging;
+  }
+  hipLaunchKernelGGL(rhdk::k_from_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream, dsrc,
+                     as<T>(dst), n);
+  HIP_TRY(h, hipGetLastError());
+  if (from_host) HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return RHD_OK;
+}
+
+template <typename T>
+int download_field(rhd_t* h, const void* src, double* dst, int n, bool to_host) {
+  double* ddst = to_host ? h->b.staging : dst;
+  hipLaunchKernelGGL(rhdk::k_to_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream,
+                     as<T>(const_cast<void*>(src)), ddst, n);
+  HIP_TRY(h, hipGetLastError());
+  if (to_host) {
+    HIP_TRY(h, hipMemcpyAsync(dst, h->b.staging, size_t(n) * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  return RHD_OK;
+}
+
+template <typename T>
+int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double* E,
+                   const double* Er, const double* Fr, const double* kappaP, const double* kappaF,
+                   int kappa_scalar, bool host) {
+  if (!rho || !mom || !Er || !Fr || !kappaP || !kappaF)
+    return fail(h, RHD_EINVAL, "rho, mom, Er, Fr, kappaP and kappaF must be non-NULL");
+  const bool iso = (h->p.flags & RHD_ISOTHERMAL) != 0;
+  if (!E && !iso) return fail(h, RHD_EINVAL, "E must be non-NULL for an ideal gas");
+  const int N = h->N;
+  int rc;
+  if ((rc = upload_field<T>(h, rho, h->b.gas[0], N, host))) return rc;
+  for (int q = 0; q < 3; ++q)
+    if ((rc = upload_field<T>(h, mom + size_t(q) * N, h->b.gas[1 + q], N, host))) return rc;
+  if (E) {
+    if ((rc = upload_field<T>(h, E, h->b.gas[4], N, host))) return rc;
+  } else {
+    hipLaunchKernelGGL(rhdk::k_fill<T>, dim3(blocks_for(N, 256)), dim3(256), 0, h->stream,
+                       as<T>(h->b.gas[4]), T(0), N);
+  }
+  if ((rc = upload_field<T>(h, Er, h->b.rad[0], N, host))) return rc;
+  for (int q = 0; q < 3; ++q)
+    if ((rc = upload_field<T>(h, Fr + size_t(q) * N, h->b.rad[1 + q], N, host))) return rc;
+  if (kappa_scalar) {
+    double kp = 0.0, kf = 0.0;
+    if (host) {
+      kp = kappaP[0];
+      kf = kappaF[0];
+    } else {
+      HIP_TRY(h, hipMemcpyAsync(&kp, kappaP, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(&kf, kappaF, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    h->kappa_scalar = true;
+    h->kP_s = double(T(kp));
+    h->kF_s = double(T(kf));
+  } else {
+    if (!h->b.kP) {
+      HIP_TRY(h, hipMalloc(&h->b.kP, size_t(N) * h->esize));
+      HIP_TRY(h, hipMalloc(&h->b.kF, size_t(N) * h->esize));
+      h->bytes += 2ll * N * (long long)h->esize;
+    }
+    if ((rc = upload_field<T>(h, kappaP, h->b.kP, N, host))) return rc;
+    if ((rc = upload_field<T>(h, kappaF, h->b.kF, N, host))) return rc;
+    h->kappa_scalar = false;
+  }
+  h->have_state = true;
+  return RHD_OK;
+}
+
+template <typename T>
+int get_state_impl(rhd_t* h, double* rho, double* mom, double* E, double* Er, double* Fr,
+                   bool host) {
+  const int N = h->N;
+  int rc;
+  if (rho && (rc = download_field<T>(h, h->b.gas[0], rho, N, host))) return rc;
+  if (mom)
+    for (int q = 0; q < 3; ++q)
+      if ((rc = download_field<T>(h, h->b.gas[1 + q], mom + size_t(q) * N, N, host))) return rc;
+  if (E && (rc = download_field<T>(h, h->b.gas[4], E, N, host))) return rc;
+  if (Er && (rc = download_field<T>(h, h->b.rad[0], Er, N, host))) return rc;
+  if (Fr)
+    for (int q = 0; q < 3; ++q)
+      if ((rc = download_field<T>(h, h->b.rad[1 + q], Fr + size_t(q) * N, N, host))) return rc;
+  return RHD_OK;
+}
+
+template <typename T>
+int suggest_impl(rhd_t* h, double chat, double* dt_gas, int* nsub) {
+  rhdk::CflConst C;
+  C.gamma = h->p.gamma;
+  C.gm1 = h->p.gamma - 1.0;
+  C.cs2 = h->p.iso_cs * h->p.iso_cs;
+  C.dxmin = h->dxmin;
+  C.iso = (h->p.flags & RHD_ISOTHERMAL) != 0;
+  const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+  const int ti = tbegin(h, KC_VMAX, h->N);
+  hipLaunchKernelGGL(rhdk::k_vmax<T>, dim3(VMAX_BLOCKS), dim3(rhdk::RED_THREADS), 0, h->stream,
+                     gas_ptrs<T>(h->b.gas), rad_ptrs<T>(h->b.rad), kFp, T(h->kF_s), C, h->N,
+                     as<T>(h->b.vmax_partials));
+  hipLaunchKernelGGL(rhdk::k_vmax_final<T>, dim3(1), dim3(rhdk::RED_THREADS), 0, h->stream,
+                     as<T>(h->b.vmax_partials), VMAX_BLOCKS, h->b.vmax);
+  tend(h, ti);
+  HIP_TRY(h, hipGetLastError());
+  double vmax = 0.0;
+  HIP_TRY(h, hipMemcpyAsync(&vmax, h->b.vmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->vmax_last = vmax;
+  if (!(vmax > 0.0) || !std::isfinite(vmax))
+    return fail(h, RHD_ENONFINITE, "v_max of the state is %g", vmax);
+  *dt_gas = h->p.cfl * h->dxmin / vmax;
+  const double r = std::ceil(chat / vmax);
+  *nsub = r < 1.0 ? 1 : (r > 1e9 ? 1000000000 : int(r));
+  return RHD_OK;
+}
+
+void free_buffers(rhd_t* h) {
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto& q : h->b.gas) fr(q);
+  for (auto& q : h->b.rad) fr(q);
+  fr(h->b.kP);
+  fr(h->b.kF);
+  fr(h->b.j);
+  for (auto& q : h->b.gh) fr(q);
+  for (auto& q : h->b.rh) fr(q);
+  for (auto& q : h->b.sn) fr(q);
+  for (auto& q : h->b.wh) fr(q);
+  fr(h->b.staging);
+  fr(h->b.ledger_partials);
+  fr(h->b.ledger);
+  fr(h->b.vmax_partials);
+  fr(h->b.vmax);
+  fr(h->b.ctr);
+  h->b = Buffers();
+}
+
+}  // namespace
+
+extern "C" {
+
+void rhd_default_params(rhd_params* p, int nx, int ny, int nz) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->dx = nx > 0 ? 1.0 / nx : 1.0;
+  p->dy = ny > 0 ? 1.0 / ny : 1.0;
+  p->dz = nz > 0 ? 1.0 / nz : 1.0;
+  p->gamma = 5.0 / 3.0;
+  p->c_light = 1.0;
+  p->a_rad = 1.0;
+  p->r_gas = 1.0;
+  p->iso_cs = 1.0;
+  p->cfl = 0.4;
+  p->theta_E = 1.0;
+  p->theta_F = 0.51;
+  p->newton_rtol = 1e-10;
+  p->newton_maxit = 50;
+  p->rho_floor = 1e-10;
+  p->p_floor = 1e-14;
+  p->er_floor = 1e-30;
+  for (int f = 0; f < 6; ++f) p->bc[f] = RHD_BC_PERIODIC;
+  p->flags = RHD_EXCHANGE_FULL;
+}
+
+long long rhd_footprint_bytes(const rhd_params* p) {
+  if (validate(p) != RHD_OK) return -1;
+  return footprint(p, nullptr, nullptr);
+}
+
+int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
+  if (!out) return fail(nullptr, RHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  rhd_t* h = new (std::nothrow) rhd();
+  if (!h) return fail(nullptr, RHD_ENOMEM, "host allocation failed");
+  h->p = *p;
+  h->mixed = (p->flags & RHD_PRECISION_MIXED) != 0;
+  h->esize = h->mixed ? 4 : 8;
+  h->G = make_geom(p);
+  long long N, NP;
+  footprint(p, &N, &NP);
+  h->N = int(N);
+  h->NP = int(NP);
+  h->dxmin = min_width(p);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, RHD_EDEVICE, "no HIP device");
+  }
+  if (hip_stream) {
+    h->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return fail(nullptr, RHD_EDEVICE, "hipStreamCreate failed");
+    }
+    h->own_stream = true;
+  }
+  const size_t es = h->esize;
+  bool ok = true;
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+      ok = false;
+      *ptr = nullptr;
+      return;
+    }
+    h->bytes += (long long)bytes;
+  };
+  for (auto& q : h->b.gas) alloc(&q, N * es);
+  for (auto& q : h->b.rad) alloc(&q, N * es);
+  for (auto& q : h->b.rh) alloc(&q, NP * es);
+  if (!(p->flags & RHD_RAD_ONLY)) {
+    for (auto& q : h->b.gh) alloc(&q, NP * es);
+    for (auto& q : h->b.sn) alloc(&q, N * es);
+    for (auto& q : h->b.wh) alloc(&q, N * es);
+  }
+  alloc(reinterpret_cast<void**>(&h->b.staging), N * sizeof(double));
+  alloc(reinterpret_cast<void**>(&h->b.ledger_partials), 5 * LEDGER_BLOCKS * sizeof(double));
+  alloc(reinterpret_cast<void**>(&h->b.ledger), 5 * sizeof(double));
+  alloc(&h->b.vmax_partials, VMAX_BLOCKS * sizeof(double));
+  alloc(reinterpret_cast<void**>(&h->b.vmax), sizeof(double));
+  alloc(reinterpret_cast<void**>(&h->b.ctr), rhdk::CTR_COUNT * sizeof(unsigned long long));
+  if (!ok) {
+    free_buffers(h);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return fail(nullptr, RHD_ENOMEM, "device allocation of %lld bytes failed", footprint(p, 0, 0));
+  }
+  hipLaunchKernelGGL(rhdk::k_reset_counters, dim3(1), dim3(64), 0, h->stream, h->b.ctr);
+  if (hipMemsetAsync(h->b.ledger, 0, 5 * sizeof(double), h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    free_buffers(h);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return fail(nullptr, RHD_EDEVICE, "initialisation failed");
+  }
+  *out = h;
+  return RHD_OK;
+}
+
+int rhd_set_state(rhd_t* h, const double* rho, const double* mom, const double* E,
+                  const double* Er, const double* Fr, const double* kappaP, const double* kappaF,
+                  int kappa_scalar) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  return h->mixed ? set_state_impl<float>(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar, true)
+                  : set_state_impl<double>(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar, true);
+}
+
+int rhd_set_state_device(rhd_t* h, const double* rho, const double* mom, const double* E,
+                         const double* Er, const double* Fr, const double* kappaP,
+                         const double* kappaF, int kappa_scalar) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  return h->mixed ? set_state_impl<float>(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar, false)
+                  : set_state_impl<double>(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar, false);
+}
+
+int rhd_set_emission(rhd_t* h, const double* j) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!j) {
+    if (h->b.j) {
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+      HIP_TRY(h, hipFree(h->b.j));
+      h->b.j = nullptr;
+      h->bytes -= (long long)h->N * (long long)h->esize;
+    }
+    return RHD_OK;
+  }
+  if (!h->b.j) {
+    HIP_TRY(h, hipMalloc(&h->b.j, size_t(h->N) * h->esize));
+    h->bytes += (long long)h->N * (long long)h->esize;
+  }
+  return h->mixed ? upload_field<float>(h, j, h->b.j, h->N, true)
+                  : upload_field<double>(h, j, h->b.j, h->N, true);
+}
+
+int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_step before rhd_set_state");
+  if (!(dt_gas > 0.0) || !std::isfinite(dt_gas))
+    return fail(h, RHD_EINVAL, "dt_gas must be finite and > 0 (got %g)", dt_gas);
+  if (!(chat > 0.0) || !std::isfinite(chat))
+    return fail(h, RHD_EINVAL, "chat must be finite and > 0 (got %g)", chat);
+  if (nsub < 0) return fail(h, RHD_EINVAL, "nsub must be >= 0 (got %d)", nsub);
+  if (nsub > 0 && chat * dt_gas / nsub > h->p.cfl * h->dxmin * (1.0 + 1e-12))
+    return fail(h, RHD_ECFL, "chat dt_gas / nsub = %g exceeds K0 dx = %g",
+                chat * dt_gas / nsub, h->p.cfl * h->dxmin);
+  int rc = h->mixed ? enqueue_step<float>(h, dt_gas, chat, nsub)
+                    : enqueue_step<double>(h, dt_gas, chat, nsub);
+  if (rc == RHD_OK) {
+    h->steps += 1;
+    h->subcycles += nsub;
+  }
+  return rc;
+}
+
+int rhd_suggest_dt(rhd_t* h, double chat, double* dt_gas, int* nsub) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!dt_gas || !nsub) return fail(h, RHD_EINVAL, "dt_gas and nsub must be non-NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_suggest_dt before rhd_set_state");
+  if (!(chat > 0.0)) return fail(h, RHD_EINVAL, "chat must be > 0");
+  return h->mixed ? suggest_impl<float>(h, chat, dt_gas, nsub)
+                  : suggest_impl<double>(h, chat, dt_gas, nsub);
+}
+
+int rhd_ledger(rhd_t* h, double chat) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_ledger before rhd_set_state");
+  if (!(chat > 0.0)) return fail(h, RHD_EINVAL, "chat must be > 0");
+  return h->mixed ? enqueue_ledger<float>(h, chat) : enqueue_ledger<double>(h, chat);
+}
+
+int rhd_get_state(rhd_t* h, double* rho, double* mom, double* E, double* Er, double* Fr) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_get_state before rhd_set_state");
+  return h->mixed ? get_state_impl<float>(h, rho, mom, E, Er, Fr, true)
+                  : get_state_impl<double>(h, rho, mom, E, Er, Fr, true);
+}
+
+int rhd_get_state_device(rhd_t* h, double* rho, double* mom, double* E, double* Er, double* Fr) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_get_state_device before rhd_set_state");
+  return h->mixed ? get_state_impl<float>(h, rho, mom, E, Er, Fr, false)
+                  : get_state_impl<double>(h, rho, mom, E, Er, Fr, false);
+}
+
+int rhd_get_diagnostics(rhd_t* h, rhd_diag* out) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!out) return fail(h, RHD_EINVAL, "out is NULL");
+  unsigned long long c[rhdk::CTR_COUNT];
+  double led[5];
+  HIP_TRY(h, hipMemcpyAsync(c, h->b.ctr, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(led, h->b.ledger, sizeof(led), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (int q = 0; q < 5; ++q) out->ledger[q] = led[q];
+  out->vmax = h->vmax_last;
+  out->exch_theta1 = (long long)c[rhdk::CTR_EXCH_THETA1];
+  out->exch_bisect = (long long)c[rhdk::CTR_EXCH_BISECT];
+  out->newton_iters = (long long)c[rhdk::CTR_NEWTON_ITERS];
+  out->newton_max = (long long)c[rhdk::CTR_NEWTON_MAX];
+  out->rad_fclamp = (long long)c[rhdk::CTR_RAD_FCLAMP];
+  out->rad_efloor = (long long)c[rhdk::CTR_RAD_EFLOOR];
+  out->gas_rhofloor = (long long)c[rhdk::CTR_GAS_RHOFLOOR];
+  out->gas_pfloor = (long long)c[rhdk::CTR_GAS_PFLOOR];
+  out->nonfinite = (long long)c[rhdk::CTR_NONFINITE];
+  out->first_nonfinite_cell = c[rhdk::CTR_FIRST_BAD] == ~0ull ? -1 : (long long)c[rhdk::CTR_FIRST_BAD];
+  out->steps = h->steps;
+  out->subcycles = h->subcycles;
+  return RHD_OK;
+}
+
+int rhd_reset_diagnostics(rhd_t* h) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  hipLaunchKernelGGL(rhdk::k_reset_counters, dim3(1), dim3(64), 0, h->stream, h->b.ctr);
+  HIP_TRY(h, hipGetLastError());
+  h->steps = 0;
+  h->subcycles = 0;
+  return RHD_OK;
+}
+
+int rhd_sync(rhd_t* h) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  unsigned long long bad = 0;
+  HIP_TRY(h, hipMemcpyAsync(&bad, h->b.ctr + rhdk::CTR_NONFINITE, sizeof(bad),
+                            hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (bad) return fail(h, RHD_ENONFINITE, "%llu non-finite values in the state", bad);
+  return RHD_OK;
+}
+
+int rhd_set_timing(rhd_t* h, int enable) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  Timer& t = h->timer;
+  if (enable && !t.start) {
+    t.start = new (std::nothrow) hipEvent_t[Timer::POOL];
+    t.stop = new (std::nothrow) hipEvent_t[Timer::POOL];
+    if (!t.start || !t.stop) return fail(h, RHD_ENOMEM, "event pool allocation failed");
+    for (int i = 0; i < Timer::POOL; ++i) {
+      HIP_TRY(h, hipEventCreate(&t.start[i]));
+      HIP_TRY(h, hipEventCreate(&t.stop[i]));
+    }
+  }
+  if (!enable) {
+    int rc = timer_drain(h);
+    t.on = false;
+    return rc;
+  }
+  int rc = timer_drain(h);
+  if (rc) return rc;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    t.calls[k] = 0;
+    t.ms[k] = 0.0;
+    t.cells[k] = 0;
+  }
+  t.on = true;
+  return RHD_OK;
+}
+
+int rhd_get_timing(rhd_t* h, rhd_timing* out) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!out) return fail(h, RHD_EINVAL, "out is NULL");
+  int rc = timer_drain(h);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->nkernels = KC_COUNT;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    std::snprintf(out->name[k], sizeof(out->name[k]), "%s", kKernelNames[k]);
+    out->calls[k] = h->timer.calls[k];
+    out->total_ms[k] = h->timer.ms[k];
+    out->cells[k] = h->timer.cells[k];
+  }
+  return RHD_OK;
+}
+
+long long rhd_device_bytes(const rhd_t* h) { return h ? h->bytes : 0; }
+
+void rhd_destroy(rhd_t* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->timer.start) {
+    for (int i = 0; i < Timer::POOL; ++i) {
+      (void)hipEventDestroy(h->timer.start[i]);
+      (void)hipEventDestroy(h->timer.stop[i]);
+    }
+    delete[] h->timer.start;
+    delete[] h->timer.stop;
+  }
+  free_buffers(h);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char* rhd_last_error(const rhd_t* h) { return h ? h->err : g_create_error; }
+
+}  // extern "C"

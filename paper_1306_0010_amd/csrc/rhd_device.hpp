@@ -1,0 +1,997 @@
+// rhd_device.hpp -- device code of the gfx950 library for the gray M1
+// radiation-hydrodynamics step of Skinner & Ostriker (2013).
+//
+// Layout: one array per field (structure of arrays), cell (i, j, k) at
+// i + nx*(j + ny*k), x fastest, so a wavefront reads 64 consecutive x-cells of a field
+// in one coalesced access. Boundary conditions are applied by index mapping when a
+// stencil reads outside the grid (periodic wrap, zero-gradient clamp, mirror with the
+// normal vector components negated), so no ghost-fill pass touches HBM.
+//
+// The half-step states of the Van Leer predictor live in padded scratch arrays with
+// two ghost layers per active dimension: the predictor is evaluated there from the
+// boundary-mapped old state, and the corrector reads those predicted ghost values
+// directly (no boundary refill between the two stages).
+//
+// T is the type of the stencil arithmetic and of the stored state (double in FP64
+// mode, float in mixed mode). The energy exchange, the ledger and all counters are
+// FP64 / 64-bit whatever T is.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rhdk {
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+
+enum {
+  CTR_EXCH_THETA1 = 0,
+  CTR_EXCH_BISECT,
+  CTR_NEWTON_ITERS,
+  CTR_NEWTON_MAX,
+  CTR_RAD_FCLAMP,
+  CTR_RAD_EFLOOR,
+  CTR_GAS_RHOFLOOR,
+  CTR_GAS_PFLOOR,
+  CTR_NONFINITE,
+  CTR_FIRST_BAD,
+  CTR_COUNT
+};
+
+struct Geom {
+  int n[3];    // interior cells per dimension
+  int act[3];  // 1 when the dimension is active (n > 1)
+  int bc[6];   // boundary kind per face
+  int g[3];    // ghost width of the padded half-step arrays (2 if active, else 0)
+  int ps[3];   // padded extents n + 2 g
+};
+
+template <typename T>
+struct RadPtrs {
+  T* E;
+  T* F[3];
+};
+
+template <typename T>
+struct GasPtrs {
+  T* rho;
+  T* m[3];
+  T* E;
+};
+
+// Frozen gas seen by the radiation subcycles.
+template <typename T>
+struct GasView {
+  const T* rho;
+  const T* m[3];
+  const T* kP;  // per-cell specific opacity, or null for the scalar below
+  const T* kF;
+  const T* j;   // emissivity or null
+  T kP_s, kF_s;
+};
+
+template <typename T>
+struct RadConst {
+  T c, inv_c, chat;
+  T inv_w[3];
+  T theta;
+  T er_floor;
+  int beta;    // O(beta tau) terms on
+  int absorb;  // absorption-only mode: E_r damped with kappa_P on each stage
+};
+
+template <typename T>
+struct GasConst {
+  T c, inv_c;
+  T inv_w[3];
+  T gamma, gm1, cs2;
+  T rho_floor, p_floor;
+  int beta;
+  int iso;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int map_index(int q, int n, int lo, int hi, int& flip) {
+  if (q < 0) {
+    if (lo == BC_PERIODIC) {
+      int r = q % n;
+      return r < 0 ? r + n : r;
+    }
+    if (lo == BC_OUTFLOW) return 0;
+    flip = -flip;
+    return -1 - q;
+  }
+  if (q >= n) {
+    if (hi == BC_PERIODIC) return q % n;
+    if (hi == BC_OUTFLOW) return n - 1;
+    flip = -flip;
+    return 2 * n - 1 - q;
+  }
+  return q;
+}
+
+// Flat interior index of a possibly out-of-range cell after boundary mapping, and
+// the sign each vector component takes there.
+__device__ __forceinline__ int mapped_cell(const Geom& G, int i, int j, int k, int s[3]) {
+  s[0] = s[1] = s[2] = 1;
+  int si = G.act[0] ? map_index(i, G.n[0], G.bc[0], G.bc[1], s[0]) : 0;
+  int sj = G.act[1] ? map_index(j, G.n[1], G.bc[2], G.bc[3], s[1]) : 0;
+  int sk = G.act[2] ? map_index(k, G.n[2], G.bc[4], G.bc[5], s[2]) : 0;
+  return si + G.n[0] * (sj + G.n[1] * sk);
+}
+
+__device__ __forceinline__ int padded_cell(const Geom& G, int i, int j, int k) {
+  return (i + G.g[0]) + G.ps[0] * ((j + G.g[1]) + G.ps[1] * (k + G.g[2]));
+}
+
+__device__ __forceinline__ bool is_interior(const Geom& G, int i, int j, int k) {
+  return i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
+}
+
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+// Monotonised-central limited slope.
+template <typename T>
+__device__ __forceinline__ T mc_slope(T dm, T dp) {
+  if (dm * dp <= T(0)) return T(0);
+  T a = fabs(T(0.5) * (dm + dp));
+  T b = T(2) * fabs(dm);
+  T e = T(2) * fabs(dp);
+  T m = tmin(a, tmin(b, e));
+  return dm > T(0) ? m : -m;
+}
+
+// Sum of v over the wavefront; lane 0 adds it to *ctr. Every lane must call it.
+__device__ __forceinline__ void wave_add(unsigned long long* ctr, unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (__lane_id() == 0 && v != 0ull) atomicAdd(ctr, v);
+}
+
+__device__ __forceinline__ void wave_max(unsigned long long* ctr, unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  if (__lane_id() == 0 && v != 0ull) atomicMax(ctr, v);
+}
+
+// ---------------------------------------------------------------------------
+// M1 closure, eigenvalues and HLL flux (Sec. 2.3, Sec. 3.3)
+// ---------------------------------------------------------------------------
+
+// Physical flux of (E_r, F) normal to d and the extreme M1 wave speeds.
+//
+// With the reduced flux f = F/(c E) (its norm clamped to 1) and s = sqrt(4 - 3 f^2),
+// the Eddington factor of Eq. m1:chi equals (5 - 2 s)/3, so the tensor of Eq. m1:m1tns
+// is T = (s - 1)/3 I + 3 f f / (2 + s): no division by |F| and no special case at F = 0.
+// For the eigenvalues of Eq. hyperbolic:evals13, mu f = f_d and the radicand
+//   (2/3)(4 - 3f^2 - s) + 2 mu^2 (2 - f^2 - s)
+// equals (2/3) s (s - 1) - 2 f_d^2 (1 - f^2) / (2 - f^2 + s), again free of 1/|F|.
+template <typename T>
+__device__ __forceinline__ void m1_flux_speeds(const T U[4], int d, T c, T inv_c, T chat,
+                                               T Phi[4], T& lmin, T& lmax) {
+  const T E = U[0];
+  const T icE = inv_c / E;
+  T f0 = U[1] * icE, f1 = U[2] * icE, f2v = U[3] * icE;
+  T ff = f0 * f0 + f1 * f1 + f2v * f2v;
+  if (ff > T(1)) {
+    T r = T(1) / sqrt(ff);
+    f0 *= r;
+    f1 *= r;
+    f2v *= r;
+    ff = T(1);
+  }
+  const T s = sqrt(T(4) - T(3) * ff);
+  const T iso = (s - T(1)) * T(1.0 / 3.0);
+  const T dir = T(3) / (T(2) + s);
+  const T fd = d == 0 ? f0 : (d == 1 ? f1 : f2v);
+  const T scale = chat * c * E;
+  Phi[0] = chat * U[1 + d] * inv_c;
+  Phi[1] = scale * (dir * fd * f0 + (d == 0 ? iso : T(0)));
+  Phi[2] = scale * (dir * fd * f1 + (d == 1 ? iso : T(0)));
+  Phi[3] = scale * (dir * fd * f2v + (d == 2 ? iso : T(0)));
+  T rad = T(2.0 / 3.0) * s * (s - T(1)) - T(2) * fd * fd * (T(1) - ff) / (T(2) - ff + s);
+  rad = tmax(rad, T(0));
+  const T r = sqrt(rad);
+  const T is = chat / s;
+  lmin = (fd - r) * is;
+  lmax = (fd + r) * is;
+}
+
+// HLL flux of Eq. hyperbolic:hllflux2 with S_L, S_R from the M1 eigenvalues of both
+// states; the central flux when both bounds vanish.
+template <typename T>
+__device__ __forceinline__ void rad_hll(const T UL[4], const T UR[4], int d, T c, T inv_c,
+                                        T chat, T flux[4]) {
+  T PL[4], PR[4], l1L, l3L, l1R, l3R;
+  m1_flux_speeds(UL, d, c, inv_c, chat, PL, l1L, l3L);
+  m1_flux_speeds(UR, d, c, inv_c, chat, PR, l1R, l3R);
+  const T SLm = tmin(tmin(l1L, l1R), T(0));
+  const T SRp = tmax(tmax(l3L, l3R), T(0));
+  const T den = SRp - SLm;
+  if (den > T(0)) {
+    const T id = T(1) / den;
+    const T pr = SRp * SLm;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) flux[q] = (SRp * PL[q] - SLm * PR[q] + pr * (UR[q] - UL[q])) * id;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) flux[q] = T(0.5) * (PL[q] + PR[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// radiation stage update (Sec. 3.4)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Frozen {
+  T rkF, rkP;
+  T v[3];
+  T j;
+};
+
+template <typename T>
+__device__ __forceinline__ Frozen<T> frozen_at(const GasView<T>& g, int a, const int s[3],
+                                               bool need_v) {
+  Frozen<T> fz;
+  const T rho = g.rho[a];
+  fz.rkF = rho * (g.kF ? g.kF[a] : g.kF_s);
+  fz.rkP = rho * (g.kP ? g.kP[a] : g.kP_s);
+  if (need_v) {
+    const T ir = T(1) / rho;
+    fz.v[0] = T(s[0]) * g.m[0][a] * ir;
+    fz.v[1] = T(s[1]) * g.m[1][a] * ir;
+    fz.v[2] = T(s[2]) * g.m[2][a] * ir;
+  } else {
+    fz.v[0] = fz.v[1] = fz.v[2] = T(0);
+  }
+  fz.j = g.j ? g.j[a] : T(0);
+  return fz;
+}
+
+// New (E_r, F) of a stage of length h from the old state Uo, the flux divergence and
+// the explicit sources at Us. F gets the theta-scheme absorption of
+// Eq. source:stiff:radmomentum:soln with the divergence and the explicit terms on the
+// same implicit footing; E_r gets the same form with kappa_P in absorption-only mode
+// (Eq. source:stiff:radenergy:soln). Then E_r >= er_floor and |F| <= c E_r.
+template <typename T>
+__device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo[4],
+                                           const T Us[4], const T div[4], const Frozen<T>& fz,
+                                           T out[4], bool& efloor, bool& fclamp) {
+  const T chat = K.chat;
+  const T b = K.beta ? T(1) : T(0);
+  const T th = K.theta;
+  const T vF = fz.v[0] * Us[1] + fz.v[1] * Us[2] + fz.v[2] * Us[3];
+  const T srcE = b * chat * fz.rkF * vF * K.inv_c * K.inv_c + chat * K.inv_c * fz.j;
+  T En;
+  if (K.absorb) {
+    const T aP = chat * fz.rkP * h;
+    En = (Uo[0] * (T(1) - (T(1) - th) * aP) + h * (-div[0] + srcE)) / (T(1) + th * aP);
+  } else {
+    En = Uo[0] + h * (-div[0] + srcE);
+  }
+  const T a = chat * fz.rkF * h;
+  const T keep = T(1) - (T(1) - th) * a;
+  const T inv = T(1) / (T(1) + th * a);
+  const T adv = b * T(4.0 / 3.0) * chat * fz.rkF * Us[0];
+  T Fn[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Fn[q] = (Uo[1 + q] * keep + h * (-div[1 + q] + adv * fz.v[q])) * inv;
+  efloor = false;
+  fclamp = false;
+  if (En < K.er_floor) {
+    En = K.er_floor;
+    efloor = true;
+  }
+  const T cE = K.c * En;
+  const T Fm2 = Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2];
+  if (Fm2 > cE * cE) {
+    const T scale = cE / sqrt(Fm2);
+    Fn[0] *= scale;
+    Fn[1] *= scale;
+    Fn[2] *= scale;
+    fclamp = true;
+  }
+  out[0] = En;
+  out[1] = Fn[0];
+  out[2] = Fn[1];
+  out[3] = Fn[2];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rad_mapped(const RadPtrs<T>& R, const Geom& G, int i, int j,
+                                                int k, T U[4]) {
+  int s[3];
+  const int a = mapped_cell(G, i, j, k, s);
+  U[0] = R.E[a];
+  U[1] = T(s[0]) * R.F[0][a];
+  U[2] = T(s[1]) * R.F[1][a];
+  U[3] = T(s[2]) * R.F[2][a];
+}
+
+// Radiation predictor: first-order HLL fluxes of U^m, half step, on the interior plus
+// two ghost layers, written to the padded half-step arrays.
+template <typename T>
+__global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
+                                                     Geom G, RadConst<T> K, T h) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
+  const int k = int(blockIdx.z) - G.g[2];
+  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+  T U0[4];
+  load_rad_mapped(Um, G, i, j, k, U0);
+  T div[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    T Ul[4], Ur[4], fl[4], fr[4];
+    load_rad_mapped(Um, G, i - di, j - dj, k - dk, Ul);
+    load_rad_mapped(Um, G, i + di, j + dj, k + dk, Ur);
+    rad_hll(Ul, U0, d, K.c, K.inv_c, K.chat, fl);
+    rad_hll(U0, Ur, d, K.c, K.inv_c, K.chat, fr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
+  }
+  int s[3];
+  const int a = mapped_cell(G, i, j, k, s);
+  const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+  T out[4];
+  bool ef, fc;
+  rad_update(K, h, U0, U0, div, fz, out, ef, fc);
+  const int p = padded_cell(G, i, j, k);
+  Uh.E[p] = out[0];
+  Uh.F[0][p] = out[1];
+  Uh.F[1][p] = out[2];
+  Uh.F[2][p] = out[3];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_padded4(const RadPtrs<T>& R, int p, T U[4]) {
+  U[0] = R.E[p];
+  U[1] = R.F[0][p];
+  U[2] = R.F[1][p];
+  U[3] = R.F[2][p];
+}
+
+// Radiation corrector: MC-limited linear reconstruction of U^{m+1/2}, HLL fluxes,
+// full step from U^m with sources at U^{m+1/2}; writes U^{m+1} over U^m (each thread
+// reads U^m only in its own cell).
+template <typename T>
+__global__ void __launch_bounds__(256) k_rad_correct(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
+                                                     Geom G, RadConst<T> K, T h,
+                                                     unsigned long long* ctr) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y);
+  const int k = int(blockIdx.z);
+  const bool valid = i < G.n[0] && j < G.n[1];
+  bool ef = false, fc = false;
+  if (valid) {
+    const int pc = padded_cell(G, i, j, k);
+    T Uc[4];
+    load_padded4(Uh, pc, Uc);
+    T div[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (!G.act[d]) continue;
+      const int stride = d == 0 ? 1 : (d == 1 ? G.ps[0] : G.ps[0] * G.ps[1]);
+      T Um2[4], Um1[4], Up1[4], Up2[4];
+      load_padded4(Uh, pc - 2 * stride, Um2);
+      load_padded4(Uh, pc - stride, Um1);
+      load_padded4(Uh, pc + stride, Up1);
+      load_padded4(Uh, pc + 2 * stride, Up2);
+      T Lm[4], Rm[4], Lp[4], Rp[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T sm = mc_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
+        const T s0 = mc_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
+        const T sp = mc_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
+        Lm[q] = Um1[q] + T(0.5) * sm;
+        Rm[q] = Uc[q] - T(0.5) * s0;
+        Lp[q] = Uc[q] + T(0.5) * s0;
+        Rp[q] = Up1[q] - T(0.5) * sp;
+      }
+      T fl[4], fr[4];
+      rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
+      rad_hll(Lp, Rp, d, K.c, K.inv_c, K.chat, fr);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
+    }
+    const int a = i + G.n[0] * (j + G.n[1] * k);
+    const int s[3] = {1, 1, 1};
+    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+    T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+    T out[4];
+    rad_update(K, h, Uo, Uc, div, fz, out, ef, fc);
+    Um.E[a] = out[0];
+    Um.F[0][a] = out[1];
+    Um.F[1][a] = out[2];
+    Um.F[2][a] = out[3];
+  }
+  wave_add(ctr + CTR_RAD_EFLOOR, ef ? 1ull : 0ull);
+  wave_add(ctr + CTR_RAD_FCLAMP, fc ? 1ull : 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// gas subsystem
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void gas_prim(const GasConst<T>& K, const T U[5], T W[5]) {
+  const T ir = T(1) / U[0];
+  W[0] = U[0];
+  W[1] = U[1] * ir;
+  W[2] = U[2] * ir;
+  W[3] = U[3] * ir;
+  if (K.iso) {
+    W[4] = U[0] * K.cs2;
+  } else {
+    W[4] = K.gm1 * (U[4] - T(0.5) * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]));
+  }
+}
+
+// Euler flux normal to d of a primitive state plus its conserved state.
+template <typename T>
+__device__ __forceinline__ void gas_flux(const GasConst<T>& K, const T W[5], int d, T U[5],
+                                         T F[5]) {
+  const T P = K.iso ? W[0] * K.cs2 : W[4];
+  U[0] = W[0];
+  U[1] = W[0] * W[1];
+  U[2] = W[0] * W[2];
+  U[3] = W[0] * W[3];
+  U[4] = K.iso ? T(0)
+               : P / K.gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+  const T un = W[1 + d];
+  F[0] = U[0] * un;
+  F[1] = U[1] * un;
+  F[2] = U[2] * un;
+  F[3] = U[3] * un;
+  F[1 + d] += P;
+  F[4] = K.iso ? T(0) : (U[4] + P) * un;
+}
+
+// HLLC with Davis wave-speed bounds (HLLE for an isothermal gas).
+template <typename T>
+__device__ __forceinline__ void gas_riemann(const GasConst<T>& K, const T WL[5], const T WR[5],
+                                            int d, T flux[5]) {
+  const T aL = K.iso ? sqrt(K.cs2) : sqrt(K.gamma * WL[4] / WL[0]);
+  const T aR = K.iso ? sqrt(K.cs2) : sqrt(K.gamma * WR[4] / WR[0]);
+  const T uL = WL[1 + d], uR = WR[1 + d];
+  const T SL = tmin(uL - aL, uR - aR);
+  const T SR = tmax(uL + aL, uR + aR);
+  T UL[5], UR[5], FL[5], FR[5];
+  gas_flux(K, WL, d, UL, FL);
+  gas_flux(K, WR, d, UR, FR);
+  if (K.iso) {
+    const T SLm = tmin(SL, T(0)), SRp = tmax(SR, T(0));
+    const T id = T(1) / (SRp - SLm);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) flux[q] = (SRp * FL[q] - SLm * FR[q] + SRp * SLm * (UR[q] - UL[q])) * id;
+    flux[4] = T(0);
+    return;
+  }
+  if (SL >= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) flux[q] = FL[q];
+    return;
+  }
+  if (SR <= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) flux[q] = FR[q];
+    return;
+  }
+  const T rL = WL[0], rR = WR[0];
+  const T SM = (WR[4] - WL[4] + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+               (rL * (SL - uL) - rR * (SR - uR));
+  const bool left = SM >= T(0);
+  const T* Wk = left ? WL : WR;
+  const T* Uk = left ? UL : UR;
+  const T* Fk = left ? FL : FR;
+  const T Sk = left ? SL : SR;
+  const T uk = Wk[1 + d];
+  const T fac = Wk[0] * (Sk - uk) / (Sk - SM);
+  T Us[5];
+  Us[0] = fac;
+  Us[1] = fac * Wk[1];
+  Us[2] = fac * Wk[2];
+  Us[3] = fac * Wk[3];
+  Us[1 + d] = fac * SM;
+  Us[4] = fac * (Uk[4] / Wk[0] + (SM - uk) * (SM + Wk[4] / (Wk[0] * (Sk - uk))));
+#pragma unroll
+  for (int q = 0; q < 5; ++q) flux[q] = Fk[q] + Sk * (Us[q] - Uk[q]);
+}
+
+// Explicit gas source (Eq. algorithm:source:explicit:gas, no gravity): momentum
+// rho kF F/c - b (4/3) rho kF E_r v/c; energy -b rho kF v.F/c. S[0] = 0.
+template <typename T>
+__device__ __forceinline__ void gas_source(const GasConst<T>& K, T rk, const T v[3], T Er,
+                                           const T F[3], T S[5]) {
+  const T b = K.beta ? T(1) : T(0);
+  S[0] = T(0);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) S[1 + q] = rk * F[q] * K.inv_c - b * T(4.0 / 3.0) * rk * Er * v[q] * K.inv_c;
+  S[4] = K.iso ? T(0) : -b * rk * (v[0] * F[0] + v[1] * F[1] + v[2] * F[2]) * K.inv_c;
+}
+
+template <typename T>
+__device__ __forceinline__ void gas_floors(const GasConst<T>& K, T U[5], bool& rf, bool& pf) {
+  rf = pf = false;
+  if (U[0] < K.rho_floor) {
+    U[0] = K.rho_floor;
+    rf = true;
+  }
+  if (!K.iso) {
+    const T ke = T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0];
+    const T P = K.gm1 * (U[4] - ke);
+    if (P < K.p_floor) {
+      U[4] = K.p_floor / K.gm1 + ke;
+      pf = true;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_gas_mapped(const GasPtrs<T>& Gp, const Geom& G, int i, int j,
+                                                int k, T U[5]) {
+  int s[3];
+  const int a = mapped_cell(G, i, j, k, s);
+  U[0] = Gp.rho[a];
+  U[1] = T(s[0]) * Gp.m[0][a];
+  U[2] = T(s[1]) * Gp.m[1][a];
+  U[3] = T(s[2]) * Gp.m[2][a];
+  U[4] = Gp.E[a];
+}
+
+// Gas predictor: first-order fluxes of U^n and S_e,gas(U^n, U_r^n), half step, on the
+// interior plus two ghost layers.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gas_predict(GasPtrs<T> Un, GasPtrs<T> Uh, RadPtrs<T> Ur,
+                                                     const T* kF, T kF_s, Geom G, GasConst<T> K,
+                                                     T h) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
+  const int k = int(blockIdx.z) - G.g[2];
+  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+  T U0[5], W0[5];
+  load_gas_mapped(Un, G, i, j, k, U0);
+  gas_prim(K, U0, W0);
+  T div[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    T Ul[5], Ur2[5], Wl[5], Wr[5], fl[5], fr[5];
+    load_gas_mapped(Un, G, i - di, j - dj, k - dk, Ul);
+    load_gas_mapped(Un, G, i + di, j + dj, k + dk, Ur2);
+    gas_prim(K, Ul, Wl);
+    gas_prim(K, Ur2, Wr);
+    gas_riemann(K, Wl, W0, d, fl);
+    gas_riemann(K, W0, Wr, d, fr);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
+  }
+  int s[3];
+  const int a = mapped_cell(G, i, j, k, s);
+  const T rk = W0[0] * (kF ? kF[a] : kF_s);
+  const T Er = Ur.E[a];
+  const T F[3] = {T(s[0]) * Ur.F[0][a], T(s[1]) * Ur.F[1][a], T(s[2]) * Ur.F[2][a]};
+  const T v[3] = {W0[1], W0[2], W0[3]};
+  T S[5];
+  gas_source(K, rk, v, Er, F, S);
+  T out[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) out[q] = U0[q] - h * div[q] + h * S[q];
+  if (K.iso) out[4] = U0[4];
+  bool rf, pf;
+  gas_floors(K, out, rf, pf);
+  const int p = padded_cell(G, i, j, k);
+  Uh.rho[p] = out[0];
+  Uh.m[0][p] = out[1];
+  Uh.m[1][p] = out[2];
+  Uh.m[2][p] = out[3];
+  Uh.E[p] = out[4];
+}
+
+// Gas corrector: MC-limited reconstruction of the primitives of U^{n+1/2}, Riemann
+// fluxes, full step from U^n with S_e,gas(U^{n+1/2}, U_r^n). Writes U^{n+1,*} over U^n
+// and keeps s_n = S_e,gas(U^{n+1/2}, U_r^n) and (rho, v)^{n+1/2} for the correction.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gas_correct(GasPtrs<T> Un, GasPtrs<T> Uh, RadPtrs<T> Ur,
+                                                     const T* kF, T kF_s, Geom G, GasConst<T> K,
+                                                     T h, T* sn0, T* sn1, T* sn2, T* sn3,
+                                                     T* wh0, T* wh1, T* wh2, T* wh3,
+                                                     unsigned long long* ctr) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y);
+  const int k = int(blockIdx.z);
+  const bool valid = i < G.n[0] && j < G.n[1];
+  bool rf = false, pf = false;
+  if (valid) {
+    const int pc = padded_cell(G, i, j, k);
+    T Wc[5];
+    {
+      T Uc[5] = {Uh.rho[pc], Uh.m[0][pc], Uh.m[1][pc], Uh.m[2][pc], Uh.E[pc]};
+      gas_prim(K, Uc, Wc);
+    }
+    T div[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (!G.act[d]) continue;
+      const int stride = d == 0 ? 1 : (d == 1 ? G.ps[0] : G.ps[0] * G.ps[1]);
+      T W[5][5];
+#pragma unroll
+      for (int t = -2; t <= 2; ++t) {
+        if (t == 0) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) W[2][q] = Wc[q];
+          continue;
+        }
+        const int p = pc + t * stride;
+        T U[5] = {Uh.rho[p], Uh.m[0][p], Uh.m[1][p], Uh.m[2][p], Uh.E[p]};
+        gas_prim(K, U, W[t + 2]);
+      }
+      T Lm[5], Rm[5], Lp[5], Rp[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T sm = mc_slope(W[1][q] - W[0][q], W[2][q] - W[1][q]);
+        const T s0 = mc_slope(W[2][q] - W[1][q], W[3][q] - W[2][q]);
+        const T sp = mc_slope(W[3][q] - W[2][q], W[4][q] - W[3][q]);
+        Lm[q] = W[1][q] + T(0.5) * sm;
+        Rm[q] = W[2][q] - T(0.5) * s0;
+        Lp[q] = W[2][q] + T(0.5) * s0;
+        Rp[q] = W[3][q] - T(0.5) * sp;
+      }
+      T fl[5], fr[5];
+      gas_riemann(K, Lm, Rm, d, fl);
+      gas_riemann(K, Lp, Rp, d, fr);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
+    }
+    const int a = i + G.n[0] * (j + G.n[1] * k);
+    const T rk = Wc[0] * (kF ? kF[a] : kF_s);
+    const T F[3] = {Ur.F[0][a], Ur.F[1][a], Ur.F[2][a]};
+    const T v[3] = {Wc[1], Wc[2], Wc[3]};
+    T S[5];
+    gas_source(K, rk, v, Ur.E[a], F, S);
+    T U0[5] = {Un.rho[a], Un.m[0][a], Un.m[1][a], Un.m[2][a], Un.E[a]};
+    T out[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q] = U0[q] - h * div[q] + h * S[q];
+    if (K.iso) out[4] = U0[4];
+    gas_floors(K, out, rf, pf);
+    Un.rho[a] = out[0];
+    Un.m[0][a] = out[1];
+    Un.m[1][a] = out[2];
+    Un.m[2][a] = out[3];
+    Un.E[a] = out[4];
+    sn0[a] = S[1];
+    sn1[a] = S[2];
+    sn2[a] = S[3];
+    sn3[a] = S[4];
+    wh0[a] = Wc[0];
+    wh1[a] = Wc[1];
+    wh2[a] = Wc[2];
+    wh3[a] = Wc[3];
+  }
+  wave_add(ctr + CTR_GAS_RHOFLOOR, rf ? 1ull : 0ull);
+  wave_add(ctr + CTR_GAS_PFLOOR, pf ? 1ull : 0ull);
+}
+
+// Second-order gas source correction: U += (dt/2)[S_e,gas(W_1/2, U_r^{n+1}) - s_n].
+template <typename T>
+__global__ void __launch_bounds__(256) k_gas_source_correct(GasPtrs<T> Ug, RadPtrs<T> Ur,
+                                                            const T* kF, T kF_s, GasConst<T> K,
+                                                            T half_dt, const T* sn0, const T* sn1,
+                                                            const T* sn2, const T* sn3,
+                                                            const T* wh0, const T* wh1,
+                                                            const T* wh2, const T* wh3, int N,
+                                                            unsigned long long* ctr) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  bool rf = false, pf = false;
+  if (a < N) {
+    const T rho_h = wh0[a];
+    const T v[3] = {wh1[a], wh2[a], wh3[a]};
+    const T F[3] = {Ur.F[0][a], Ur.F[1][a], Ur.F[2][a]};
+    T S[5];
+    gas_source(K, rho_h * (kF ? kF[a] : kF_s), v, Ur.E[a], F, S);
+    T U[5] = {Ug.rho[a], Ug.m[0][a], Ug.m[1][a], Ug.m[2][a], Ug.E[a]};
+    U[1] += half_dt * (S[1] - sn0[a]);
+    U[2] += half_dt * (S[2] - sn1[a]);
+    U[3] += half_dt * (S[3] - sn2[a]);
+    if (!K.iso) U[4] += half_dt * (S[4] - sn3[a]);
+    gas_floors(K, U, rf, pf);
+    Ug.rho[a] = U[0];
+    Ug.m[0][a] = U[1];
+    Ug.m[1][a] = U[2];
+    Ug.m[2][a] = U[3];
+    Ug.E[a] = U[4];
+  }
+  wave_add(ctr + CTR_GAS_RHOFLOOR, rf ? 1ull : 0ull);
+  wave_add(ctr + CTR_GAS_PFLOOR, pf ? 1ull : 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// implicit energy exchange (Sec. 3.4), FP64 whatever T is
+// ---------------------------------------------------------------------------
+
+struct ExchConst {
+  double c, chat, dt;
+  double gm1, a_rad, r_gas;
+  double theta, rtol;
+  int maxit;
+};
+
+__device__ __forceinline__ double quart(double c4, double c1, double c0, double x) {
+  const double x2 = x * x;
+  return c4 * x2 * x2 + c1 * x + c0;
+}
+
+__device__ __forceinline__ double newton(double c4, double c1, double c0, double x) {
+  const double x2 = x * x;
+  return x - (c4 * x2 * x2 + c1 * x + c0) / (4.0 * c4 * x2 * x + c1);
+}
+
+// theta-scheme update of (e, E_r) over dt with Ebar = e + (c/chat) E_r held fixed:
+// the new internal energy x solves c4 x^4 + c1 x + c0 = 0 (Eq. source:polynomial) with
+// its root in (0, min(-c0/c1, (-c0/c4)^{1/4})]. Newton starts at that upper bound
+// (f is increasing and convex, so the iterates fall monotonically onto the root),
+// stops at |dx| <= eps x and takes one more step; bisection with a final Newton step
+// takes over if it leaves the bracket or runs out of iterations. c0 > 0 (possible for
+// theta < 1) redoes the cell with theta = 1.
+__device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, double e,
+                                                double Er, double kP, double& Er_new, int& iters,
+                                                bool& th1, bool& bis) {
+  const double g = X.gm1 / (rho * X.r_gas);
+  const double g2 = g * g;
+  const double alpha = X.a_rad * g2 * g2;
+  const double eta = X.c * rho * kP * X.dt;
+  const double rc = X.chat / X.c;
+  const double Ebar = e + Er / rc;
+  double theta = X.theta;
+  th1 = false;
+  bis = false;
+  iters = 0;
+  const double e2 = e * e;
+  double c4 = alpha * eta * theta;
+  double c1 = 1.0 + rc * eta * theta;
+  double c0 = (1.0 - theta) * eta * (alpha * e2 * e2 - Er) - (e + rc * eta * theta * Ebar);
+  if (c0 > 0.0 && theta < 1.0) {
+    theta = 1.0;
+    th1 = true;
+    c4 = alpha * eta;
+    c1 = 1.0 + rc * eta;
+    c0 = -(e + rc * eta * Ebar);
+  }
+  double x;
+  if (c0 >= 0.0) {
+    x = 0.0;
+  } else if (c4 == 0.0) {
+    x = -c0 / c1;
+  } else {
+    const double u = fmin(-c0 / c1, sqrt(sqrt(-c0 / c4)));
+    x = u;
+    bool conv = false;
+    for (int it = 0; it < X.maxit; ++it) {
+      const double xn = newton(c4, c1, c0, x);
+      ++iters;
+      const double dx = x - xn;
+      x = xn;
+      if (!(x >= 0.0 && x <= u)) break;
+      if (fabs(dx) <= X.rtol * x) {
+        conv = true;
+        break;
+      }
+    }
+    if (conv) {
+      x = newton(c4, c1, c0, x);
+    } else {
+      bis = true;
+      double lo = 0.0, hi = u;
+      for (int b = 0; b < 200 && hi - lo > X.rtol * hi; ++b) {
+        const double mid = 0.5 * (lo + hi);
+        if (quart(c4, c1, c0, mid) < 0.0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      x = newton(c4, c1, c0, 0.5 * (lo + hi));
+    }
+  }
+  Er_new = rc * (Ebar - x);
+  return x;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_exchange(GasPtrs<T> Ug, RadPtrs<T> Ur, const T* kP,
+                                                  double kP_s, ExchConst X, int N,
+                                                  unsigned long long* ctr) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  int it = 0;
+  bool th1 = false, bis = false;
+  if (a < N) {
+    const double rho = double(Ug.rho[a]);
+    const double m0 = double(Ug.m[0][a]), m1 = double(Ug.m[1][a]), m2 = double(Ug.m[2][a]);
+    const double Et = double(Ug.E[a]);
+    const double ke = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+    const double e = Et - ke;
+    double Er_new;
+    const double x = exchange_root(X, rho, e, double(Ur.E[a]), kP ? double(kP[a]) : kP_s, Er_new,
+                                   it, th1, bis);
+    Ug.E[a] = T(Et + (x - e));
+    Ur.E[a] = T(Er_new);
+  }
+  wave_add(ctr + CTR_EXCH_THETA1, th1 ? 1ull : 0ull);
+  wave_add(ctr + CTR_EXCH_BISECT, bis ? 1ull : 0ull);
+  wave_add(ctr + CTR_NEWTON_ITERS, (unsigned long long)it);
+  wave_max(ctr + CTR_NEWTON_MAX, (unsigned long long)it);
+}
+
+// ---------------------------------------------------------------------------
+// reductions: FP64 ledger with non-finite check, and v_max for the CFL step
+// ---------------------------------------------------------------------------
+
+constexpr int RED_THREADS = 256;
+
+// Block b sums cells b, b + B, b + 2B, ... in a fixed order per thread and a fixed
+// tree over the block, so the result does not depend on scheduling.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_ledger(GasPtrs<T> Ug, RadPtrs<T> Ur,
+                                                        double c_over_chat, double inv_cchat,
+                                                        int N, double* partials,
+                                                        unsigned long long* ctr) {
+  __shared__ double sh[5][RED_THREADS];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  unsigned long long bad = 0;
+  unsigned long long first = ~0ull;
+  const int stride = int(gridDim.x * blockDim.x);
+  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride) {
+    const double rho = double(Ug.rho[a]);
+    const double m[3] = {double(Ug.m[0][a]), double(Ug.m[1][a]), double(Ug.m[2][a])};
+    const double E = double(Ug.E[a]);
+    const double Er = double(Ur.E[a]);
+    const double F[3] = {double(Ur.F[0][a]), double(Ur.F[1][a]), double(Ur.F[2][a])};
+    acc[0] += E + c_over_chat * Er;
+    acc[1] += m[0] + F[0] * inv_cchat;
+    acc[2] += m[1] + F[1] * inv_cchat;
+    acc[3] += m[2] + F[2] * inv_cchat;
+    acc[4] += rho;
+    const bool fin = isfinite(rho) && isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]) &&
+                     isfinite(E) && isfinite(Er) && isfinite(F[0]) && isfinite(F[1]) &&
+                     isfinite(F[2]);
+    if (!fin) {
+      ++bad;
+      if ((unsigned long long)a < first) first = (unsigned long long)a;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) partials[5 * blockIdx.x + q] = sh[q][0];
+  }
+  wave_add(ctr + CTR_NONFINITE, bad);
+  if (bad) atomicMin(ctr + CTR_FIRST_BAD, first);
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_ledger_final(const double* partials, int nblocks,
+                                                              double dV, double* out) {
+  __shared__ double sh[5][RED_THREADS];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = int(threadIdx.x); b < nblocks; b += RED_THREADS) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q] += partials[5 * b + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q] = sh[q][0] * dV;
+  }
+}
+
+struct CflConst {
+  double gamma, gm1, cs2;
+  double dxmin;
+  int iso;
+};
+
+// max over cells of |v| + c_eff, c_eff^2 = (gamma P + (4/9) E_r (1 - exp(-rho kF dx)))/rho
+// (Eq. algorithm:ceff). Computed in T; the maximum itself is exact.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_vmax(GasPtrs<T> Ug, RadPtrs<T> Ur, const T* kF,
+                                                      T kF_s, CflConst C, int N, T* partials) {
+  __shared__ T sh[RED_THREADS];
+  T best = T(0);
+  const int stride = int(gridDim.x * blockDim.x);
+  const T gamma = T(C.gamma), gm1 = T(C.gm1), cs2 = T(C.cs2), dxm = T(C.dxmin);
+  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride) {
+    const T rho = Ug.rho[a];
+    const T ir = T(1) / rho;
+    const T v0 = Ug.m[0][a] * ir, v1 = Ug.m[1][a] * ir, v2 = Ug.m[2][a] * ir;
+    const T v2s = v0 * v0 + v1 * v1 + v2 * v2;
+    const T gP = C.iso ? rho * cs2 : gamma * gm1 * (Ug.E[a] - T(0.5) * rho * v2s);
+    const T k = kF ? kF[a] : kF_s;
+    const T ceff = sqrt((gP + T(4.0 / 9.0) * Ur.E[a] * (T(1) - exp(-rho * k * dxm))) * ir);
+    const T s = sqrt(v2s) + ceff;
+    best = s > best ? s : best;
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) sh[threadIdx.x] = tmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_vmax_final(const T* partials, int nblocks,
+                                                            double* out) {
+  __shared__ T sh[RED_THREADS];
+  T best = T(0);
+  for (int b = int(threadIdx.x); b < nblocks; b += RED_THREADS) best = tmax(best, partials[b]);
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) sh[threadIdx.x] = tmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = double(sh[0]);
+}
+
+// ---------------------------------------------------------------------------
+// conversions between the caller's FP64 arrays and the stored type
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_from_f64(const double* __restrict__ src, T* __restrict__ dst,
+                                                  int n) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a < n) dst[a] = T(src[a]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_to_f64(const T* __restrict__ src, double* __restrict__ dst,
+                                                int n) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a < n) dst[a] = double(src[a]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(T* dst, T value, int n) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a < n) dst[a] = value;
+}
+
+__global__ void k_reset_counters(unsigned long long* ctr) {
+  const int q = int(threadIdx.x);
+  if (q < CTR_COUNT) ctr[q] = q == CTR_FIRST_BAD ? ~0ull : 0ull;
+}
+
+}  // namespace rhdk

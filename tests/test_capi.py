@@ -1,0 +1,81 @@
+"""Host-side checks of the C interface (no GPU needed): the library loads, exports
+every function include/rhd.h declares, fills defaults, sizes its footprint and
+rejects invalid parameters before touching a device."""
+import os
+import re
+
+import pytest
+
+import paper_1306_0010_amd as P
+import rhd_inputs as ri
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rhd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rhd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(P.EXPORTED) == names
+
+
+def test_default_params():
+    p = P.rhd_default_params(16, 8, 1)
+    assert (p.nx, p.ny, p.nz) == (16, 8, 1)
+    assert p.dx == pytest.approx(1 / 16) and p.dy == pytest.approx(1 / 8)
+    assert p.cfl == 0.4 and p.theta_E == 1.0 and p.theta_F == 0.51
+    assert p.newton_rtol == 1e-10 and p.newton_maxit == 50
+    assert list(p.bc) == [0] * 6 and p.flags == P.RHD_EXCHANGE_FULL
+
+
+def test_footprint_scales_with_precision_and_mode():
+    spec = ri.default_spec(nx=64, ny=64, nz=64, dx=1 / 64, dy=1 / 64, dz=1 / 64)
+    full64 = P.rhd_footprint_bytes(P.params_from_spec(spec))
+    full32 = P.rhd_footprint_bytes(P.params_from_spec(dict(spec, precision="mixed")))
+    rad32 = P.rhd_footprint_bytes(P.params_from_spec(dict(spec, precision="mixed", rad_only=True)))
+    N, NP = 64 ** 3, 68 ** 3
+    assert full64 > full32 > rad32
+    assert rad32 >= 4 * (9 * N + 4 * NP) and rad32 < 4 * (9 * N + 4 * NP) + 8 * N + 200000
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("cfl", 0.0), ("cfl", 1.5), ("theta_F", 0.4), ("theta_E", 1.2),
+    ("newton_rtol", 0.0), ("newton_maxit", -1), ("gamma", 1.0), ("c_light", 0.0), ("dx", 0.0),
+    ("rho_floor", -1.0)])
+def test_invalid_params_rejected_before_device(field, value):
+    spec = ri.default_spec(nx=8, ny=8, nz=1, dx=0.125, dy=0.125)
+    p = P.params_from_spec(spec)
+    setattr(p, field, value)
+    with pytest.raises(P.RhdError) as e:
+        P.rhd_create(p)
+    assert e.value.code == P.RHD_EINVAL
+    assert P.rhd_last_error(None)
+
+
+def test_invalid_boundaries_rejected():
+    spec = ri.default_spec(nx=8, ny=2, nz=1, dx=0.125, dy=0.5,
+                           bc=("periodic", "outflow", "periodic", "periodic", "periodic", "periodic"))
+    with pytest.raises(P.RhdError) as e:
+        P.rhd_create(P.params_from_spec(spec))
+    assert e.value.code == P.RHD_EINVAL and "pairs" in str(e.value)
+    spec = ri.default_spec(nx=8, ny=2, nz=1, dx=0.125, dy=0.5,
+                           bc=("outflow", "outflow", "reflect", "reflect", "periodic", "periodic"))
+    with pytest.raises(P.RhdError) as e:
+        P.rhd_create(P.params_from_spec(spec))
+    assert e.value.code == P.RHD_EINVAL and "3 cells" in str(e.value)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(P.RhdError) as e:
+        P.rhd_default_params(4, 4, 4)
+    assert "missing" in str(e.value)
