@@ -193,6 +193,17 @@ int rhd_set_timing(rhd_t* h, int enable);
 /* Totals since timing was started. Synchronises. */
 int rhd_get_timing(rhd_t* h, rhd_timing* out);
 
+/* Kernel variants of the radiation subcycle (rhd_set_kernel_variant). */
+#define RHD_KERNELS_PER_CELL  0   /* one thread per cell, every face flux evaluated twice     */
+#define RHD_KERNELS_TILED     1   /* x-y tiles in LDS marching along z, every face flux once;
+                                     3D grids only (other grids use the per-cell kernels)   */
+
+/* Select the kernels of the radiation subcycle: variant RHD_KERNELS_*, tile_rows the
+   rows of a 64-wide tile (4, 8 or 16; FP64 handles 4 or 8), zchunk the z-planes one tile
+   walks (>= 1). Defaults after rhd_create: tiled, 8 rows, 16 planes. Results do not
+   depend on the choice beyond rounding. RHD_EINVAL for values outside these sets. */
+int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk);
+
 /* Device bytes the handle holds (state, opacities, emission and scratch). */
 long long rhd_device_bytes(const rhd_t* h);
 

@@ -35,12 +35,14 @@ RHD_EXCHANGE_NONE = 2 << 1
 RHD_BETA_TAU = 1 << 3
 RHD_RAD_ONLY = 1 << 4
 RHD_PRECISION_MIXED = 1 << 5
+RHD_KERNELS_PER_CELL = 0
+RHD_KERNELS_TILED = 1
 
 EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_device",
             "rhd_set_emission", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
             "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics", "rhd_sync",
             "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
-            "rhd_set_timing", "rhd_get_timing")
+            "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant")
 
 
 class RhdError(RuntimeError):
@@ -128,13 +130,14 @@ def lib():
     L.rhd_destroy.argtypes = [vp]
     L.rhd_destroy.restype = None
     L.rhd_set_timing.argtypes = [vp, ctypes.c_int]
+    L.rhd_set_kernel_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.rhd_get_timing.argtypes = [vp, ctypes.POINTER(rhd_timing)]
     L.rhd_last_error.argtypes = [vp]
     L.rhd_last_error.restype = ctypes.c_char_p
     for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
                  "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
                  "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
-                 "rhd_sync", "rhd_set_timing", "rhd_get_timing"):
+                 "rhd_sync", "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -240,6 +243,10 @@ def rhd_get_timing(h):
     return t.as_dict()
 
 
+def rhd_set_kernel_variant(h, variant, tile_rows=8, zchunk=16):
+    _check(lib().rhd_set_kernel_variant(h, int(variant), int(tile_rows), int(zchunk)), h)
+
+
 def rhd_device_bytes(h):
     return int(lib().rhd_device_bytes(h))
 
@@ -332,6 +339,9 @@ class Solver:
 
     def step(self, dt_gas, chat, nsub):
         rhd_step(self.h, dt_gas, chat, nsub)
+
+    def set_kernel_variant(self, variant, tile_rows=8, zchunk=16):
+        rhd_set_kernel_variant(self.h, variant, tile_rows, zchunk)
 
     def suggest_dt(self, chat):
         return rhd_suggest_dt(self.h, chat)

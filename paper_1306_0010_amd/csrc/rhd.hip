@@ -7,6 +7,7 @@
 //   -> nsub x [radiation predictor -> radiation corrector]
 //   -> gas source correction -> FP64 ledger with non-finite check.
 #include "rhd_device.hpp"
+#include "rhd_tile.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -92,6 +93,9 @@ struct rhd {
   long long steps = 0, subcycles = 0;
   double vmax_last = 0.0;
   long long bytes = 0;
+  int variant = RHD_KERNELS_TILED;
+  int tile_rows = 8;
+  int zchunk = 16;
   Timer timer;
   char err[512] = "no error";
 };
@@ -301,6 +305,47 @@ int enqueue_ledger(rhd_t* h, double chat) {
   return RHD_OK;
 }
 
+// One radiation subcycle with the tiled kernels (3D grids).
+template <typename T, int BY>
+void launch_tiled_rows(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasView<T> view,
+                       const rhdk::RadConst<T>& RK, T h_pred, T h_corr) {
+  const rhdk::Geom& G = h->G;
+  constexpr int TX = rhdk::TILE_BX - 2, TY = BY - 2;
+  const int zc = h->zchunk;
+  const dim3 block(rhdk::TILE_BX, BY, 1);
+  const dim3 gp((G.n[0] + 4 + TX - 1) / TX, (G.n[1] + 4 + TY - 1) / TY, (G.n[2] + 4 + zc - 1) / zc);
+  const dim3 gc((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, (G.n[2] + zc - 1) / zc);
+  int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
+  hipLaunchKernelGGL((rhdk::k_rad_predict_tile<T, BY>), gp, block, 0, h->stream, rad, rh, view, G,
+                     RK, h_pred, zc);
+  tend(h, ti);
+  ti = tbegin(h, KC_RAD_CORRECT, h->N);
+  hipLaunchKernelGGL((rhdk::k_rad_correct_tile<T, BY>), gc, block, 0, h->stream, rad, rh, view, G,
+                     RK, h_corr, zc, h->b.ctr);
+  tend(h, ti);
+}
+
+template <typename T>
+int launch_tiled(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasView<T> view,
+                 const rhdk::RadConst<T>& RK, T h_pred, T h_corr) {
+  switch (h->tile_rows) {
+    case 4:
+      launch_tiled_rows<T, 4>(h, rad, rh, view, RK, h_pred, h_corr);
+      break;
+    case 8:
+      launch_tiled_rows<T, 8>(h, rad, rh, view, RK, h_pred, h_corr);
+      break;
+    default:
+      if constexpr (sizeof(T) == 4) {
+        launch_tiled_rows<T, 16>(h, rad, rh, view, RK, h_pred, h_corr);
+      } else {
+        return fail(h, RHD_EINVAL, "tile rows %d not available in FP64", h->tile_rows);
+      }
+  }
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
+
 template <typename T>
 int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
   const rhd_params& p = h->p;
@@ -380,10 +425,17 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
     auto view = gas_view<T>(h);
     auto rh = rad_ptrs<T>(h->b.rh);
     const double hr = dt / nsub;
+    const bool three_d = G.act[0] && G.act[1] && G.act[2];
+    if (three_d && h->variant == RHD_KERNELS_TILED) {
+      for (int m = 0; m < nsub; ++m) {
+        int rc = launch_tiled<T>(h, rad, rh, view, RK, T(0.5 * hr), T(hr));
+        if (rc) return rc;
+      }
+    }
     dim3 gp, bp, gc, bc;
     region_launch(G.ps, gp, bp);
     region_launch(G.n, gc, bc);
-    for (int m = 0; m < nsub; ++m) {
+    for (int m = 0; m < nsub && !(three_d && h->variant == RHD_KERNELS_TILED); ++m) {
       int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
       hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK,
                          T(0.5 * hr));
@@ -835,6 +887,19 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out) {
     out->total_ms[k] = h->timer.ms[k];
     out->cells[k] = h->timer.cells[k];
   }
+  return RHD_OK;
+}
+
+int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (variant != RHD_KERNELS_PER_CELL && variant != RHD_KERNELS_TILED)
+    return fail(h, RHD_EINVAL, "unknown kernel variant %d", variant);
+  const bool rows_ok = tile_rows == 4 || tile_rows == 8 || (tile_rows == 16 && h->mixed);
+  if (!rows_ok) return fail(h, RHD_EINVAL, "tile rows must be 4, 8 (or 16 in mixed precision)");
+  if (zchunk < 1) return fail(h, RHD_EINVAL, "zchunk must be >= 1");
+  h->variant = variant;
+  h->tile_rows = tile_rows;
+  h->zchunk = zchunk;
   return RHD_OK;
 }
 

@@ -168,65 +168,123 @@ __device__ __forceinline__ void wave_max(unsigned long long* ctr, unsigned long 
 // M1 closure, eigenvalues and HLL flux (Sec. 2.3, Sec. 3.3)
 // ---------------------------------------------------------------------------
 
-// Physical flux of (E_r, F) normal to d and the extreme M1 wave speeds.
+// Reciprocal and square roots: the hardware approximations (about 1 ulp) in FP32,
+// correctly rounded operations in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+
+// Direction-independent part of the M1 closure of one state (E_r, F).
 //
-// With the reduced flux f = F/(c E) (its norm clamped to 1) and s = sqrt(4 - 3 f^2),
-// the Eddington factor of Eq. m1:chi equals (5 - 2 s)/3, so the tensor of Eq. m1:m1tns
-// is T = (s - 1)/3 I + 3 f f / (2 + s): no division by |F| and no special case at F = 0.
-// For the eigenvalues of Eq. hyperbolic:evals13, mu f = f_d and the radicand
-//   (2/3)(4 - 3f^2 - s) + 2 mu^2 (2 - f^2 - s)
-// equals (2/3) s (s - 1) - 2 f_d^2 (1 - f^2) / (2 - f^2 + s), again free of 1/|F|.
+// With the reduced flux f = F/(c E) (norm clamped to 1) and s = sqrt(4 - 3 f^2), the
+// Eddington factor of Eq. m1:chi equals (5 - 2 s)/3, so the tensor of Eq. m1:m1tns is
+//   T = (s - 1)/3 I + 3 f f / (2 + s),
+// with no division by |F| and no special case at F = 0. One reciprocal of s (2 + s)
+// gives both 1/s (for the wave speeds) and 3/(2 + s).
 template <typename T>
-__device__ __forceinline__ void m1_flux_speeds(const T U[4], int d, T c, T inv_c, T chat,
-                                               T Phi[4], T& lmin, T& lmax) {
-  const T E = U[0];
-  const T icE = inv_c / E;
-  T f0 = U[1] * icE, f1 = U[2] * icE, f2v = U[3] * icE;
-  T ff = f0 * f0 + f1 * f1 + f2v * f2v;
+struct M1State {
+  T E, F[3];     // the state
+  T f[3];        // reduced flux after the clamp
+  T s;           // sqrt(4 - 3 f^2)
+  T iso;         // (s - 1)/3, the isotropic part of T
+  T dir;         // 3/(2 + s), the f f part of T
+  T chat_s;      // chat / s
+};
+
+template <typename T>
+__device__ __forceinline__ M1State<T> m1_state(const T U[4], T inv_c, T chat) {
+  M1State<T> m;
+  m.E = U[0];
+  m.F[0] = U[1];
+  m.F[1] = U[2];
+  m.F[2] = U[3];
+  const T icE = inv_c * rcp(U[0]);
+  m.f[0] = U[1] * icE;
+  m.f[1] = U[2] * icE;
+  m.f[2] = U[3] * icE;
+  T ff = m.f[0] * m.f[0] + m.f[1] * m.f[1] + m.f[2] * m.f[2];
   if (ff > T(1)) {
-    T r = T(1) / sqrt(ff);
-    f0 *= r;
-    f1 *= r;
-    f2v *= r;
+    const T r = rsqrt_(ff);
+    m.f[0] *= r;
+    m.f[1] *= r;
+    m.f[2] *= r;
     ff = T(1);
   }
-  const T s = sqrt(T(4) - T(3) * ff);
-  const T iso = (s - T(1)) * T(1.0 / 3.0);
-  const T dir = T(3) / (T(2) + s);
-  const T fd = d == 0 ? f0 : (d == 1 ? f1 : f2v);
-  const T scale = chat * c * E;
-  Phi[0] = chat * U[1 + d] * inv_c;
-  Phi[1] = scale * (dir * fd * f0 + (d == 0 ? iso : T(0)));
-  Phi[2] = scale * (dir * fd * f1 + (d == 1 ? iso : T(0)));
-  Phi[3] = scale * (dir * fd * f2v + (d == 2 ? iso : T(0)));
-  T rad = T(2.0 / 3.0) * s * (s - T(1)) - T(2) * fd * fd * (T(1) - ff) / (T(2) - ff + s);
-  rad = tmax(rad, T(0));
-  const T r = sqrt(rad);
-  const T is = chat / s;
-  lmin = (fd - r) * is;
-  lmax = (fd + r) * is;
+  m.s = sqrt_(T(4) - T(3) * ff);
+  const T two_s = T(2) + m.s;
+  const T r2 = rcp(m.s * two_s);
+  m.dir = T(3) * m.s * r2;
+  m.chat_s = chat * two_s * r2;
+  m.iso = (m.s - T(1)) * T(1.0 / 3.0);
+  return m;
 }
 
-// HLL flux of Eq. hyperbolic:hllflux2 with S_L, S_R from the M1 eigenvalues of both
-// states; the central flux when both bounds vanish.
+// Physical flux normal to d (chat F_d / c, chat c P_d.) and the extreme wave speeds of
+// Eq. hyperbolic:evals13. With mu f = f_d, the radicand
+//   (2/3)(4 - 3 f^2 - s) + 2 mu^2 (2 - f^2 - s)
+// equals (2/3)(s - 1)(s - 3 f_d^2 / (2 + s)), which is free of 1/|F| and carries the
+// factor (s - 1) that vanishes at f = 1 explicitly.
+template <typename T>
+__device__ __forceinline__ void m1_dir(const M1State<T>& m, int d, T c, T inv_c, T chat,
+                                       T Phi[4], T& lmin, T& lmax) {
+  const T fd = d == 0 ? m.f[0] : (d == 1 ? m.f[1] : m.f[2]);
+  const T scale = chat * c * m.E;
+  const T a = m.dir * fd;
+  Phi[0] = chat * m.F[d] * inv_c;
+  Phi[1] = scale * (a * m.f[0] + (d == 0 ? m.iso : T(0)));
+  Phi[2] = scale * (a * m.f[1] + (d == 1 ? m.iso : T(0)));
+  Phi[3] = scale * (a * m.f[2] + (d == 2 ? m.iso : T(0)));
+  T rad = T(2.0 / 3.0) * (m.s - T(1)) * (m.s - a * fd);
+  rad = tmax(rad, T(0));
+  const T r = sqrt_(rad);
+  lmin = (fd - r) * m.chat_s;
+  lmax = (fd + r) * m.chat_s;
+}
+
+// Closure data of one state for the faces normal to d: the state, its physical flux and
+// its extreme wave speeds.
+template <typename T>
+struct FaceSide {
+  T U[4];
+  T Phi[4];
+  T lmin, lmax;
+};
+
+template <typename T>
+__device__ __forceinline__ FaceSide<T> face_side(const T U[4], int d, T c, T inv_c, T chat) {
+  FaceSide<T> q;
+  const M1State<T> m = m1_state(U, inv_c, chat);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q.U[k] = U[k];
+  m1_dir(m, d, c, inv_c, chat, q.Phi, q.lmin, q.lmax);
+  return q;
+}
+
+// HLL flux of Eq. hyperbolic:hllflux2 with S_L = min(lambda_1(U_L), lambda_1(U_R)) and
+// S_R = max(lambda_3(U_L), lambda_3(U_R)); the central flux when both bounds vanish.
+template <typename T>
+__device__ __forceinline__ void hll(const FaceSide<T>& L, const FaceSide<T>& R, T flux[4]) {
+  const T SLm = tmin(tmin(L.lmin, R.lmin), T(0));
+  const T SRp = tmax(tmax(L.lmax, R.lmax), T(0));
+  const T den = SRp - SLm;
+  if (den > T(0)) {
+    const T id = rcp(den);
+    const T pr = SRp * SLm;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) flux[q] = (SRp * L.Phi[q] - SLm * R.Phi[q] + pr * (R.U[q] - L.U[q])) * id;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) flux[q] = T(0.5) * (L.Phi[q] + R.Phi[q]);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void rad_hll(const T UL[4], const T UR[4], int d, T c, T inv_c,
                                         T chat, T flux[4]) {
-  T PL[4], PR[4], l1L, l3L, l1R, l3R;
-  m1_flux_speeds(UL, d, c, inv_c, chat, PL, l1L, l3L);
-  m1_flux_speeds(UR, d, c, inv_c, chat, PR, l1R, l3R);
-  const T SLm = tmin(tmin(l1L, l1R), T(0));
-  const T SRp = tmax(tmax(l3L, l3R), T(0));
-  const T den = SRp - SLm;
-  if (den > T(0)) {
-    const T id = T(1) / den;
-    const T pr = SRp * SLm;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) flux[q] = (SRp * PL[q] - SLm * PR[q] + pr * (UR[q] - UL[q])) * id;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) flux[q] = T(0.5) * (PL[q] + PR[q]);
-  }
+  hll(face_side(UL, d, c, inv_c, chat), face_side(UR, d, c, inv_c, chat), flux);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,13 +334,13 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
   T En;
   if (K.absorb) {
     const T aP = chat * fz.rkP * h;
-    En = (Uo[0] * (T(1) - (T(1) - th) * aP) + h * (-div[0] + srcE)) / (T(1) + th * aP);
+    En = (Uo[0] * (T(1) - (T(1) - th) * aP) + h * (-div[0] + srcE)) * rcp(T(1) + th * aP);
   } else {
     En = Uo[0] + h * (-div[0] + srcE);
   }
   const T a = chat * fz.rkF * h;
   const T keep = T(1) - (T(1) - th) * a;
-  const T inv = T(1) / (T(1) + th * a);
+  const T inv = rcp(T(1) + th * a);
   const T adv = b * T(4.0 / 3.0) * chat * fz.rkF * Us[0];
   T Fn[3];
 #pragma unroll
@@ -296,7 +354,7 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
   const T cE = K.c * En;
   const T Fm2 = Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2];
   if (Fm2 > cE * cE) {
-    const T scale = cE / sqrt(Fm2);
+    const T scale = cE * rsqrt_(Fm2);
     Fn[0] *= scale;
     Fn[1] *= scale;
     Fn[2] *= scale;
@@ -330,16 +388,21 @@ __global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> U
   if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
   T U0[4];
   load_rad_mapped(Um, G, i, j, k, U0);
+  const M1State<T> m0 = m1_state(U0, K.inv_c, K.chat);
   T div[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (!G.act[d]) continue;
     const int di = d == 0, dj = d == 1, dk = d == 2;
+    FaceSide<T> own;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) own.U[q] = U0[q];
+    m1_dir(m0, d, K.c, K.inv_c, K.chat, own.Phi, own.lmin, own.lmax);
     T Ul[4], Ur[4], fl[4], fr[4];
     load_rad_mapped(Um, G, i - di, j - dj, k - dk, Ul);
     load_rad_mapped(Um, G, i + di, j + dj, k + dk, Ur);
-    rad_hll(Ul, U0, d, K.c, K.inv_c, K.chat, fl);
-    rad_hll(U0, Ur, d, K.c, K.inv_c, K.chat, fr);
+    hll(face_side(Ul, d, K.c, K.inv_c, K.chat), own, fl);
+    hll(own, face_side(Ur, d, K.c, K.inv_c, K.chat), fr);
 #pragma unroll
     for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
   }

@@ -29,10 +29,12 @@ def announce(name):
     sys.stdout.flush()
 
 
-def run_gpu(spec, st, steps, chat, dt=None, nsub=None):
-    """Run ``steps`` gas steps on the GPU; dt/nsub None means the oracle's CFL step of
-    the initial state (so both sides take identical steps)."""
+def run_gpu(spec, st, steps, chat, dt=None, nsub=None, variant=None):
+    """Run ``steps`` gas steps on the GPU with the given (dt, nsub). ``variant`` is
+    (kernel variant, tile rows, z chunk) or None for the library's default."""
     with P.Solver(spec) as s:
+        if variant is not None:
+            s.set_kernel_variant(*variant)
         s.set_state(st)
         for _ in range(steps):
             s.step(dt, chat, nsub)
@@ -116,14 +118,18 @@ def two_d_reflect(precision):
     return spec, st, 5.0, 3
 
 
+VARIANTS = {"per_cell": (P.RHD_KERNELS_PER_CELL, 8, 16), "tiled": (P.RHD_KERNELS_TILED, 8, 16)}
+
+
+@pytest.mark.parametrize("variant", ["per_cell", "tiled"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_step_matches_oracle(name, precision):
-    announce(f"{name} {precision}")
+def test_step_matches_oracle(name, precision, variant):
+    announce(f"{name} {precision} {variant}")
     spec, st, chat, steps = CASES[name](precision)
     dt, ns = step_sizes(spec, st, chat)
     ref, cnt = oracle.step(spec, st, dt, chat, ns, steps=steps)
-    gpu, diag = run_gpu(spec, st, steps, chat, dt, ns)
+    gpu, diag = run_gpu(spec, st, steps, chat, dt, ns, VARIANTS[variant])
     assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"{name} {precision}")
     assert diag["nonfinite"] == 0 and diag["steps"] == steps and diag["subcycles"] == steps * ns
     if precision == "fp64":
@@ -131,6 +137,18 @@ def test_step_matches_oracle(name, precision):
         for k in ("exch_theta1", "exch_bisect", "gas_rhofloor", "gas_pfloor", "rad_efloor"):
             assert diag[k] == cnt[k], (k, diag[k], cnt[k])
         assert abs(diag["newton_iters"] - cnt["newton_iters"]) <= 1e-3 * max(1, cnt["newton_iters"])
+
+
+@pytest.mark.parametrize("rows,zchunk,precision", [(4, 16, "fp64"), (8, 3, "fp64"), (4, 7, "mixed"),
+                                                   (8, 16, "mixed"), (16, 16, "mixed"), (16, 1, "mixed")])
+def test_tile_shapes_agree_with_per_cell_kernels(rows, zchunk, precision):
+    """Every tile shape gives the per-cell kernels' result to rounding."""
+    announce(f"tile shape {rows} {zchunk} {precision}")
+    spec, st, chat, steps = rhd3d_mixed_bc_beta_tau(precision)
+    dt, ns = step_sizes(spec, st, chat)
+    a, _ = run_gpu(spec, st, 2, chat, dt, ns, (P.RHD_KERNELS_PER_CELL, 8, 16))
+    b, _ = run_gpu(spec, st, 2, chat, dt, ns, (P.RHD_KERNELS_TILED, rows, zchunk))
+    assert_parity(spec, b, a, 1e-13 if precision == "fp64" else 2e-6, "max", label="tile vs per-cell")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
