@@ -204,6 +204,60 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
    depend on the choice beyond rounding. RHD_EINVAL for values outside these sets. */
 int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk);
 
+/* Pick the fastest radiation-subcycle kernels for this handle's grid by timing them:
+   every variant and tile shape (tile rows x z chunk) runs `reps` subcycles of dt_rad on
+   the current state with HIP events, and the fastest becomes the handle's choice (see
+   rhd_set_kernel_variant). The state is copied aside first and restored afterwards, so
+   it is unchanged bit for bit. This call allocates a temporary copy of the radiation
+   fields and synchronises; the choice is also remembered for later handles of the same
+   grid shape and precision in this process. RHD_ECFL if chat dt_rad > K0 dx. */
+int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, int* tile_rows,
+                 int* zchunk);
+
+/* ---- many independent solves advanced together (served form) ------------------------- */
+
+typedef struct rhd_batch rhd_batch_t;
+
+/* Create a batch that advances up to max_solves independent 3D handles together: every
+   radiation Van Leer stage of all members goes out as one launch over a packed list of
+   tiles (64 x tile_rows cells, zchunk planes; tile_rows 4, 8 or 16 in mixed precision,
+   4 or 8 in FP64). hip_stream is a hipStream_t or NULL for an owned stream. */
+int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk,
+                     rhd_batch_t** out);
+
+/* Add a handle and the reduced speed of light it runs with. The handle must hold a state,
+   be 3D, have the precision of the batch (the first member fixes it) and belong to no
+   other batch; RHD_EINVAL otherwise, or when the batch is full. While it is a member its
+   work runs on the batch's stream; on the handle itself only rhd_get_state,
+   rhd_get_diagnostics, rhd_ledger and rhd_sync may be called (they wait for that stream).
+   Grows the batch's tile lists (device allocation). */
+int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat);
+
+/* Remove a member: waits for the batch's stream and gives the handle its own stream back. */
+int rhd_batch_remove(rhd_batch_t* b, rhd_t* h);
+
+/* Advance every member by one gas step with its own CFL step and subcycle count
+   (Sec. 3.1, Eqs. algorithm:gastimestep and algorithm:radtimestep): one synchronisation
+   reads all v_max values; the exchange and gas step of each member follow; then the
+   radiation subcycles of all members run as rounds of batched launches, round r covering
+   the members with nsub > r; each member's correction and ledger close the step. A
+   member's result is bit for bit the one rhd_step with the tiled kernels gives it alone.
+   nsub_out and dt_out (each NULL or room for rhd_batch_size() values, member order)
+   receive each member's nsub and dt_gas. Allocates nothing. */
+int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out);
+
+/* Number of members. */
+int rhd_batch_size(const rhd_batch_t* b);
+
+/* Wait for the batch's stream. */
+int rhd_batch_sync(rhd_batch_t* b);
+
+/* Destroy the batch; members get their own streams back (they are not destroyed). */
+void rhd_batch_destroy(rhd_batch_t* b);
+
+/* Message of the last failure of a batch call (b may be NULL for rhd_batch_create). */
+const char* rhd_batch_last_error(const rhd_batch_t* b);
+
 /* Device bytes the handle holds (state, opacities, emission and scratch). */
 long long rhd_device_bytes(const rhd_t* h);
 

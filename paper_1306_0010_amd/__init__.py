@@ -42,7 +42,9 @@ EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_
             "rhd_set_emission", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
             "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics", "rhd_sync",
             "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
-            "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant")
+            "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant", "rhd_autotune",
+            "rhd_batch_create", "rhd_batch_add", "rhd_batch_remove", "rhd_batch_step",
+            "rhd_batch_size", "rhd_batch_sync", "rhd_batch_destroy", "rhd_batch_last_error")
 
 
 class RhdError(RuntimeError):
@@ -131,13 +133,27 @@ def lib():
     L.rhd_destroy.restype = None
     L.rhd_set_timing.argtypes = [vp, ctypes.c_int]
     L.rhd_set_kernel_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.rhd_autotune.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ip, ip, ip]
     L.rhd_get_timing.argtypes = [vp, ctypes.POINTER(rhd_timing)]
     L.rhd_last_error.argtypes = [vp]
     L.rhd_last_error.restype = ctypes.c_char_p
+    L.rhd_batch_create.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.rhd_batch_add.argtypes = [vp, vp, ctypes.c_double]
+    L.rhd_batch_remove.argtypes = [vp, vp]
+    L.rhd_batch_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.rhd_batch_size.argtypes = [vp]
+    L.rhd_batch_sync.argtypes = [vp]
+    L.rhd_batch_destroy.argtypes = [vp]
+    L.rhd_batch_destroy.restype = None
+    L.rhd_batch_last_error.argtypes = [vp]
+    L.rhd_batch_last_error.restype = ctypes.c_char_p
     for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
                  "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
                  "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
-                 "rhd_sync", "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant"):
+                 "rhd_sync", "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant",
+                 "rhd_autotune", "rhd_batch_create", "rhd_batch_add", "rhd_batch_remove",
+                 "rhd_batch_step", "rhd_batch_size", "rhd_batch_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -247,6 +263,60 @@ def rhd_set_kernel_variant(h, variant, tile_rows=8, zchunk=16):
     _check(lib().rhd_set_kernel_variant(h, int(variant), int(tile_rows), int(zchunk)), h)
 
 
+def rhd_autotune(h, chat, dt_rad, reps=3):
+    """Returns (variant, tile_rows, zchunk) chosen for the handle."""
+    v, r, z = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().rhd_autotune(h, float(chat), float(dt_rad), int(reps), ctypes.byref(v),
+                              ctypes.byref(r), ctypes.byref(z)), h)
+    return v.value, r.value, z.value
+
+
+def _bcheck(rc, b=None):
+    if rc != RHD_OK:
+        raise RhdError(rc, lib().rhd_batch_last_error(b).decode(errors="replace"))
+
+
+def rhd_batch_create(max_solves, tile_rows=8, zchunk=16, stream=None):
+    b = ctypes.c_void_p()
+    _bcheck(lib().rhd_batch_create(ctypes.c_void_p(stream) if stream else None, int(max_solves),
+                                   int(tile_rows), int(zchunk), ctypes.byref(b)))
+    return b.value
+
+
+def rhd_batch_add(b, h, chat):
+    _bcheck(lib().rhd_batch_add(b, h, float(chat)), b)
+
+
+def rhd_batch_remove(b, h):
+    _bcheck(lib().rhd_batch_remove(b, h), b)
+
+
+def rhd_batch_step(b):
+    """One gas step of every member; returns (nsub list, dt list) in member order."""
+    n = lib().rhd_batch_size(b)
+    ns = (ctypes.c_int * max(n, 1))()
+    dt = (ctypes.c_double * max(n, 1))()
+    _bcheck(lib().rhd_batch_step(b, ns, dt), b)
+    return list(ns)[:n], list(dt)[:n]
+
+
+def rhd_batch_size(b):
+    return int(lib().rhd_batch_size(b))
+
+
+def rhd_batch_sync(b):
+    _bcheck(lib().rhd_batch_sync(b), b)
+
+
+def rhd_batch_destroy(b):
+    if b:
+        lib().rhd_batch_destroy(b)
+
+
+def rhd_batch_last_error(b=None):
+    return lib().rhd_batch_last_error(b).decode(errors="replace")
+
+
 def rhd_device_bytes(h):
     return int(lib().rhd_device_bytes(h))
 
@@ -342,6 +412,9 @@ class Solver:
 
     def set_kernel_variant(self, variant, tile_rows=8, zchunk=16):
         rhd_set_kernel_variant(self.h, variant, tile_rows, zchunk)
+
+    def autotune(self, chat, dt_rad, reps=3):
+        return rhd_autotune(self.h, chat, dt_rad, reps)
 
     def suggest_dt(self, chat):
         return rhd_suggest_dt(self.h, chat)

@@ -16,7 +16,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/rhd.h"
 
@@ -93,6 +95,7 @@ struct rhd {
   long long steps = 0, subcycles = 0;
   double vmax_last = 0.0;
   long long bytes = 0;
+  bool in_batch = false;
   int variant = RHD_KERNELS_TILED;
   int tile_rows = 8;
   int zchunk = 16;
@@ -101,6 +104,36 @@ struct rhd {
 };
 
 namespace {
+
+// Kernel choices found by rhd_autotune, shared by later handles of the same grid shape,
+// precision and flags in this process.
+struct TuneKey {
+  int n[3];
+  bool mixed;
+  unsigned flags;
+};
+
+struct TuneEntry {
+  TuneKey key;
+  int variant, rows, zchunk;
+};
+
+std::mutex g_tune_mutex;
+TuneEntry g_tuned[64];
+int g_ntuned = 0;
+
+bool same_key(const TuneKey& a, const TuneKey& b) {
+  return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.mixed == b.mixed &&
+         a.flags == b.flags;
+}
+
+TuneKey tune_key(const rhd_t* h) {
+  TuneKey k;
+  for (int d = 0; d < 3; ++d) k.n[d] = h->G.n[d];
+  k.mixed = h->mixed;
+  k.flags = h->p.flags;
+  return k;
+}
 
 int fail(rhd_t* h, int code, const char* fmt, ...) {
   char* dst = h ? h->err : g_create_error;
@@ -347,12 +380,84 @@ int launch_tiled(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasV
 }
 
 template <typename T>
-int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
+rhdk::RadConst<T> rad_const(const rhd_t* h, double chat) {
+  const rhd_params& p = h->p;
+  const rhdk::Geom& G = h->G;
+  rhdk::RadConst<T> RK;
+  RK.c = T(p.c_light);
+  RK.inv_c = T(1.0 / p.c_light);
+  RK.chat = T(chat);
+  RK.inv_w[0] = G.act[0] ? T(1.0 / p.dx) : T(0);
+  RK.inv_w[1] = G.act[1] ? T(1.0 / p.dy) : T(0);
+  RK.inv_w[2] = G.act[2] ? T(1.0 / p.dz) : T(0);
+  RK.theta = T(p.theta_F);
+  RK.er_floor = T(p.er_floor);
+  RK.beta = (p.flags & RHD_BETA_TAU) != 0;
+  RK.absorb = (p.flags & RHD_EXCHANGE_MASK) == RHD_EXCHANGE_ABSORB_ONLY;
+  return RK;
+}
+
+// nsub radiation Van Leer subcycles of dt/nsub with the gas frozen (Sec. 3.3, 3.4).
+template <typename T>
+int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
+  const rhdk::Geom& G = h->G;
+  const rhdk::RadConst<T> RK = rad_const<T>(h, chat);
+  auto rad = rad_ptrs<T>(h->b.rad);
+  auto rh = rad_ptrs<T>(h->b.rh);
+  auto view = gas_view<T>(h);
+  const double hr = dt / nsub;
+  const bool three_d = G.act[0] && G.act[1] && G.act[2];
+  if (three_d && h->variant == RHD_KERNELS_TILED) {
+    for (int m = 0; m < nsub; ++m) {
+      int rc = launch_tiled<T>(h, rad, rh, view, RK, T(0.5 * hr), T(hr));
+      if (rc) return rc;
+    }
+    return RHD_OK;
+  }
+  dim3 gp, bp, gc, bc;
+  region_launch(G.ps, gp, bp);
+  region_launch(G.n, gc, bc);
+  for (int m = 0; m < nsub; ++m) {
+    int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
+    hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK,
+                       T(0.5 * hr));
+    tend(h, ti);
+    ti = tbegin(h, KC_RAD_CORRECT, h->N);
+    hipLaunchKernelGGL(rhdk::k_rad_correct<T>, gc, bc, 0, h->stream, rad, rh, view, G, RK, T(hr),
+                       h->b.ctr);
+    tend(h, ti);
+  }
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
+
+template <typename T>
+rhdk::GasConst<T> gas_const(const rhd_t* h) {
+  const rhd_params& p = h->p;
+  const rhdk::Geom& G = h->G;
+  rhdk::GasConst<T> GK;
+  GK.c = T(p.c_light);
+  GK.inv_c = T(1.0 / p.c_light);
+  GK.inv_w[0] = G.act[0] ? T(1.0 / p.dx) : T(0);
+  GK.inv_w[1] = G.act[1] ? T(1.0 / p.dy) : T(0);
+  GK.inv_w[2] = G.act[2] ? T(1.0 / p.dz) : T(0);
+  GK.gamma = T(p.gamma);
+  GK.gm1 = T(p.gamma - 1.0);
+  GK.cs2 = T(p.iso_cs * p.iso_cs);
+  GK.rho_floor = T(p.rho_floor);
+  GK.p_floor = T(p.p_floor);
+  GK.beta = (p.flags & RHD_BETA_TAU) != 0;
+  GK.iso = (p.flags & RHD_ISOTHERMAL) != 0;
+  return GK;
+}
+
+// Steps 2-3 of a gas step (Sec. 3.1): the implicit exchange and the gas Van Leer step.
+template <typename T>
+int enqueue_pre(rhd_t* h, double dt, double chat) {
   const rhd_params& p = h->p;
   const unsigned mode = p.flags & RHD_EXCHANGE_MASK;
   const bool iso = (p.flags & RHD_ISOTHERMAL) != 0;
   const bool rad_only = (p.flags & RHD_RAD_ONLY) != 0;
-  const bool beta = (p.flags & RHD_BETA_TAU) != 0;
   const rhdk::Geom& G = h->G;
   auto gas = gas_ptrs<T>(h->b.gas);
   auto rad = rad_ptrs<T>(h->b.rad);
@@ -360,7 +465,7 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
   const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
   const int threads = 256;
 
-  // 1. implicit energy exchange over dt_gas (FP64)
+  // implicit energy exchange over dt_gas (FP64)
   if (mode == RHD_EXCHANGE_FULL && !iso) {
     rhdk::ExchConst X;
     X.c = p.c_light;
@@ -378,21 +483,9 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
     tend(h, ti);
   }
 
-  // 2. gas Van Leer step with S_e,gas at first order
-  rhdk::GasConst<T> GK;
-  GK.c = T(p.c_light);
-  GK.inv_c = T(1.0 / p.c_light);
-  GK.inv_w[0] = G.act[0] ? T(1.0 / p.dx) : T(0);
-  GK.inv_w[1] = G.act[1] ? T(1.0 / p.dy) : T(0);
-  GK.inv_w[2] = G.act[2] ? T(1.0 / p.dz) : T(0);
-  GK.gamma = T(p.gamma);
-  GK.gm1 = T(p.gamma - 1.0);
-  GK.cs2 = T(p.iso_cs * p.iso_cs);
-  GK.rho_floor = T(p.rho_floor);
-  GK.p_floor = T(p.p_floor);
-  GK.beta = beta;
-  GK.iso = iso;
+  // gas Van Leer step with S_e,gas at first order
   if (!rad_only) {
+    const rhdk::GasConst<T> GK = gas_const<T>(h);
     dim3 grid, block;
     region_launch(G.ps, grid, block);
     auto gh = gas_ptrs<T>(h->b.gh);
@@ -408,59 +501,36 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
                        as<T>(h->b.wh[2]), as<T>(h->b.wh[3]), h->b.ctr);
     tend(h, ti);
   }
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
 
-  // 3. radiation subcycles with the gas frozen
-  if (nsub > 0) {
-    rhdk::RadConst<T> RK;
-    RK.c = T(p.c_light);
-    RK.inv_c = T(1.0 / p.c_light);
-    RK.chat = T(chat);
-    RK.inv_w[0] = GK.inv_w[0];
-    RK.inv_w[1] = GK.inv_w[1];
-    RK.inv_w[2] = GK.inv_w[2];
-    RK.theta = T(p.theta_F);
-    RK.er_floor = T(p.er_floor);
-    RK.beta = beta;
-    RK.absorb = mode == RHD_EXCHANGE_ABSORB_ONLY;
-    auto view = gas_view<T>(h);
-    auto rh = rad_ptrs<T>(h->b.rh);
-    const double hr = dt / nsub;
-    const bool three_d = G.act[0] && G.act[1] && G.act[2];
-    if (three_d && h->variant == RHD_KERNELS_TILED) {
-      for (int m = 0; m < nsub; ++m) {
-        int rc = launch_tiled<T>(h, rad, rh, view, RK, T(0.5 * hr), T(hr));
-        if (rc) return rc;
-      }
-    }
-    dim3 gp, bp, gc, bc;
-    region_launch(G.ps, gp, bp);
-    region_launch(G.n, gc, bc);
-    for (int m = 0; m < nsub && !(three_d && h->variant == RHD_KERNELS_TILED); ++m) {
-      int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
-      hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK,
-                         T(0.5 * hr));
-      tend(h, ti);
-      ti = tbegin(h, KC_RAD_CORRECT, h->N);
-      hipLaunchKernelGGL(rhdk::k_rad_correct<T>, gc, bc, 0, h->stream, rad, rh, view, G, RK, T(hr),
-                         h->b.ctr);
-      tend(h, ti);
-    }
-  }
-
-  // 4. second-order correction of the gas sources
+// Steps 6 and the ledger: second-order gas source correction, then the FP64 ledger.
+template <typename T>
+int enqueue_post(rhd_t* h, double dt, double chat) {
+  const bool rad_only = (h->p.flags & RHD_RAD_ONLY) != 0;
   if (!rad_only) {
+    const rhdk::GasConst<T> GK = gas_const<T>(h);
+    const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+    const int threads = 256;
     const int ti = tbegin(h, KC_GAS_SOURCE, h->N);
     hipLaunchKernelGGL(rhdk::k_gas_source_correct<T>, dim3(blocks_for(h->N, threads)), dim3(threads),
-                       0, h->stream, gas, rad, kFp, T(h->kF_s), GK, T(0.5 * dt),
-                       as<T>(h->b.sn[0]), as<T>(h->b.sn[1]), as<T>(h->b.sn[2]), as<T>(h->b.sn[3]),
-                       as<T>(h->b.wh[0]), as<T>(h->b.wh[1]), as<T>(h->b.wh[2]), as<T>(h->b.wh[3]),
-                       h->N, h->b.ctr);
+                       0, h->stream, gas_ptrs<T>(h->b.gas), rad_ptrs<T>(h->b.rad), kFp,
+                       T(h->kF_s), GK, T(0.5 * dt), as<T>(h->b.sn[0]), as<T>(h->b.sn[1]),
+                       as<T>(h->b.sn[2]), as<T>(h->b.sn[3]), as<T>(h->b.wh[0]), as<T>(h->b.wh[1]),
+                       as<T>(h->b.wh[2]), as<T>(h->b.wh[3]), h->N, h->b.ctr);
     tend(h, ti);
+    HIP_TRY(h, hipGetLastError());
   }
-  HIP_TRY(h, hipGetLastError());
-
-  // 5. FP64 ledger and non-finite check
   return enqueue_ledger<T>(h, chat);
+}
+
+template <typename T>
+int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
+  int rc = enqueue_pre<T>(h, dt, chat);
+  if (rc) return rc;
+  if (nsub > 0 && (rc = enqueue_subcycles<T>(h, dt, chat, nsub))) return rc;
+  return enqueue_post<T>(h, dt, chat);
 }
 
 template <typename T>
@@ -611,6 +681,99 @@ void free_buffers(rhd_t* h) {
 
 }  // namespace
 
+namespace {
+
+template <typename T>
+int time_subcycles(rhd_t* h, double chat, double dt_rad, int reps, double* ms_per) {
+  hipEvent_t a, b;
+  HIP_TRY(h, hipEventCreate(&a));
+  HIP_TRY(h, hipEventCreate(&b));
+  int rc = enqueue_subcycles<T>(h, dt_rad, chat, 1);  // warm-up
+  if (!rc) {
+    (void)hipEventRecord(a, h->stream);
+    rc = enqueue_subcycles<T>(h, dt_rad * reps, chat, reps);
+    (void)hipEventRecord(b, h->stream);
+  }
+  if (!rc) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      rc = fail(h, RHD_EDEVICE, "autotune event timing failed");
+    *ms_per = double(ms) / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+template <typename T>
+int autotune_impl(rhd_t* h, double chat, double dt_rad, int reps) {
+  const size_t bytes = size_t(h->N) * h->esize;
+  void* save[4] = {};
+  for (int q = 0; q < 4; ++q) {
+    if (hipMalloc(&save[q], bytes) != hipSuccess) {
+      for (int r = 0; r < q; ++r) (void)hipFree(save[r]);
+      return fail(h, RHD_ENOMEM, "autotune snapshot allocation failed");
+    }
+    HIP_TRY(h, hipMemcpyAsync(save[q], h->b.rad[q], bytes, hipMemcpyDeviceToDevice, h->stream));
+  }
+  unsigned long long ctr_save[rhdk::CTR_COUNT];
+  HIP_TRY(h, hipMemcpyAsync(ctr_save, h->b.ctr, sizeof(ctr_save), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  const bool was_timing = h->timer.on;
+  h->timer.on = false;
+  const bool three_d = h->G.act[0] && h->G.act[1] && h->G.act[2];
+  struct Cand {
+    int variant, rows, zchunk;
+  };
+  Cand cands[32];
+  int nc = 0;
+  cands[nc++] = {RHD_KERNELS_PER_CELL, 8, 16};
+  if (three_d) {
+    const int rows_list[3] = {4, 8, 16};
+    const int zc_list[4] = {8, 16, 32, 64};
+    for (int r : rows_list) {
+      if (r == 16 && !h->mixed) continue;
+      for (int z : zc_list) cands[nc++] = {RHD_KERNELS_TILED, r, z};
+    }
+  }
+  double best = 1e300;
+  Cand choice = cands[0];
+  int rc = RHD_OK;
+  for (int c = 0; c < nc && !rc; ++c) {
+    h->variant = cands[c].variant;
+    h->tile_rows = cands[c].rows;
+    h->zchunk = cands[c].zchunk;
+    double ms = 0.0;
+    rc = time_subcycles<T>(h, chat, dt_rad, reps, &ms);
+    for (int q = 0; q < 4 && !rc; ++q)
+      if (hipMemcpyAsync(h->b.rad[q], save[q], bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+        rc = fail(h, RHD_EDEVICE, "autotune restore failed");
+    if (!rc && ms < best) {
+      best = ms;
+      choice = cands[c];
+    }
+  }
+  if (hipMemcpyAsync(h->b.ctr, ctr_save, sizeof(ctr_save), hipMemcpyHostToDevice, h->stream) != hipSuccess && !rc)
+    rc = fail(h, RHD_EDEVICE, "autotune counter restore failed");
+  (void)hipStreamSynchronize(h->stream);
+  for (int q = 0; q < 4; ++q) (void)hipFree(save[q]);
+  h->timer.on = was_timing;
+  h->variant = choice.variant;
+  h->tile_rows = choice.rows;
+  h->zchunk = choice.zchunk;
+  if (!rc) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    int slot = -1;
+    for (int t = 0; t < g_ntuned; ++t)
+      if (same_key(g_tuned[t].key, tune_key(h))) slot = t;
+    if (slot < 0 && g_ntuned < 64) slot = g_ntuned++;
+    if (slot >= 0) g_tuned[slot] = {tune_key(h), choice.variant, choice.rows, choice.zchunk};
+  }
+  return rc;
+}
+
+}  // namespace
+
 extern "C" {
 
 void rhd_default_params(rhd_params* p, int nx, int ny, int nz) {
@@ -704,6 +867,15 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
     delete h;
     return fail(nullptr, RHD_ENOMEM, "device allocation of %lld bytes failed", footprint(p, 0, 0));
   }
+  std::unique_lock<std::mutex> lock(g_tune_mutex);
+  for (int t = 0; t < g_ntuned; ++t) {
+    if (same_key(g_tuned[t].key, tune_key(h))) {
+      h->variant = g_tuned[t].variant;
+      h->tile_rows = g_tuned[t].rows;
+      h->zchunk = g_tuned[t].zchunk;
+    }
+  }
+  lock.unlock();
   hipLaunchKernelGGL(rhdk::k_reset_counters, dim3(1), dim3(64), 0, h->stream, h->b.ctr);
   if (hipMemsetAsync(h->b.ledger, 0, 5 * sizeof(double), h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -903,7 +1075,357 @@ int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk) {
   return RHD_OK;
 }
 
+int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, int* tile_rows,
+                 int* zchunk) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_autotune before rhd_set_state");
+  if (!(chat > 0.0) || !(dt_rad > 0.0) || reps < 1)
+    return fail(h, RHD_EINVAL, "chat and dt_rad must be > 0 and reps >= 1");
+  if (chat * dt_rad > h->p.cfl * h->dxmin * (1.0 + 1e-12))
+    return fail(h, RHD_ECFL, "chat dt_rad exceeds K0 dx");
+  int rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
+                    : autotune_impl<double>(h, chat, dt_rad, reps);
+  if (variant) *variant = h->variant;
+  if (tile_rows) *tile_rows = h->tile_rows;
+  if (zchunk) *zchunk = h->zchunk;
+  return rc;
+}
+
 long long rhd_device_bytes(const rhd_t* h) { return h ? h->bytes : 0; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batch of independent solves
+// ---------------------------------------------------------------------------
+
+struct rhd_batch {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int max_solves = 0;
+  int rows = 8;
+  int zchunk = 16;
+  int precision = -1;  // -1 unset, 0 FP64, 1 mixed
+  std::vector<rhd_t*> members;
+  std::vector<double> chat;
+  std::vector<hipStream_t> saved_streams;
+  void* d_desc = nullptr;
+  int4* d_tiles_pred = nullptr;
+  int4* d_tiles_corr = nullptr;
+  int* d_counts = nullptr;
+  void* h_desc = nullptr;
+  int4* h_tiles_pred = nullptr;
+  int4* h_tiles_corr = nullptr;
+  int* h_counts = nullptr;
+  double* h_vmax = nullptr;
+  int cap_pred = 0, cap_corr = 0;
+  char err[512] = "no error";
+};
+
+namespace {
+
+constexpr int BATCH_MAX_ROUNDS = 4096;
+
+thread_local char g_batch_error[512] = "no error";
+
+int bfail(rhd_batch_t* b, int code, const char* fmt, ...) {
+  char* dst = b ? b->err : g_batch_error;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define BHIP_TRY(b, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return bfail((b), RHD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+  } while (0)
+
+void tile_counts(const rhd_t* h, int rows, int zc, int pg[3], int cg[3]) {
+  const int TX = rhdk::TILE_BX - 2, TY = rows - 2;
+  const rhdk::Geom& G = h->G;
+  pg[0] = (G.n[0] + 4 + TX - 1) / TX;
+  pg[1] = (G.n[1] + 4 + TY - 1) / TY;
+  pg[2] = (G.n[2] + 4 + zc - 1) / zc;
+  cg[0] = (G.n[0] + TX - 1) / TX;
+  cg[1] = (G.n[1] + TY - 1) / TY;
+  cg[2] = (G.n[2] + zc - 1) / zc;
+}
+
+int batch_reserve(rhd_batch_t* b, int need_pred, int need_corr) {
+  if (need_pred > b->cap_pred) {
+    int cap = std::max(need_pred, 2 * b->cap_pred);
+    if (b->d_tiles_pred) BHIP_TRY(b, hipFree(b->d_tiles_pred));
+    if (b->h_tiles_pred) BHIP_TRY(b, hipHostFree(b->h_tiles_pred));
+    b->d_tiles_pred = nullptr;
+    b->h_tiles_pred = nullptr;
+    BHIP_TRY(b, hipMalloc(&b->d_tiles_pred, size_t(cap) * sizeof(int4)));
+    BHIP_TRY(b, hipHostMalloc(&b->h_tiles_pred, size_t(cap) * sizeof(int4), hipHostMallocDefault));
+    b->cap_pred = cap;
+  }
+  if (need_corr > b->cap_corr) {
+    int cap = std::max(need_corr, 2 * b->cap_corr);
+    if (b->d_tiles_corr) BHIP_TRY(b, hipFree(b->d_tiles_corr));
+    if (b->h_tiles_corr) BHIP_TRY(b, hipHostFree(b->h_tiles_corr));
+    b->d_tiles_corr = nullptr;
+    b->h_tiles_corr = nullptr;
+    BHIP_TRY(b, hipMalloc(&b->d_tiles_corr, size_t(cap) * sizeof(int4)));
+    BHIP_TRY(b, hipHostMalloc(&b->h_tiles_corr, size_t(cap) * sizeof(int4), hipHostMallocDefault));
+    b->cap_corr = cap;
+  }
+  return RHD_OK;
+}
+
+template <typename T, int BY>
+void launch_batch_round(rhd_batch_t* b, int total_pred, int total_corr, int r) {
+  const dim3 block(rhdk::TILE_BX, BY, 1);
+  const auto* sd = static_cast<const rhdk::SolveDesc<T>*>(b->d_desc);
+  hipLaunchKernelGGL((rhdk::k_rad_predict_batch<T, BY>), dim3(total_pred), block, 0, b->stream, sd,
+                     b->d_tiles_pred, b->d_counts + 2 * r, b->zchunk);
+  hipLaunchKernelGGL((rhdk::k_rad_correct_batch<T, BY>), dim3(total_corr), block, 0, b->stream, sd,
+                     b->d_tiles_corr, b->d_counts + 2 * r + 1, b->zchunk);
+}
+
+template <typename T>
+int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
+  const int S = int(b->members.size());
+  // 1. v_max of every member, one synchronisation
+  for (int i = 0; i < S; ++i) {
+    rhd_t* h = b->members[i];
+    rhdk::CflConst C;
+    C.gamma = h->p.gamma;
+    C.gm1 = h->p.gamma - 1.0;
+    C.cs2 = h->p.iso_cs * h->p.iso_cs;
+    C.dxmin = h->dxmin;
+    C.iso = (h->p.flags & RHD_ISOTHERMAL) != 0;
+    const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+    hipLaunchKernelGGL(rhdk::k_vmax<T>, dim3(VMAX_BLOCKS), dim3(rhdk::RED_THREADS), 0, b->stream,
+                       gas_ptrs<T>(h->b.gas), rad_ptrs<T>(h->b.rad), kFp, T(h->kF_s), C, h->N,
+                       as<T>(h->b.vmax_partials));
+    hipLaunchKernelGGL(rhdk::k_vmax_final<T>, dim3(1), dim3(rhdk::RED_THREADS), 0, b->stream,
+                       as<T>(h->b.vmax_partials), VMAX_BLOCKS, h->b.vmax);
+    BHIP_TRY(b, hipMemcpyAsync(b->h_vmax + i, h->b.vmax, sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream));
+  }
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  std::vector<int> nsub(S);
+  std::vector<double> dt(S);
+  for (int i = 0; i < S; ++i) {
+    rhd_t* h = b->members[i];
+    const double vmax = b->h_vmax[i];
+    h->vmax_last = vmax;
+    if (!(vmax > 0.0) || !std::isfinite(vmax))
+      return bfail(b, RHD_ENONFINITE, "member %d: v_max is %g", i, vmax);
+    dt[i] = h->p.cfl * h->dxmin / vmax;
+    const double r = std::ceil(b->chat[i] / vmax);
+    nsub[i] = r < 1.0 ? 1 : (r > BATCH_MAX_ROUNDS ? BATCH_MAX_ROUNDS + 1 : int(r));
+    if (nsub[i] > BATCH_MAX_ROUNDS)
+      return bfail(b, RHD_EINVAL, "member %d needs %d subcycles (limit %d)", i, nsub[i], BATCH_MAX_ROUNDS);
+  }
+  // 2. exchange and gas step of every member
+  for (int i = 0; i < S; ++i) {
+    rhd_t* h = b->members[i];
+    if (int rc = enqueue_pre<T>(h, dt[i], b->chat[i])) return bfail(b, rc, "member %d: %s", i, h->err);
+  }
+  // 3. radiation subcycles: members by decreasing nsub, so round r covers a prefix
+  std::vector<int> order(S);
+  for (int i = 0; i < S; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nsub[a] > nsub[c]; });
+  auto* desc = static_cast<rhdk::SolveDesc<T>*>(b->h_desc);
+  std::vector<int> pred_end(S), corr_end(S);
+  int np = 0, nc = 0;
+  for (int k = 0; k < S; ++k) {
+    const int i = order[k];
+    rhd_t* h = b->members[i];
+    rhdk::SolveDesc<T> d;
+    d.Um = rad_ptrs<T>(h->b.rad);
+    d.Uh = rad_ptrs<T>(h->b.rh);
+    d.gas = gas_view<T>(h);
+    d.G = h->G;
+    d.K = rad_const<T>(h, b->chat[i]);
+    const double hr = dt[i] / nsub[i];
+    d.h_pred = T(0.5 * hr);
+    d.h_corr = T(hr);
+    d.ctr = h->b.ctr;
+    desc[k] = d;
+    int pg[3], cg[3];
+    tile_counts(h, b->rows, b->zchunk, pg, cg);
+    for (int z = 0; z < pg[2]; ++z)
+      for (int y = 0; y < pg[1]; ++y)
+        for (int x = 0; x < pg[0]; ++x) b->h_tiles_pred[np++] = make_int4(k, x, y, z);
+    for (int z = 0; z < cg[2]; ++z)
+      for (int y = 0; y < cg[1]; ++y)
+        for (int x = 0; x < cg[0]; ++x) b->h_tiles_corr[nc++] = make_int4(k, x, y, z);
+    pred_end[k] = np;
+    corr_end[k] = nc;
+  }
+  const int rounds = S > 0 ? nsub[order[0]] : 0;
+  for (int r = 0; r < rounds; ++r) {
+    int k = 0;
+    while (k < S && nsub[order[k]] > r) ++k;
+    b->h_counts[2 * r] = k > 0 ? pred_end[k - 1] : 0;
+    b->h_counts[2 * r + 1] = k > 0 ? corr_end[k - 1] : 0;
+  }
+  BHIP_TRY(b, hipMemcpyAsync(b->d_desc, desc, size_t(S) * sizeof(rhdk::SolveDesc<T>),
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_tiles_pred, b->h_tiles_pred, size_t(np) * sizeof(int4),
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_tiles_corr, b->h_tiles_corr, size_t(nc) * sizeof(int4),
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_counts, b->h_counts, size_t(2 * rounds) * sizeof(int),
+                             hipMemcpyHostToDevice, b->stream));
+  for (int r = 0; r < rounds; ++r) {
+    switch (b->rows) {
+      case 4:
+        launch_batch_round<T, 4>(b, np, nc, r);
+        break;
+      case 8:
+        launch_batch_round<T, 8>(b, np, nc, r);
+        break;
+      default:
+        if constexpr (sizeof(T) == 4) launch_batch_round<T, 16>(b, np, nc, r);
+        break;
+    }
+  }
+  BHIP_TRY(b, hipGetLastError());
+  // 4. correction and ledger of every member
+  for (int i = 0; i < S; ++i) {
+    rhd_t* h = b->members[i];
+    if (int rc = enqueue_post<T>(h, dt[i], b->chat[i])) return bfail(b, rc, "member %d: %s", i, h->err);
+    h->steps += 1;
+    h->subcycles += nsub[i];
+    if (nsub_out) nsub_out[i] = nsub[i];
+    if (dt_out) dt_out[i] = dt[i];
+  }
+  return RHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk,
+                     rhd_batch_t** out) {
+  if (!out) return bfail(nullptr, RHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_solves < 1) return bfail(nullptr, RHD_EINVAL, "max_solves must be >= 1");
+  if (tile_rows != 4 && tile_rows != 8 && tile_rows != 16)
+    return bfail(nullptr, RHD_EINVAL, "tile_rows must be 4, 8 or 16");
+  if (zchunk < 1) return bfail(nullptr, RHD_EINVAL, "zchunk must be >= 1");
+  rhd_batch_t* b = new (std::nothrow) rhd_batch();
+  if (!b) return bfail(nullptr, RHD_ENOMEM, "host allocation failed");
+  b->max_solves = max_solves;
+  b->rows = tile_rows;
+  b->zchunk = zchunk;
+  bool ok = true;
+  if (hip_stream) {
+    b->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    b->own_stream = ok;
+  }
+  const size_t desc_bytes = size_t(max_solves) * sizeof(rhdk::SolveDesc<double>);
+  ok = ok && hipMalloc(&b->d_desc, desc_bytes) == hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_desc, desc_bytes, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_counts, 2 * BATCH_MAX_ROUNDS * sizeof(int)) == hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_counts, 2 * BATCH_MAX_ROUNDS * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_vmax, size_t(max_solves) * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    rhd_batch_destroy(b);
+    return bfail(nullptr, RHD_ENOMEM, "batch allocation failed");
+  }
+  *out = b;
+  return RHD_OK;
+}
+
+int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
+  if (!b || !h) return bfail(b, RHD_EINVAL, "batch or handle is NULL");
+  if (int(b->members.size()) >= b->max_solves) return bfail(b, RHD_EINVAL, "batch is full");
+  if (!h->have_state) return bfail(b, RHD_ESTATE, "member has no state");
+  if (!(h->G.act[0] && h->G.act[1] && h->G.act[2])) return bfail(b, RHD_EINVAL, "members must be 3D");
+  if (!(chat > 0.0)) return bfail(b, RHD_EINVAL, "chat must be > 0");
+  for (rhd_t* m : b->members)
+    if (m == h) return bfail(b, RHD_EINVAL, "handle is already a member");
+  if (h->in_batch) return bfail(b, RHD_EINVAL, "handle belongs to another batch");
+  const int prec = h->mixed ? 1 : 0;
+  if (b->precision >= 0 && prec != b->precision)
+    return bfail(b, RHD_EINVAL, "member precision differs from the batch's");
+  if (!h->mixed && b->rows == 16) return bfail(b, RHD_EINVAL, "16-row tiles need mixed precision");
+  int pg[3], cg[3];
+  tile_counts(h, b->rows, b->zchunk, pg, cg);
+  int need_p = pg[0] * pg[1] * pg[2], need_c = cg[0] * cg[1] * cg[2];
+  for (rhd_t* m : b->members) {
+    int p2[3], c2[3];
+    tile_counts(m, b->rows, b->zchunk, p2, c2);
+    need_p += p2[0] * p2[1] * p2[2];
+    need_c += c2[0] * c2[1] * c2[2];
+  }
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(h->stream));
+  if (int rc = batch_reserve(b, need_p, need_c)) return rc;
+  b->precision = prec;
+  b->members.push_back(h);
+  b->chat.push_back(chat);
+  b->saved_streams.push_back(h->stream);
+  h->stream = b->stream;
+  h->in_batch = true;
+  return RHD_OK;
+}
+
+int rhd_batch_remove(rhd_batch_t* b, rhd_t* h) {
+  if (!b || !h) return bfail(b, RHD_EINVAL, "batch or handle is NULL");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (b->members[i] != h) continue;
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    h->stream = b->saved_streams[i];
+    h->in_batch = false;
+    b->members.erase(b->members.begin() + long(i));
+    b->chat.erase(b->chat.begin() + long(i));
+    b->saved_streams.erase(b->saved_streams.begin() + long(i));
+    return RHD_OK;
+  }
+  return bfail(b, RHD_EINVAL, "handle is not a member");
+}
+
+int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out) {
+  if (!b) return bfail(nullptr, RHD_EINVAL, "batch is NULL");
+  if (b->members.empty()) return RHD_OK;
+  return b->precision == 1 ? batch_step_impl<float>(b, nsub_out, dt_out)
+                           : batch_step_impl<double>(b, nsub_out, dt_out);
+}
+
+int rhd_batch_size(const rhd_batch_t* b) { return b ? int(b->members.size()) : 0; }
+
+int rhd_batch_sync(rhd_batch_t* b) {
+  if (!b) return bfail(nullptr, RHD_EINVAL, "batch is NULL");
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return RHD_OK;
+}
+
+void rhd_batch_destroy(rhd_batch_t* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    b->members[i]->stream = b->saved_streams[i];
+    b->members[i]->in_batch = false;
+  }
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->h_desc) (void)hipHostFree(b->h_desc);
+  if (b->d_tiles_pred) (void)hipFree(b->d_tiles_pred);
+  if (b->h_tiles_pred) (void)hipHostFree(b->h_tiles_pred);
+  if (b->d_tiles_corr) (void)hipFree(b->d_tiles_corr);
+  if (b->h_tiles_corr) (void)hipHostFree(b->h_tiles_corr);
+  if (b->d_counts) (void)hipFree(b->d_counts);
+  if (b->h_counts) (void)hipHostFree(b->h_counts);
+  if (b->h_vmax) (void)hipHostFree(b->h_vmax);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char* rhd_batch_last_error(const rhd_batch_t* b) { return b ? b->err : g_batch_error; }
 
 void rhd_destroy(rhd_t* h) {
   if (!h) return;

@@ -35,23 +35,33 @@ __device__ __forceinline__ FaceSide<T> side_dir(const M1State<T>& m, const T U[4
 // Predictor: first-order HLL fluxes of U^m, half step, on the interior plus two ghost
 // layers of a 3D grid. Grid: (ceil((nx+4)/62), ceil((ny+4)/(BY-2)), ceil((nz+4)/zc)).
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
-                                                                   GasView<T> gas, Geom G,
-                                                                   RadConst<T> K, T h, int zc) {
+struct PredictShared {
+  FaceSide<T> sx[BY][TILE_BX];
+  FaceSide<T> sy[BY][TILE_BX];
+  T sfx[BY][TILE_BX][4];
+  T sfy[BY][TILE_BX][4];
+};
+
+// One tile (bx, by, bz) of the predictor; called by every thread of the block.
+template <typename T, int BY>
+__device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
+                                                      const GasView<T>& gas, const Geom& G,
+                                                      const RadConst<T>& K, T h, int zc, int bx,
+                                                      int by, int bz, PredictShared<T, BY>& sh) {
   constexpr int BX = TILE_BX, TX = BX - 2, TY = BY - 2;
-  __shared__ FaceSide<T> sx[BY][BX];
-  __shared__ FaceSide<T> sy[BY][BX];
-  __shared__ T sfx[BY][BX][4];
-  __shared__ T sfy[BY][BX][4];
+  auto& sx = sh.sx;
+  auto& sy = sh.sy;
+  auto& sfx = sh.sfx;
+  auto& sfy = sh.sfy;
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
-  const int x = -2 + int(blockIdx.x) * TX + tx - 1;
-  const int y = -2 + int(blockIdx.y) * TY + ty - 1;
+  const int x = -2 + bx * TX + tx - 1;
+  const int y = -2 + by * TY + ty - 1;
   const int xhi = G.n[0] + 2, yhi = G.n[1] + 2;
   // stencil reads stay within [-3, n + 2] in every dimension
   const int xl = x < xhi ? x : xhi;
   const int yl = y < yhi ? y : yhi;
   const bool out_xy = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && x < xhi && y < yhi;
-  const int z0 = -2 + int(blockIdx.z) * zc;
+  const int z0 = -2 + bz * zc;
   const int z1 = min(z0 + zc, G.n[2] + 2);
   const T c = K.c, ic = K.inv_c, chat = K.chat;
 
@@ -117,26 +127,44 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_tile(RadPtrs<T> Um
   }
 }
 
+template <typename T, int BY>
+__global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
+                                                                   GasView<T> gas, Geom G,
+                                                                   RadConst<T> K, T h, int zc) {
+  __shared__ PredictShared<T, BY> sh;
+  rad_predict_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, int(blockIdx.x), int(blockIdx.y),
+                               int(blockIdx.z), sh);
+}
+
 // Corrector: MC-limited reconstruction of U^{m+1/2}, HLL fluxes, full step from U^m
 // with sources at U^{m+1/2}; U^{m+1} overwrites U^m on the interior of a 3D grid.
 // Grid: (ceil(nx/62), ceil(ny/(BY-2)), ceil(nz/zc)).
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
-                                                                   GasView<T> gas, Geom G,
-                                                                   RadConst<T> K, T h, int zc,
-                                                                   unsigned long long* ctr) {
+struct CorrectShared {
+  T sU[BY + 2][TILE_BX + 2][4];   // U^{m+1/2} of plane t with a one-cell ring
+  FaceSide<T> sq[BY][TILE_BX];    // plus-side face data (x faces, then y faces)
+  T sf[BY][TILE_BX][4];           // left (x) then bottom (y) face fluxes
+};
+
+// One tile (bx, by, bz) of the corrector; called by every thread of the block.
+template <typename T, int BY>
+__device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
+                                                      const GasView<T>& gas, const Geom& G,
+                                                      const RadConst<T>& K, T h, int zc, int bx,
+                                                      int by, int bz, unsigned long long* ctr,
+                                                      CorrectShared<T, BY>& sh) {
   constexpr int BX = TILE_BX, TX = BX - 2, TY = BY - 2;
   constexpr int RX = BX + 2, RY = BY + 2;
-  __shared__ T sU[RY][RX][4];          // U^{m+1/2} of plane t with a one-cell ring
-  __shared__ FaceSide<T> sq[BY][BX];   // plus-side face data (x faces, then y faces)
-  __shared__ T sf[BY][BX][4];          // left (x) then bottom (y) face fluxes
+  auto& sU = sh.sU;
+  auto& sq = sh.sq;
+  auto& sf = sh.sf;
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
   const int tid = tx + BX * ty;
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
-  const int x0 = int(blockIdx.x) * TX, y0 = int(blockIdx.y) * TY;
+  const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx - 1, y = y0 + ty - 1;
   const bool out_xy = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && x < n0 && y < n1;
-  const int z0 = int(blockIdx.z) * zc;
+  const int z0 = bz * zc;
   const int z1 = min(z0 + zc, n2);
   // the half-step arrays hold valid values on [-2, n + 2)
   const int xl = clamp_i(x, -2, n0 + 1), yl = clamp_i(y, -2, n1 + 1);
@@ -243,6 +271,57 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um
   }
   wave_add(ctr + CTR_RAD_EFLOOR, nef);
   wave_add(ctr + CTR_RAD_FCLAMP, nfc);
+}
+
+template <typename T, int BY>
+__global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
+                                                                   GasView<T> gas, Geom G,
+                                                                   RadConst<T> K, T h, int zc,
+                                                                   unsigned long long* ctr) {
+  __shared__ CorrectShared<T, BY> sh;
+  rad_correct_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, int(blockIdx.x), int(blockIdx.y),
+                               int(blockIdx.z), ctr, sh);
+}
+
+// ---------------------------------------------------------------------------
+// many independent solves in one launch: a packed list of tiles
+// ---------------------------------------------------------------------------
+
+// Everything one solve's radiation stages need; one entry per member of a batch.
+template <typename T>
+struct SolveDesc {
+  RadPtrs<T> Um, Uh;
+  GasView<T> gas;
+  Geom G;
+  RadConst<T> K;
+  T h_pred, h_corr;
+  unsigned long long* ctr;
+};
+
+// Tile i of a launch is (solve, bx, by, bz) = tiles[i]; blocks past ntiles exit at once,
+// so one grid size serves every round.
+template <typename T, int BY>
+__global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_batch(const SolveDesc<T>* __restrict__ sd,
+                                                                    const int4* __restrict__ tiles,
+                                                                    const int* __restrict__ ntiles,
+                                                                    int zc) {
+  if (int(blockIdx.x) >= *ntiles) return;
+  const int4 tr = tiles[blockIdx.x];
+  const SolveDesc<T> d = sd[tr.x];
+  __shared__ PredictShared<T, BY> sh;
+  rad_predict_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_pred, zc, tr.y, tr.z, tr.w, sh);
+}
+
+template <typename T, int BY>
+__global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_batch(const SolveDesc<T>* __restrict__ sd,
+                                                                    const int4* __restrict__ tiles,
+                                                                    const int* __restrict__ ntiles,
+                                                                    int zc) {
+  if (int(blockIdx.x) >= *ntiles) return;
+  const int4 tr = tiles[blockIdx.x];
+  const SolveDesc<T> d = sd[tr.x];
+  __shared__ CorrectShared<T, BY> sh;
+  rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, zc, tr.y, tr.z, tr.w, d.ctr, sh);
 }
 
 }  // namespace rhdk

@@ -1,0 +1,153 @@
+"""Continuous batching of independent radiation-hydrodynamics solves on one GPU.
+
+Requests arrive over time, each with its own grid, opacity, reduced speed of light and
+number of gas steps. Between two batch steps the server admits waiting requests in
+arrival order while two limits allow it: the device-memory budget (the sum of
+``rhd_footprint_bytes`` of the admitted solves) and the number of slots. For each
+admitted request it creates a handle, uploads the state and adds the handle to the
+batch. Every batch step advances each active solve by one gas step (``rhd_batch_step``);
+the radiation subcycles of all solves share launches over a packed tile list. A solve
+that has taken its steps is copied back, removed and destroyed, which frees its memory
+and slot for the next admission.
+
+Latency is measured from a request's arrival to its result on the host. Synthesising a
+request's initial state on the host is not counted: the clock stops while it runs, as
+if the client had sent a ready state.
+
+``serve_serial`` runs the same requests one at a time with one handle each, for
+comparison.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import (RHD_KERNELS_TILED, Solver, params_from_spec, rhd_batch_add, rhd_batch_create,
+               rhd_batch_destroy, rhd_batch_remove, rhd_batch_step, rhd_batch_sync,
+               rhd_footprint_bytes)
+
+
+class _Clock:
+    """Wall clock that can be paused for work that is not the server's."""
+
+    def __init__(self):
+        self.t0 = time.perf_counter()
+        self.excluded = 0.0
+
+    def now(self):
+        return time.perf_counter() - self.t0 - self.excluded
+
+    def exclude(self, fn):
+        t = time.perf_counter()
+        out = fn()
+        self.excluded += time.perf_counter() - t
+        return out
+
+
+def _percentiles(lat):
+    a = np.sort(np.asarray(lat, dtype=np.float64))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def serve_batched(requests, make_problem, budget_bytes=16 << 30, max_slots=64, tile_rows=8,
+                  zchunk=16, keep_results=False):
+    """Serve ``requests`` (dicts with 'id', 'arrival' in seconds, 'steps') with
+    continuous batching. ``make_problem(req)`` returns the problem dict (spec, state,
+    chat). Returns a summary dict and, with keep_results, the final states by id."""
+    order = [dict(r) for r in sorted(requests, key=lambda r: r["arrival"])]
+    clock = _Clock()
+    batch = rhd_batch_create(max_slots, tile_rows, zchunk)
+    waiting = list(order)
+    active = []  # dicts: req, solver, footprint, steps_done, cells
+    used = 0
+    lat, results, zone_updates, peak_active, steps_taken = {}, {}, 0, 0, 0
+    try:
+        while waiting or active:
+            now = clock.now()
+            # admission in arrival order, by memory budget and slots
+            while waiting and waiting[0]["arrival"] <= now and len(active) < max_slots:
+                req = waiting[0]
+                if "_problem" not in req:
+                    req["_problem"] = clock.exclude(lambda: make_problem(req))
+                pb = req["_problem"]
+                fp = rhd_footprint_bytes(params_from_spec(pb["spec"]))
+                if used + fp > budget_bytes and active:
+                    break
+                waiting.pop(0)
+                del req["_problem"]
+                s = Solver(pb["spec"])
+                s.set_state(pb["state"])
+                rhd_batch_add(batch, s.h, pb["chat"])
+                used += fp
+                active.append({"req": req, "solver": s, "fp": fp, "done": 0,
+                               "cells": int(np.prod(s.shape))})
+                peak_active = max(peak_active, len(active))
+            if not active:
+                # idle until the next arrival
+                wait = waiting[0]["arrival"] - clock.now()
+                if wait > 0:
+                    time.sleep(wait)
+                continue
+            nsub, _ = rhd_batch_step(batch)
+            steps_taken += 1
+            for a, ns in zip(active, nsub):
+                a["done"] += 1
+                zone_updates += a["cells"] * ns
+            finished = [a for a in active if a["done"] >= a["req"]["steps"]]
+            for a in finished:
+                out = a["solver"].get_state()  # waits for the batch's stream
+                lat[a["req"]["id"]] = clock.now() - a["req"]["arrival"]
+                if keep_results:
+                    results[a["req"]["id"]] = out
+                rhd_batch_remove(batch, a["solver"].h)
+                a["solver"].close()
+                used -= a["fp"]
+                active.remove(a)
+        rhd_batch_sync(batch)
+    finally:
+        for a in active:
+            rhd_batch_remove(batch, a["solver"].h)
+            a["solver"].close()
+        rhd_batch_destroy(batch)
+    elapsed = clock.now()
+    p50, p99 = _percentiles(list(lat.values()))
+    summary = {"mode": "batched", "requests": len(lat), "zone_updates": zone_updates,
+               "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
+               "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": peak_active,
+               "batch_steps": steps_taken, "budget_bytes": budget_bytes, "max_slots": max_slots}
+    return summary, results
+
+
+def serve_serial(requests, make_problem, keep_results=False, variant=None):
+    """Serve the same requests one at a time, one handle each, in arrival order."""
+    order = sorted(requests, key=lambda r: r["arrival"])
+    clock = _Clock()
+    lat, results, zone_updates = {}, {}, 0
+    for req in order:
+        wait = req["arrival"] - clock.now()
+        if wait > 0:
+            time.sleep(wait)
+        pb = clock.exclude(lambda: make_problem(req))
+        with Solver(pb["spec"]) as s:
+            if variant is not None:
+                s.set_kernel_variant(*variant)
+            s.set_state(pb["state"])
+            cells = int(np.prod(s.shape))
+            for _ in range(req["steps"]):
+                dt, ns = s.suggest_dt(pb["chat"])
+                s.step(dt, pb["chat"], ns)
+                zone_updates += cells * ns
+            out = s.get_state()
+        lat[req["id"]] = clock.now() - req["arrival"]
+        if keep_results:
+            results[req["id"]] = out
+    elapsed = clock.now()
+    p50, p99 = _percentiles(list(lat.values()))
+    summary = {"mode": "one_at_a_time", "requests": len(lat), "zone_updates": zone_updates,
+               "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
+               "p50_latency_s": p50, "p99_latency_s": p99}
+    return summary, results
+
+
+DEFAULT_VARIANT = (RHD_KERNELS_TILED, 8, 16)

@@ -261,6 +261,32 @@ def test_checkpoint_restart_and_determinism(precision):
         assert np.array_equal(a[k], c[k]), k
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_keeps_state_and_result(precision):
+    """The autotuner restores the state and counters exactly, picks a valid kernel
+    choice, and the step after it still matches the oracle."""
+    announce(f"autotune {precision}")
+    spec, st, chat, _ = rhd3d_periodic(precision)
+    dt, ns = step_sizes(spec, st, chat)
+    ref, _ = oracle.step(spec, st, dt, chat, ns)
+    with P.Solver(spec) as s:
+        s.set_state(st)
+        before = s.get_state()
+        d0 = s.diagnostics()
+        v, rows, zc = s.autotune(chat, dt / ns, reps=2)
+        assert v in (P.RHD_KERNELS_PER_CELL, P.RHD_KERNELS_TILED) and rows in (4, 8, 16) and zc >= 1
+        after = s.get_state()
+        for k in ri.FIELDS:
+            assert np.array_equal(before[k], after[k]), k
+        d1 = s.diagnostics()
+        for k in ("rad_fclamp", "rad_efloor", "nonfinite"):
+            assert d0[k] == d1[k]
+        s.step(dt, chat, ns)
+        s.sync()
+        gpu = s.get_state()
+    assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label="after autotune")
+
+
 def test_torch_stream_and_device_pointers():
     announce("torch interop")
     import torch
