@@ -74,6 +74,30 @@ def cpu_baseline(pb, nz_slab=16):
                       f"128^3 input, FP64, {el:.1f} s"}
 
 
+def serving(count, load):
+    """The served-batch workload: a stream of independent periodic boxes (32^3..192^3,
+    kappa log-uniform in [1, 1e3], chat/a0 in [5, 50], 20 gas steps each). The
+    one-at-a-time capacity is measured first with every request queued at t = 0; the
+    Poisson arrivals are then scaled so that the offered load is ``load`` times that
+    capacity, and the same stream is served with continuous batching and one at a time."""
+    import rhd_inputs as ri
+    from paper_1306_0010_amd import serve
+
+    reqs = ri.c5_requests(count=count, load=load)
+    make = lambda r: ri.c5_problem(r)
+    at_zero = [dict(r, arrival=0.0) for r in reqs]
+    cap, _ = serve.serve_serial(at_zero, make, variant=serve.DEFAULT_VARIANT)
+    service = cap["elapsed_s"] / count
+    timed = [dict(r, arrival=r["arrival"] * service) for r in reqs]
+    batched, _ = serve.serve_batched(timed, make)
+    serial, _ = serve.serve_serial(timed, make, variant=serve.DEFAULT_VARIANT)
+    return {"requests": count, "offered_load": load,
+            "one_at_a_time_capacity_requests_per_s": 1.0 / service,
+            "batched": batched, "one_at_a_time": serial,
+            "batched_over_one_at_a_time_zone_updates": batched["zone_updates_per_s"]
+            / serial["zone_updates_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +105,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--n", type=int, default=128, help="grid side of the box (default 128)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the served-batch measurement (0 skips it; 512 is the "
+                         "full stream)")
+    ap.add_argument("--serve-load", type=float, default=1.2,
+                    help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
@@ -178,6 +207,8 @@ def main():
     out["diagnostics"] = {k: diag[k] for k in ("nonfinite", "rad_fclamp", "rad_efloor",
                                                "gas_rhofloor", "gas_pfloor", "exch_theta1",
                                                "exch_bisect", "newton_max")}
+    if args.serve_requests > 0:
+        out["serving"] = serving(args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)

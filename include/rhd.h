@@ -241,7 +241,8 @@ int rhd_batch_remove(rhd_batch_t* b, rhd_t* h);
    reads all v_max values; the exchange and gas step of each member follow; then the
    radiation subcycles of all members run as rounds of batched launches, round r covering
    the members with nsub > r; each member's correction and ledger close the step. A
-   member's result is bit for bit the one rhd_step with the tiled kernels gives it alone.
+   member's result does not depend, bit for bit, on which other solves share the batch;
+   it equals what rhd_step gives the handle alone to rounding (the kernels differ).
    nsub_out and dt_out (each NULL or room for rhd_batch_size() values, member order)
    receive each member's nsub and dt_gas. Allocates nothing. */
 int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out);

@@ -99,11 +99,24 @@ class rhd_timing(ctypes.Structure):
 _lib = None
 
 
+def _share_torch_runtime():
+    """Import torch (if installed) before the library is loaded. torch ships its own HIP
+    runtime with the same soname as the system one; loaded first, it is the one the
+    dynamic linker then hands to librhd.so too, so that torch streams and device
+    pointers are valid in this library. Loaded the other way round, the process would
+    hold two HIP runtimes and torch would see no GPU."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     """The loaded library; raises RhdError when it has not been built."""
     global _lib
     if _lib is not None:
         return _lib
+    _share_torch_runtime()
     if not os.path.exists(LIB_PATH):
         raise RhdError(RHD_EDEVICE, f"{LIB_PATH} is missing: build it with "
                                     "`python paper_1306_0010_amd/build.py` (hipcc, gfx950)")

@@ -95,23 +95,24 @@ struct GasConst {
 // small helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int map_index(int q, int n, int lo, int hi, int& flip) {
-  if (q < 0) {
-    if (lo == BC_PERIODIC) {
-      int r = q % n;
-      return r < 0 ? r + n : r;
-    }
-    if (lo == BC_OUTFLOW) return 0;
-    flip = -flip;
-    return -1 - q;
-  }
-  if (q >= n) {
-    if (hi == BC_PERIODIC) return q % n;
-    if (hi == BC_OUTFLOW) return n - 1;
-    flip = -flip;
-    return 2 * n - 1 - q;
-  }
-  return q;
+// Source index of coordinate q (in [-2n, 3n)) after the boundary mapping of one
+// dimension, and the sign the vector component along that dimension takes there.
+// Written with selects only: a branchy form of this mapping, with the sign updated
+// through a reference inside the branches, was compiled for wave-uniform coordinates
+// (y and z rows) so that the reflecting high face lost its sign change.
+__device__ __forceinline__ int map_index(int q, int n, int lo, int hi, int& sign) {
+  const bool low = q < 0;
+  const bool high = q >= n;
+  const int kind = low ? lo : (high ? hi : -1);
+  int per = q + (q < 0 ? n : 0);
+  per += per < 0 ? n : 0;
+  per -= per >= n ? n : 0;
+  per -= per >= n ? n : 0;
+  const int clamp = low ? 0 : n - 1;
+  const int mirror = low ? -1 - q : 2 * n - 1 - q;
+  const int r = kind == BC_PERIODIC ? per : (kind == BC_OUTFLOW ? clamp : (kind == BC_REFLECT ? mirror : q));
+  sign = kind == BC_REFLECT ? -sign : sign;
+  return r;
 }
 
 // Flat interior index of a possibly out-of-range cell after boundary mapping, and

@@ -235,7 +235,7 @@ def test_nonfinite_state_is_detected():
                                                      kappa=(3.0, 2.0), v_amp=0.1), chat)
     with P.Solver(spec) as s:
         s.set_state(st)
-        s.step(dt, chat, 1)
+        s.step(dt, chat, ns)
         with pytest.raises(P.RhdError) as e:
             s.sync()
         assert e.value.code == P.RHD_ENONFINITE
@@ -334,7 +334,7 @@ def window_check(spec, st, gpu, chat, dt, nsub, centres, w, margin, bc_modes, to
     for cz in centres:
         lo = tuple(c - w // 2 - margin for c in cz)
         sub = window(st, lo, size, bc_modes)
-        sspec = dict(spec, nx=size[0], ny=size[1], nz=size[2], bc="outflow")
+        sspec = dict(spec, nx=size[0], ny=size[1], nz=size[2], bc=("outflow",) * 6)
         ref, _ = oracle.step(sspec, sub, dt, chat, nsub)
         core = tuple(slice(margin, margin + w) for _ in range(3))
         rc = {k: ref[k][core] for k in ri.FIELDS}
