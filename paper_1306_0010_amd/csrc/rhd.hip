@@ -28,6 +28,7 @@ thread_local char g_create_error[512] = "no error";
 
 constexpr int LEDGER_BLOCKS = 1024;
 constexpr int VMAX_BLOCKS = 1024;
+constexpr int EXCH_BLOCKS = 2048;  // grid-stride exchange: 8 waves per SIMD
 
 struct Buffers {
   void* gas[5] = {};   // rho, mx, my, mz, E
@@ -44,6 +45,7 @@ struct Buffers {
   double* ledger = nullptr;          // 5
   void* vmax_partials = nullptr;     // VMAX_BLOCKS of T
   double* vmax = nullptr;            // 1
+  unsigned long long* exch_partials = nullptr;  // EXCH_STATS x EXCH_BLOCKS
   unsigned long long* ctr = nullptr; // rhdk::CTR_COUNT
 };
 
@@ -236,6 +238,7 @@ long long footprint(const rhd_params* p, long long* N_out, long long* NP_out) {
   if (gas) bytes += 5 * NP * es + 8 * N * es;  // gas half step, s_n, W_1/2
   bytes += N * 8;                       // staging
   bytes += 5 * LEDGER_BLOCKS * 8 + 5 * 8 + VMAX_BLOCKS * 8 + 8 + rhdk::CTR_COUNT * 8;
+  bytes += rhdk::EXCH_STATS * EXCH_BLOCKS * 8;
   return bytes;
 }
 
@@ -463,7 +466,6 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
   auto rad = rad_ptrs<T>(h->b.rad);
   const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
   const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
-  const int threads = 256;
 
   // implicit energy exchange over dt_gas (FP64)
   if (mode == RHD_EXCHANGE_FULL && !iso) {
@@ -478,9 +480,12 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
     X.rtol = p.newton_rtol;
     X.maxit = p.newton_maxit;
     const int ti = tbegin(h, KC_EXCHANGE, h->N);
-    hipLaunchKernelGGL(rhdk::k_exchange<T>, dim3(blocks_for(h->N, threads)), dim3(threads), 0,
-                       h->stream, gas, rad, kPp, h->kP_s, X, h->N, h->b.ctr);
+    const int eb = std::min(EXCH_BLOCKS, blocks_for(h->N, rhdk::EXCH_THREADS));
+    hipLaunchKernelGGL(rhdk::k_exchange<T>, dim3(eb), dim3(rhdk::EXCH_THREADS), 0, h->stream, gas,
+                       rad, kPp, h->kP_s, X, h->N, h->b.exch_partials);
     tend(h, ti);
+    hipLaunchKernelGGL(rhdk::k_exchange_final, dim3(1), dim3(rhdk::EXCH_THREADS), 0, h->stream,
+                       h->b.exch_partials, eb, h->b.ctr);
   }
 
   // gas Van Leer step with S_e,gas at first order
@@ -675,6 +680,7 @@ void free_buffers(rhd_t* h) {
   fr(h->b.ledger);
   fr(h->b.vmax_partials);
   fr(h->b.vmax);
+  fr(h->b.exch_partials);
   fr(h->b.ctr);
   h->b = Buffers();
 }
@@ -860,6 +866,8 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
   alloc(reinterpret_cast<void**>(&h->b.ledger), 5 * sizeof(double));
   alloc(&h->b.vmax_partials, VMAX_BLOCKS * sizeof(double));
   alloc(reinterpret_cast<void**>(&h->b.vmax), sizeof(double));
+  alloc(reinterpret_cast<void**>(&h->b.exch_partials),
+        rhdk::EXCH_STATS * EXCH_BLOCKS * sizeof(unsigned long long));
   alloc(reinterpret_cast<void**>(&h->b.ctr), rhdk::CTR_COUNT * sizeof(unsigned long long));
   if (!ok) {
     free_buffers(h);

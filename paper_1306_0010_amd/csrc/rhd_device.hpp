@@ -875,29 +875,91 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
   return x;
 }
 
+// The exchange kernel keeps its solver statistics (theta = 1 fallbacks, bisections,
+// Newton iterations and their maximum) in registers, reduces them over the block and
+// writes one record of EXCH_STATS values per block; k_exchange_final folds the records
+// into the counters. No atomics: a same-address atomic per wave costs more than the
+// exchange itself.
+constexpr int EXCH_THREADS = 256;
+constexpr int EXCH_STATS = 4;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_exchange(GasPtrs<T> Ug, RadPtrs<T> Ur, const T* kP,
-                                                  double kP_s, ExchConst X, int N,
-                                                  unsigned long long* ctr) {
-  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
-  int it = 0;
-  bool th1 = false, bis = false;
-  if (a < N) {
+__global__ void __launch_bounds__(EXCH_THREADS) k_exchange(GasPtrs<T> Ug, RadPtrs<T> Ur,
+                                                           const T* kP, double kP_s, ExchConst X,
+                                                           int N, unsigned long long* part) {
+  __shared__ unsigned long long sh[EXCH_STATS][EXCH_THREADS / 64];
+  unsigned n_th1 = 0, n_bis = 0, n_it = 0, it_max = 0;
+  const int stride = int(gridDim.x * blockDim.x);
+  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride) {
     const double rho = double(Ug.rho[a]);
     const double m0 = double(Ug.m[0][a]), m1 = double(Ug.m[1][a]), m2 = double(Ug.m[2][a]);
     const double Et = double(Ug.E[a]);
     const double ke = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
     const double e = Et - ke;
     double Er_new;
+    int it = 0;
+    bool th1 = false, bis = false;
     const double x = exchange_root(X, rho, e, double(Ur.E[a]), kP ? double(kP[a]) : kP_s, Er_new,
                                    it, th1, bis);
     Ug.E[a] = T(Et + (x - e));
     Ur.E[a] = T(Er_new);
+    n_th1 += th1 ? 1u : 0u;
+    n_bis += bis ? 1u : 0u;
+    n_it += unsigned(it);
+    it_max = unsigned(it) > it_max ? unsigned(it) : it_max;
   }
-  wave_add(ctr + CTR_EXCH_THETA1, th1 ? 1ull : 0ull);
-  wave_add(ctr + CTR_EXCH_BISECT, bis ? 1ull : 0ull);
-  wave_add(ctr + CTR_NEWTON_ITERS, (unsigned long long)it);
-  wave_max(ctr + CTR_NEWTON_MAX, (unsigned long long)it);
+  unsigned long long v[EXCH_STATS] = {n_th1, n_bis, n_it, it_max};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    const unsigned long long o = __shfl_xor(v[3], off, 64);
+    v[3] = o > v[3] ? o : v[3];
+  }
+  const int w = int(threadIdx.x) >> 6;
+  if (__lane_id() == 0) {
+#pragma unroll
+    for (int k = 0; k < EXCH_STATS; ++k) sh[k][w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < EXCH_STATS) {
+    const int k = int(threadIdx.x);
+    unsigned long long r = sh[k][0];
+    for (int q = 1; q < EXCH_THREADS / 64; ++q) r = k == 3 ? (sh[k][q] > r ? sh[k][q] : r) : r + sh[k][q];
+    part[size_t(blockIdx.x) * EXCH_STATS + k] = r;
+  }
+}
+
+// One block: folds the nblocks records of k_exchange into the counters.
+__global__ void __launch_bounds__(EXCH_THREADS) k_exchange_final(const unsigned long long* part,
+                                                                 int nblocks,
+                                                                 unsigned long long* ctr) {
+  __shared__ unsigned long long sh[EXCH_STATS][EXCH_THREADS];
+  unsigned long long v[EXCH_STATS] = {0ull, 0ull, 0ull, 0ull};
+  for (int b = int(threadIdx.x); b < nblocks; b += EXCH_THREADS) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += part[size_t(b) * EXCH_STATS + k];
+    const unsigned long long m = part[size_t(b) * EXCH_STATS + 3];
+    v[3] = m > v[3] ? m : v[3];
+  }
+#pragma unroll
+  for (int k = 0; k < EXCH_STATS; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = EXCH_THREADS / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+      const unsigned long long o = sh[3][threadIdx.x + s];
+      sh[3][threadIdx.x] = o > sh[3][threadIdx.x] ? o : sh[3][threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctr[CTR_EXCH_THETA1] += sh[0][0];
+    ctr[CTR_EXCH_BISECT] += sh[1][0];
+    ctr[CTR_NEWTON_ITERS] += sh[2][0];
+    ctr[CTR_NEWTON_MAX] = sh[3][0] > ctr[CTR_NEWTON_MAX] ? sh[3][0] : ctr[CTR_NEWTON_MAX];
+  }
 }
 
 // ---------------------------------------------------------------------------
