@@ -112,6 +112,10 @@ def main():
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the timed region, copy a buffer of this many MiB once "
+                         "(device to device): the reference dispatch for scaling hardware "
+                         "byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,6 +147,14 @@ def main():
         dt, ns = solver.suggest_dt(chat)
         solver.step(dt, chat, ns)
         return ns
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         one_step()

@@ -346,18 +346,17 @@ template <typename T, int BY>
 void launch_tiled_rows(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasView<T> view,
                        const rhdk::RadConst<T>& RK, T h_pred, T h_corr) {
   const rhdk::Geom& G = h->G;
-  constexpr int TX = rhdk::TILE_BX - 2, TY = BY - 2;
-  const int zc = h->zchunk;
+  const rhdk::TileGrid tg = rhdk::tile_grid<BY>(G.n, h->zchunk);
   const dim3 block(rhdk::TILE_BX, BY, 1);
-  const dim3 gp((G.n[0] + 4 + TX - 1) / TX, (G.n[1] + 4 + TY - 1) / TY, (G.n[2] + 4 + zc - 1) / zc);
-  const dim3 gc((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, (G.n[2] + zc - 1) / zc);
+  const dim3 gp(tg.pred[0], tg.pred[1], tg.pred[2]);
+  const dim3 gc(tg.corr[0], tg.corr[1], tg.corr[2]);
   int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
   hipLaunchKernelGGL((rhdk::k_rad_predict_tile<T, BY>), gp, block, 0, h->stream, rad, rh, view, G,
-                     RK, h_pred, zc);
+                     RK, h_pred, tg.zc_pred);
   tend(h, ti);
   ti = tbegin(h, KC_RAD_CORRECT, h->N);
   hipLaunchKernelGGL((rhdk::k_rad_correct_tile<T, BY>), gc, block, 0, h->stream, rad, rh, view, G,
-                     RK, h_corr, zc, h->b.ctr);
+                     RK, h_corr, tg.zc_corr, h->b.ctr);
   tend(h, ti);
 }
 
@@ -1152,15 +1151,15 @@ int bfail(rhd_batch_t* b, int code, const char* fmt, ...) {
       return bfail((b), RHD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
   } while (0)
 
-void tile_counts(const rhd_t* h, int rows, int zc, int pg[3], int cg[3]) {
-  const int TX = rhdk::TILE_BX - 2, TY = rows - 2;
-  const rhdk::Geom& G = h->G;
-  pg[0] = (G.n[0] + 4 + TX - 1) / TX;
-  pg[1] = (G.n[1] + 4 + TY - 1) / TY;
-  pg[2] = (G.n[2] + 4 + zc - 1) / zc;
-  cg[0] = (G.n[0] + TX - 1) / TX;
-  cg[1] = (G.n[1] + TY - 1) / TY;
-  cg[2] = (G.n[2] + zc - 1) / zc;
+rhdk::TileGrid tile_counts(const rhd_t* h, int rows, int zc) {
+  switch (rows) {
+    case 4:
+      return rhdk::tile_grid<4>(h->G.n, zc);
+    case 8:
+      return rhdk::tile_grid<8>(h->G.n, zc);
+    default:
+      return rhdk::tile_grid<16>(h->G.n, zc);
+  }
 }
 
 int batch_reserve(rhd_batch_t* b, int need_pred, int need_corr) {
@@ -1192,9 +1191,9 @@ void launch_batch_round(rhd_batch_t* b, int total_pred, int total_corr, int r) {
   const dim3 block(rhdk::TILE_BX, BY, 1);
   const auto* sd = static_cast<const rhdk::SolveDesc<T>*>(b->d_desc);
   hipLaunchKernelGGL((rhdk::k_rad_predict_batch<T, BY>), dim3(total_pred), block, 0, b->stream, sd,
-                     b->d_tiles_pred, b->d_counts + 2 * r, b->zchunk);
+                     b->d_tiles_pred, b->d_counts + 2 * r);
   hipLaunchKernelGGL((rhdk::k_rad_correct_batch<T, BY>), dim3(total_corr), block, 0, b->stream, sd,
-                     b->d_tiles_corr, b->d_counts + 2 * r + 1, b->zchunk);
+                     b->d_tiles_corr, b->d_counts + 2 * r + 1);
 }
 
 template <typename T>
@@ -1258,15 +1257,16 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
     d.h_pred = T(0.5 * hr);
     d.h_corr = T(hr);
     d.ctr = h->b.ctr;
+    const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
+    d.zc_pred = tg.zc_pred;
+    d.zc_corr = tg.zc_corr;
     desc[k] = d;
-    int pg[3], cg[3];
-    tile_counts(h, b->rows, b->zchunk, pg, cg);
-    for (int z = 0; z < pg[2]; ++z)
-      for (int y = 0; y < pg[1]; ++y)
-        for (int x = 0; x < pg[0]; ++x) b->h_tiles_pred[np++] = make_int4(k, x, y, z);
-    for (int z = 0; z < cg[2]; ++z)
-      for (int y = 0; y < cg[1]; ++y)
-        for (int x = 0; x < cg[0]; ++x) b->h_tiles_corr[nc++] = make_int4(k, x, y, z);
+    for (int z = 0; z < tg.pred[2]; ++z)
+      for (int y = 0; y < tg.pred[1]; ++y)
+        for (int x = 0; x < tg.pred[0]; ++x) b->h_tiles_pred[np++] = make_int4(k, x, y, z);
+    for (int z = 0; z < tg.corr[2]; ++z)
+      for (int y = 0; y < tg.corr[1]; ++y)
+        for (int x = 0; x < tg.corr[0]; ++x) b->h_tiles_corr[nc++] = make_int4(k, x, y, z);
     pred_end[k] = np;
     corr_end[k] = nc;
   }
@@ -1362,14 +1362,12 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   if (b->precision >= 0 && prec != b->precision)
     return bfail(b, RHD_EINVAL, "member precision differs from the batch's");
   if (!h->mixed && b->rows == 16) return bfail(b, RHD_EINVAL, "16-row tiles need mixed precision");
-  int pg[3], cg[3];
-  tile_counts(h, b->rows, b->zchunk, pg, cg);
-  int need_p = pg[0] * pg[1] * pg[2], need_c = cg[0] * cg[1] * cg[2];
+  const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
+  int need_p = tg.pred[0] * tg.pred[1] * tg.pred[2], need_c = tg.corr[0] * tg.corr[1] * tg.corr[2];
   for (rhd_t* m : b->members) {
-    int p2[3], c2[3];
-    tile_counts(m, b->rows, b->zchunk, p2, c2);
-    need_p += p2[0] * p2[1] * p2[2];
-    need_c += c2[0] * c2[1] * c2[2];
+    const rhdk::TileGrid t2 = tile_counts(m, b->rows, b->zchunk);
+    need_p += t2.pred[0] * t2.pred[1] * t2.pred[2];
+    need_c += t2.corr[0] * t2.corr[1] * t2.corr[2];
   }
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
   BHIP_TRY(b, hipStreamSynchronize(h->stream));

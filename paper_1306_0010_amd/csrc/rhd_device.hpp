@@ -378,15 +378,12 @@ __device__ __forceinline__ void load_rad_mapped(const RadPtrs<T>& R, const Geom&
   U[3] = T(s[2]) * R.F[2][a];
 }
 
-// Radiation predictor: first-order HLL fluxes of U^m, half step, on the interior plus
-// two ghost layers, written to the padded half-step arrays.
+// Radiation predictor at one cell (i, j, k) of the padded region: first-order HLL fluxes
+// of U^m, half step, result written to the padded half-step arrays.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
-                                                     Geom G, RadConst<T> K, T h) {
-  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
-  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
-  const int k = int(blockIdx.z) - G.g[2];
-  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+__device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
+                                                 const GasView<T>& gas, const Geom& G,
+                                                 const RadConst<T>& K, T h, int i, int j, int k) {
   T U0[4];
   load_rad_mapped(Um, G, i, j, k, U0);
   const M1State<T> m0 = m1_state(U0, K.inv_c, K.chat);
@@ -418,6 +415,18 @@ __global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> U
   Uh.F[0][p] = out[1];
   Uh.F[1][p] = out[2];
   Uh.F[2][p] = out[3];
+}
+
+// Radiation predictor: first-order HLL fluxes of U^m, half step, on the interior plus
+// two ghost layers, written to the padded half-step arrays.
+template <typename T>
+__global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
+                                                     Geom G, RadConst<T> K, T h) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
+  const int k = int(blockIdx.z) - G.g[2];
+  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+  rad_predict_cell(Um, Uh, gas, G, K, h, i, j, k);
 }
 
 template <typename T>

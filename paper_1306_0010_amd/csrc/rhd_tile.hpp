@@ -1,16 +1,16 @@
 // rhd_tile.hpp -- tiled radiation Van Leer stages for 3D grids (gfx950).
 //
-// A block of 64 x BY threads owns an x-y tile of (64 - 2) x (BY - 2) output cells and
-// walks a chunk of zc planes along z. Every thread evaluates the M1 closure of its own
-// cell (predictor) or of its own reconstructed face states (corrector) exactly once:
-// x- and y-neighbours exchange closure data and face fluxes through LDS, and the z
-// neighbour's data is carried in registers from the previous plane, so each face flux
-// of the HLL solver is computed once. The outer ring of threads of a tile only supplies
-// the data for the faces on the tile's edge. One wavefront is one x-row of 64 cells,
-// so every global load and store of a row is one coalesced access.
+// A block of 64 x BY threads owns an x-y tile of 64 x BY cells, one wavefront per x-row,
+// and walks a chunk of z planes. Each thread owns the faces on the low side of its cell:
+// in x and y the neighbour's data comes through LDS, in z from the registers of the
+// previous plane, so every face flux inside a tile is evaluated once. The faces on the
+// high x and y edges of a tile (and, in the predictor, the closure data of the cells just
+// outside it) are extra work items gathered into one or two wavefronts of the block, so
+// no thread of a tile exists only to supply a halo. Every global load and store of a row
+// is one coalesced 64-wide access.
 //
-// Both kernels produce exactly what the per-cell kernels of rhd_device.hpp produce:
-// the predictor writes U^{m+1/2} on the interior plus two ghost layers, the corrector
+// Both kernels produce what the per-cell kernels of rhd_device.hpp produce: the
+// predictor writes U^{m+1/2} on the interior plus two ghost layers, the corrector
 // overwrites U^m with U^{m+1} on the interior.
 #pragma once
 
@@ -20,7 +20,66 @@ namespace rhdk {
 
 constexpr int TILE_BX = 64;
 
-__device__ __forceinline__ int clamp_i(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
+__host__ __device__ __forceinline__ int clamp_i(int q, int lo, int hi) {
+  return q < lo ? lo : (q > hi ? hi : q);
+}
+
+// Planes per z chunk: the requested chunk length rebalanced so that the chunks of a
+// range of L planes are as even as possible.
+__host__ __device__ __forceinline__ int balanced_chunk(int L, int zc) {
+  const int chunks = (L + zc - 1) / zc;
+  return (L + chunks - 1) / chunks;
+}
+
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T v[4];
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+  T v[2];
+};
+
+template <typename T>
+__device__ __forceinline__ void put4(V4<T>& d, const T s[4]) {
+  V4<T> t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t.v[q] = s[q];
+  d = t;
+}
+
+template <typename T>
+__device__ __forceinline__ void get4(const V4<T>& d, T s[4]) {
+  const V4<T> t = d;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s[q] = t.v[q];
+}
+
+// Closure data (state, physical flux, wave speeds) of R x C cells for the faces of one
+// direction, stored so that each part is one vector LDS access per lane.
+template <typename T, int R, int C>
+struct SideTile {
+  V4<T> U[R][C];
+  V4<T> P[R][C];
+  V2<T> L[R][C];
+  __device__ __forceinline__ void put(int r, int c, const FaceSide<T>& s) {
+    put4(U[r][c], s.U);
+    put4(P[r][c], s.Phi);
+    V2<T> l;
+    l.v[0] = s.lmin;
+    l.v[1] = s.lmax;
+    L[r][c] = l;
+  }
+  __device__ __forceinline__ FaceSide<T> get(int r, int c) const {
+    FaceSide<T> s;
+    get4(U[r][c], s.U);
+    get4(P[r][c], s.Phi);
+    const V2<T> l = L[r][c];
+    s.lmin = l.v[0];
+    s.lmax = l.v[1];
+    return s;
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ FaceSide<T> side_dir(const M1State<T>& m, const T U[4], int d, T c,
@@ -32,82 +91,90 @@ __device__ __forceinline__ FaceSide<T> side_dir(const M1State<T>& m, const T U[4
   return q;
 }
 
-// Predictor: first-order HLL fluxes of U^m, half step, on the interior plus two ghost
-// layers of a 3D grid. Grid: (ceil((nx+4)/62), ceil((ny+4)/(BY-2)), ceil((nz+4)/zc)).
+// Closure data of the boundary-mapped cell (x, y, z) of U^m for faces normal to d.
+template <typename T>
+__device__ __forceinline__ FaceSide<T> side_at(const RadPtrs<T>& Um, const Geom& G, int x, int y,
+                                               int z, int d, T c, T inv_c, T chat) {
+  T U[4];
+  load_rad_mapped(Um, G, x, y, z, U);
+  return face_side(U, d, c, inv_c, chat);
+}
+
+// ---------------------------------------------------------------------------
+// predictor: first-order HLL fluxes of U^m, half step, on the interior plus two ghost
+// layers of a 3D grid
+// ---------------------------------------------------------------------------
+//
+// Grid: (ntx + 1, ceil((n1 + 4)/BY), ceil((n2 + 4)/zc)) with ntx = ceil(n0/64). Block
+// (bx < ntx, by, bz) covers x in [64 bx, 64 bx + 64) within [0, n0), y in
+// [-2 + BY by, -2 + BY (by + 1)) within [-2, n1 + 2) and z in [-2 + zc bz, -2 + zc (bz + 1))
+// within [-2, n2 + 2). Block bx = ntx evaluates the four ghost columns x = -2, -1, n0,
+// n0 + 1 of the same y-z range cell by cell.
+
 template <typename T, int BY>
 struct PredictShared {
-  FaceSide<T> sx[BY][TILE_BX];
-  FaceSide<T> sy[BY][TILE_BX];
-  T sfx[BY][TILE_BX][4];
-  T sfy[BY][TILE_BX][4];
+  SideTile<T, BY, TILE_BX + 2> sx;  // [r][c]: x data of cell (x0 - 1 + c, y0 + r)
+  SideTile<T, BY + 2, TILE_BX> sy;  // [r][c]: y data of cell (x0 + c, y0 - 1 + r)
+  V4<T> fx[BY][TILE_BX + 1];        // [r][i]: flux through the low x face of (x0 + i, y0 + r)
+  V4<T> fy[BY + 1][TILE_BX];        // [j][c]: flux through the low y face of (x0 + c, y0 + j)
 };
 
-// One tile (bx, by, bz) of the predictor; called by every thread of the block.
 template <typename T, int BY>
 __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
                                                       const GasView<T>& gas, const Geom& G,
                                                       const RadConst<T>& K, T h, int zc, int bx,
                                                       int by, int bz, PredictShared<T, BY>& sh) {
-  constexpr int BX = TILE_BX, TX = BX - 2, TY = BY - 2;
-  auto& sx = sh.sx;
-  auto& sy = sh.sy;
-  auto& sfx = sh.sfx;
-  auto& sfy = sh.sfy;
+  static_assert(BY >= 2, "the extra work items need two wavefronts");
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
-  const int x = -2 + bx * TX + tx - 1;
-  const int y = -2 + by * TY + ty - 1;
-  const int xhi = G.n[0] + 2, yhi = G.n[1] + 2;
-  // stencil reads stay within [-3, n + 2] in every dimension
-  const int xl = x < xhi ? x : xhi;
-  const int yl = y < yhi ? y : yhi;
-  const bool out_xy = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && x < xhi && y < yhi;
+  const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+  const int ntx = (n0 + TILE_BX - 1) / TILE_BX;
+  const int y0 = -2 + by * BY;
   const int z0 = -2 + bz * zc;
-  const int z1 = min(z0 + zc, G.n[2] + 2);
+  const int z1 = min(z0 + zc, n2 + 2);
+  if (bx >= ntx) {
+    // the ghost columns, one cell per work item
+    const int ylim = min(y0 + BY, n1 + 2);
+    const int items = 4 * BY * (z1 - z0);
+    for (int e = tx + TILE_BX * ty; e < items; e += TILE_BX * BY) {
+      const int g = e & 3;
+      const int r = (e >> 2) % BY;
+      const int p = (e >> 2) / BY;
+      const int x = g < 2 ? g - 2 : n0 + g - 2;
+      if (y0 + r < ylim) rad_predict_cell(Um, Uh, gas, G, K, h, x, y0 + r, z0 + p);
+    }
+    return;
+  }
+  const int x0 = bx * TILE_BX;
+  const int x = x0 + tx, y = y0 + ty;
+  // every read stays within [-3, n + 2], where the boundary mapping is defined
+  const int xl = min(x, n0 + 2), yl = min(y, n1 + 2);
+  const bool out_xy = x < n0 && y < n1 + 2;
+  // extra items: wave 0 brings the y data of row y0 - 1; wave BY - 1 the y data of row
+  // y0 + BY and the high y faces; lanes < 2 BY of wave 1 the x data of cells x0 - 1 and
+  // x0 + 64 of row lane mod BY, and lanes < BY of wave 1 the high x faces
+  const int hrow = tx % BY;
+  const int xh = tx < BY ? x0 - 1 : min(x0 + TILE_BX, n0 + 2);
+  const int yh = min(y0 + hrow, n1 + 2);
+  const int ybot = y0 - 1, ytop = min(y0 + BY, n1 + 2);
   const T c = K.c, ic = K.inv_c, chat = K.chat;
 
-  FaceSide<T> zprev;
+  FaceSide<T> zprev;  // z data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
   T divprev[4] = {T(0), T(0), T(0), T(0)};
   for (int t = z0 - 1; t <= z1; ++t) {
     T U[4];
     load_rad_mapped(Um, G, xl, yl, t, U);
     const M1State<T> m = m1_state(U, ic, chat);
-    const bool xy = t >= z0 && t < z1;  // planes whose own update is produced
-    FaceSide<T> fxs, fys;
-    if (xy) {
-      fxs = side_dir(m, U, 0, c, ic, chat);
-      fys = side_dir(m, U, 1, c, ic, chat);
-      sx[ty][tx] = fxs;
-      sy[ty][tx] = fys;
-    }
+    // z face t-1/2, then plane t-1 is complete: its z faces are t-3/2 and t-1/2
     const FaceSide<T> fzs = side_dir(m, U, 2, c, ic, chat);
-    __syncthreads();
-    T fl[4] = {T(0), T(0), T(0), T(0)}, fb[4] = {T(0), T(0), T(0), T(0)};
-    if (xy) {
-      if (tx >= 1) hll(sx[ty][tx - 1], fxs, fl);
-      if (ty >= 1) hll(sy[ty - 1][tx], fys, fb);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        sfx[ty][tx][q] = fl[q];
-        sfy[ty][tx][q] = fb[q];
-      }
-    }
     T fz[4] = {T(0), T(0), T(0), T(0)};
     if (t > z0 - 1) hll(zprev, fzs, fz);
-    __syncthreads();
-    T div[4] = {T(0), T(0), T(0), T(0)};
-    if (xy && tx < BX - 1 && ty < BY - 1) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        div[q] = (sfx[ty][tx + 1][q] - fl[q]) * K.inv_w[0] + (sfy[ty + 1][tx][q] - fb[q]) * K.inv_w[1];
-    }
     if (t > z0 && out_xy) {
-      // plane t-1 is complete: its z faces are t-3/2 (fzprev) and t-1/2 (fz)
       T d[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
       int s[3];
-      const int a = mapped_cell(G, xl, yl, t - 1, s);
+      const int a = mapped_cell(G, x, y, t - 1, s);
       const Frozen<T> gz = frozen_at(gas, a, s, K.beta != 0);
       T out[4];
       bool ef, fc;
@@ -120,15 +187,44 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
     }
     zprev = fzs;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      fzprev[q] = fz[q];
-      divprev[q] = div[q];
+    for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
+    if (t >= z0 && t < z1) {
+      // x and y faces of plane t
+      sh.sx.put(ty, tx + 1, side_dir(m, U, 0, c, ic, chat));
+      sh.sy.put(ty + 1, tx, side_dir(m, U, 1, c, ic, chat));
+      if (ty == 0) sh.sy.put(0, tx, side_at(Um, G, xl, ybot, t, 1, c, ic, chat));
+      if (ty == BY - 1) sh.sy.put(BY + 1, tx, side_at(Um, G, xl, ytop, t, 1, c, ic, chat));
+      if (ty == 1 && tx < 2 * BY)
+        sh.sx.put(hrow, tx < BY ? 0 : TILE_BX + 1, side_at(Um, G, xh, yh, t, 0, c, ic, chat));
+      __syncthreads();
+      T fl[4], fb[4];
+      hll(sh.sx.get(ty, tx), sh.sx.get(ty, tx + 1), fl);
+      hll(sh.sy.get(ty, tx), sh.sy.get(ty + 1, tx), fb);
+      put4(sh.fx[ty][tx], fl);
+      put4(sh.fy[ty][tx], fb);
+      if (ty == 1 && tx < BY) {
+        T f[4];
+        hll(sh.sx.get(tx, TILE_BX), sh.sx.get(tx, TILE_BX + 1), f);
+        put4(sh.fx[tx][TILE_BX], f);
+      }
+      if (ty == BY - 1) {
+        T f[4];
+        hll(sh.sy.get(BY, tx), sh.sy.get(BY + 1, tx), f);
+        put4(sh.fy[BY][tx], f);
+      }
+      __syncthreads();
+      T fr[4], ft[4];
+      get4(sh.fx[ty][tx + 1], fr);
+      get4(sh.fy[ty + 1][tx], ft);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        divprev[q] = (fr[q] - fl[q]) * K.inv_w[0] + (ft[q] - fb[q]) * K.inv_w[1];
     }
   }
 }
 
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
                                                                    GasView<T> gas, Geom G,
                                                                    RadConst<T> K, T h, int zc) {
   __shared__ PredictShared<T, BY> sh;
@@ -136,137 +232,208 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_tile(RadPtrs<T> Um
                                int(blockIdx.z), sh);
 }
 
-// Corrector: MC-limited reconstruction of U^{m+1/2}, HLL fluxes, full step from U^m
-// with sources at U^{m+1/2}; U^{m+1} overwrites U^m on the interior of a 3D grid.
-// Grid: (ceil(nx/62), ceil(ny/(BY-2)), ceil(nz/zc)).
+// ---------------------------------------------------------------------------
+// corrector: MC-limited reconstruction of U^{m+1/2}, HLL fluxes, full step from U^m
+// with sources at U^{m+1/2}; U^{m+1} overwrites U^m on the interior of a 3D grid
+// ---------------------------------------------------------------------------
+//
+// Grid: (ceil(n0/64), ceil(n1/BY), ceil(n2/zc)); block (bx, by, bz) covers
+// x in [64 bx, 64 bx + 64), y in [BY by, BY (by + 1)), z in [zc bz, zc (bz + 1)), each
+// within [0, n). The current plane of U^{m+1/2} sits in LDS with a two-cell ring; the
+// ring's cells of the next plane are loaded while the current one is processed.
+
 template <typename T, int BY>
 struct CorrectShared {
-  T sU[BY + 2][TILE_BX + 2][4];   // U^{m+1/2} of plane t with a one-cell ring
-  FaceSide<T> sq[BY][TILE_BX];    // plus-side face data (x faces, then y faces)
-  T sf[BY][TILE_BX][4];           // left (x) then bottom (y) face fluxes
+  V4<T> U[BY + 4][TILE_BX + 4];  // [r][c]: U^{m+1/2} of cell (x0 - 2 + c, y0 - 2 + r)
+  V4<T> fx[BY][TILE_BX + 1];     // [r][i]: flux through the low x face of (x0 + i, y0 + r)
+  V4<T> fy[BY + 1][TILE_BX];     // [j][c]: flux through the low y face of (x0 + c, y0 + j)
 };
 
-// One tile (bx, by, bz) of the corrector; called by every thread of the block.
+template <int BY>
+struct CorrectRing {
+  static constexpr int W = TILE_BX + 4;
+  static constexpr int cells = 4 * W + 4 * BY;  // two rows below and above, two columns each side
+  static constexpr int per_thread = (cells + TILE_BX * BY - 1) / (TILE_BX * BY);
+  // LDS position (row r, column c) of ring cell e
+  __host__ __device__ static void rc(int e, int& r, int& c) {
+    if (e < 4 * W) {
+      const int q = e / W;
+      c = e - q * W;
+      r = q < 2 ? q : BY + q;
+    } else {
+      const int k = e - 4 * W;
+      const int s = k & 3;
+      c = s < 2 ? s : TILE_BX + s;
+      r = 2 + (k >> 2);
+    }
+  }
+};
+
+// MC-limited face states of a cell with neighbours um (below) and up (above) along one
+// direction: lo on its low face, hi on its high face; s is the limited slope.
+template <typename T>
+__device__ __forceinline__ void mc_states(const T um[4], const T u[4], const T up[4], T lo[4],
+                                          T hi[4], T s[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    s[q] = mc_slope(u[q] - um[q], up[q] - u[q]);
+    lo[q] = u[q] - T(0.5) * s[q];
+    hi[q] = u[q] + T(0.5) * s[q];
+  }
+}
+
+// HLL flux through the face between cells b and c of the row a, b, c, d along direction
+// dir, from the MC-limited states of b (high side) and c (low side).
+template <typename T>
+__device__ __forceinline__ void face_flux4(const T a[4], const T b[4], const T cc[4], const T d[4],
+                                           int dir, T c, T ic, T chat, T f[4]) {
+  T lo[4], hi[4], s[4], bh[4], cl[4];
+  mc_states(a, b, cc, lo, bh, s);
+  mc_states(b, cc, d, cl, hi, s);
+  hll(face_side(bh, dir, c, ic, chat), face_side(cl, dir, c, ic, chat), f);
+}
+
 template <typename T, int BY>
 __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
                                                       const GasView<T>& gas, const Geom& G,
                                                       const RadConst<T>& K, T h, int zc, int bx,
                                                       int by, int bz, unsigned long long* ctr,
                                                       CorrectShared<T, BY>& sh) {
-  constexpr int BX = TILE_BX, TX = BX - 2, TY = BY - 2;
-  constexpr int RX = BX + 2, RY = BY + 2;
-  auto& sU = sh.sU;
-  auto& sq = sh.sq;
-  auto& sf = sh.sf;
+  using Ring = CorrectRing<BY>;
+  constexpr int RP = Ring::per_thread;
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
-  const int tid = tx + BX * ty;
+  const int tid = tx + TILE_BX * ty;
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
-  const int x0 = bx * TX, y0 = by * TY;
-  const int x = x0 + tx - 1, y = y0 + ty - 1;
-  const bool out_xy = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && x < n0 && y < n1;
+  const int x0 = bx * TILE_BX, y0 = by * BY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool out_xy = x < n0 && y < n1;
   const int z0 = bz * zc;
   const int z1 = min(z0 + zc, n2);
-  // the half-step arrays hold valid values on [-2, n + 2)
-  const int xl = clamp_i(x, -2, n0 + 1), yl = clamp_i(y, -2, n1 + 1);
-  const int zstride = G.ps[0] * G.ps[1];
-  const int pcol = padded_cell(G, xl, yl, 0);
+  const int zs = G.ps[0] * G.ps[1];
+  // the half-step arrays hold valid values on [-2, n + 2) in every dimension
+  const int pcol = padded_cell(G, clamp_i(x, -2, n0 + 1), clamp_i(y, -2, n1 + 1), 0);
+  int rpos[RP], rcol[RP];
+#pragma unroll
+  for (int s = 0; s < RP; ++s) {
+    const int e = tid + s * TILE_BX * BY;
+    rpos[s] = -1;
+    rcol[s] = 0;
+    if (e < Ring::cells) {
+      int r, c;
+      Ring::rc(e, r, c);
+      rpos[s] = r * (TILE_BX + 4) + c;
+      rcol[s] = padded_cell(G, clamp_i(x0 - 2 + c, -2, n0 + 1), clamp_i(y0 - 2 + r, -2, n1 + 1), 0);
+    }
+  }
   const T c = K.c, ic = K.inv_c, chat = K.chat;
+  V4<T>* const sUf = &sh.U[0][0];
 
-  T Uzm[4], Uz0[4], Uzp[4];
-  load_padded4(Uh, pcol + (z0 - 2) * zstride, Uzm);
-  load_padded4(Uh, pcol + (z0 - 1) * zstride, Uz0);
-  FaceSide<T> zplus;  // plus-z face data of plane t-1
+  T Uzm[4], Uz0[4], Uzp[4], Upp[4];
+  load_padded4(Uh, pcol + (z0 - 2) * zs, Uzm);
+  load_padded4(Uh, pcol + (z0 - 1) * zs, Uz0);
+  load_padded4(Uh, pcol + z0 * zs, Uzp);
+  T ring[RP][4];
+#pragma unroll
+  for (int s = 0; s < RP; ++s)
+    if (rpos[s] >= 0) load_padded4(Uh, rcol[s] + z0 * zs, ring[s]);
+  FaceSide<T> zplus;  // high-z face data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
   T divprev[4] = {T(0), T(0), T(0), T(0)};
-  T Uhprev[4] = {T(0), T(0), T(0), T(0)};
   unsigned long long nef = 0, nfc = 0;
   for (int t = z0 - 1; t <= z1; ++t) {
-    load_padded4(Uh, pcol + (t + 1) * zstride, Uzp);
-    for (int idx = tid; idx < RX * RY; idx += BX * BY) {
-      const int ix = idx % RX, iy = idx / RX;
-      const int gx = clamp_i(x0 - 2 + ix, -2, n0 + 1);
-      const int gy = clamp_i(y0 - 2 + iy, -2, n1 + 1);
-      const int p = padded_cell(G, gx, gy, t);
-      sU[iy][ix][0] = Uh.E[p];
-      sU[iy][ix][1] = Uh.F[0][p];
-      sU[iy][ix][2] = Uh.F[1][p];
-      sU[iy][ix][3] = Uh.F[2][p];
-    }
-    __syncthreads();
-    const bool xy = t >= z0 && t < z1;
-    // limited slopes and the face states of this cell
-    T mx[4], px[4], my[4], py[4], mz[4], pz[4];
+    const bool plane = t >= z0 && t < z1;  // planes whose x and y faces are needed
+    if (plane) {
+      put4(sh.U[ty + 2][tx + 2], Uz0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T u = Uz0[q];
-      const T sxq = mc_slope(u - sU[ty + 1][tx][q], sU[ty + 1][tx + 2][q] - u);
-      const T syq = mc_slope(u - sU[ty][tx + 1][q], sU[ty + 2][tx + 1][q] - u);
-      const T szq = mc_slope(u - Uzm[q], Uzp[q] - u);
-      mx[q] = u - T(0.5) * sxq;
-      px[q] = u + T(0.5) * sxq;
-      my[q] = u - T(0.5) * syq;
-      py[q] = u + T(0.5) * syq;
-      mz[q] = u - T(0.5) * szq;
-      pz[q] = u + T(0.5) * szq;
-    }
-    T fl[4] = {T(0), T(0), T(0), T(0)}, fb[4] = {T(0), T(0), T(0), T(0)}, fr[4] = {T(0), T(0), T(0), T(0)};
-    if (xy) sq[ty][tx] = face_side(px, 0, c, ic, chat);
-    __syncthreads();
-    if (xy && tx >= 1) hll(sq[ty][tx - 1], face_side(mx, 0, c, ic, chat), fl);
-    __syncthreads();
-    if (xy) {
-      sq[ty][tx] = face_side(py, 1, c, ic, chat);
+      for (int s = 0; s < RP; ++s)
+        if (rpos[s] >= 0) put4(sUf[rpos[s]], ring[s]);
+      if (t + 1 < z1) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sf[ty][tx][q] = fl[q];
-    }
-    __syncthreads();
-    if (xy) {
-      if (tx < BX - 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fr[q] = sf[ty][tx + 1][q];
+        for (int s = 0; s < RP; ++s)
+          if (rpos[s] >= 0) load_padded4(Uh, rcol[s] + (t + 1) * zs, ring[s]);
       }
-      if (ty >= 1) hll(sq[ty - 1][tx], face_side(my, 1, c, ic, chat), fb);
     }
-    __syncthreads();
-    if (xy) {
+    if (t < z1) load_padded4(Uh, pcol + (t + 2) * zs, Upp);
+    // z: limited states of the own cell; the low z face pairs them with plane t-1
+    {
+      T mz[4], pz[4], sz[4];
+      mc_states(Uzm, Uz0, Uzp, mz, pz, sz);
+      T fz[4] = {T(0), T(0), T(0), T(0)};
+      if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, chat), fz);
+      if (t > z0 && out_xy) {
+        // plane t-1 is complete: its z faces are t-3/2 (fzprev) and t-1/2 (fz)
+        T d[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sf[ty][tx][q] = fb[q];
+        for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
+        const int a = x + n0 * (y + n1 * (t - 1));
+        const int s[3] = {1, 1, 1};
+        const Frozen<T> gz = frozen_at(gas, a, s, K.beta != 0);
+        T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+        T out[4];
+        bool ef, fc;
+        rad_update(K, h, Uo, Uzm, d, gz, out, ef, fc);
+        nef += ef ? 1ull : 0ull;
+        nfc += fc ? 1ull : 0ull;
+        Um.E[a] = out[0];
+        Um.F[0][a] = out[1];
+        Um.F[1][a] = out[2];
+        Um.F[2][a] = out[3];
+      }
+      if (t < z1) zplus = face_side(pz, 2, c, ic, chat);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     }
-    __syncthreads();
-    T div[4] = {T(0), T(0), T(0), T(0)};
-    if (xy && tx < BX - 1 && ty < BY - 1) {
+    if (plane) {
+      __syncthreads();
+      T fl[4], fb[4];
+      {
+        T a[4], b[4], d[4];
+        get4(sh.U[ty + 2][tx], a);
+        get4(sh.U[ty + 2][tx + 1], b);
+        get4(sh.U[ty + 2][tx + 3], d);
+        face_flux4(a, b, Uz0, d, 0, c, ic, chat, fl);
+      }
+      {
+        T a[4], b[4], d[4];
+        get4(sh.U[ty][tx + 2], a);
+        get4(sh.U[ty + 1][tx + 2], b);
+        get4(sh.U[ty + 3][tx + 2], d);
+        face_flux4(a, b, Uz0, d, 1, c, ic, chat, fb);
+      }
+      put4(sh.fx[ty][tx], fl);
+      put4(sh.fy[ty][tx], fb);
+      if (ty == 0 && tx < BY) {
+        // high x face of row tx: cells x0 + 62 ... x0 + 65
+        T a[4], b[4], cc[4], d[4], f[4];
+        get4(sh.U[tx + 2][TILE_BX], a);
+        get4(sh.U[tx + 2][TILE_BX + 1], b);
+        get4(sh.U[tx + 2][TILE_BX + 2], cc);
+        get4(sh.U[tx + 2][TILE_BX + 3], d);
+        face_flux4(a, b, cc, d, 0, c, ic, chat, f);
+        put4(sh.fx[tx][TILE_BX], f);
+      }
+      if (ty == BY - 1) {
+        // high y face of column tx: rows y0 + BY - 2 ... y0 + BY + 1
+        T a[4], cc[4], d[4], f[4];
+        get4(sh.U[BY][tx + 2], a);
+        get4(sh.U[BY + 2][tx + 2], cc);
+        get4(sh.U[BY + 3][tx + 2], d);
+        face_flux4(a, Uz0, cc, d, 1, c, ic, chat, f);
+        put4(sh.fy[BY][tx], f);
+      }
+      __syncthreads();
+      T fr[4], ft[4];
+      get4(sh.fx[ty][tx + 1], fr);
+      get4(sh.fy[ty + 1][tx], ft);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        div[q] = (fr[q] - fl[q]) * K.inv_w[0] + (sf[ty + 1][tx][q] - fb[q]) * K.inv_w[1];
+        divprev[q] = (fr[q] - fl[q]) * K.inv_w[0] + (ft[q] - fb[q]) * K.inv_w[1];
     }
-    T fz[4] = {T(0), T(0), T(0), T(0)};
-    if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, chat), fz);
-    if (t > z0 && out_xy) {
-      T d[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
-      const int a = x + n0 * (y + n1 * (t - 1));
-      const int s[3] = {1, 1, 1};
-      const Frozen<T> gz = frozen_at(gas, a, s, K.beta != 0);
-      T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
-      T out[4];
-      bool ef, fc;
-      rad_update(K, h, Uo, Uhprev, d, gz, out, ef, fc);
-      nef += ef ? 1ull : 0ull;
-      nfc += fc ? 1ull : 0ull;
-      Um.E[a] = out[0];
-      Um.F[0][a] = out[1];
-      Um.F[1][a] = out[2];
-      Um.F[2][a] = out[3];
-    }
-    if (t < z1) zplus = face_side(pz, 2, c, ic, chat);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      fzprev[q] = fz[q];
-      divprev[q] = div[q];
-      Uhprev[q] = Uz0[q];
       Uzm[q] = Uz0[q];
       Uz0[q] = Uzp[q];
+      Uzp[q] = Upp[q];
     }
   }
   wave_add(ctr + CTR_RAD_EFLOOR, nef);
@@ -283,6 +450,28 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um
                                int(blockIdx.z), ctr, sh);
 }
 
+// Tile counts of the two launches for a grid n and requested chunk length zc, with the
+// rebalanced chunk lengths they use.
+struct TileGrid {
+  int pred[3], corr[3];
+  int zc_pred, zc_corr;
+};
+
+template <int BY>
+__host__ __device__ inline TileGrid tile_grid(const int n[3], int zc) {
+  TileGrid g;
+  const int ntx = (n[0] + TILE_BX - 1) / TILE_BX;
+  g.zc_pred = balanced_chunk(n[2] + 4, zc);
+  g.zc_corr = balanced_chunk(n[2], zc);
+  g.pred[0] = ntx + 1;
+  g.pred[1] = (n[1] + 4 + BY - 1) / BY;
+  g.pred[2] = (n[2] + 4 + g.zc_pred - 1) / g.zc_pred;
+  g.corr[0] = ntx;
+  g.corr[1] = (n[1] + BY - 1) / BY;
+  g.corr[2] = (n[2] + g.zc_corr - 1) / g.zc_corr;
+  return g;
+}
+
 // ---------------------------------------------------------------------------
 // many independent solves in one launch: a packed list of tiles
 // ---------------------------------------------------------------------------
@@ -295,33 +484,34 @@ struct SolveDesc {
   Geom G;
   RadConst<T> K;
   T h_pred, h_corr;
+  int zc_pred, zc_corr;
   unsigned long long* ctr;
 };
 
 // Tile i of a launch is (solve, bx, by, bz) = tiles[i]; blocks past ntiles exit at once,
 // so one grid size serves every round.
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_predict_batch(const SolveDesc<T>* __restrict__ sd,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_rad_predict_batch(const SolveDesc<T>* __restrict__ sd,
                                                                     const int4* __restrict__ tiles,
-                                                                    const int* __restrict__ ntiles,
-                                                                    int zc) {
+                                                                    const int* __restrict__ ntiles) {
   if (int(blockIdx.x) >= *ntiles) return;
   const int4 tr = tiles[blockIdx.x];
   const SolveDesc<T> d = sd[tr.x];
   __shared__ PredictShared<T, BY> sh;
-  rad_predict_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_pred, zc, tr.y, tr.z, tr.w, sh);
+  rad_predict_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_pred, d.zc_pred, tr.y, tr.z, tr.w,
+                               sh);
 }
 
 template <typename T, int BY>
 __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_batch(const SolveDesc<T>* __restrict__ sd,
                                                                     const int4* __restrict__ tiles,
-                                                                    const int* __restrict__ ntiles,
-                                                                    int zc) {
+                                                                    const int* __restrict__ ntiles) {
   if (int(blockIdx.x) >= *ntiles) return;
   const int4 tr = tiles[blockIdx.x];
   const SolveDesc<T> d = sd[tr.x];
   __shared__ CorrectShared<T, BY> sh;
-  rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, zc, tr.y, tr.z, tr.w, d.ctr, sh);
+  rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, d.zc_corr, tr.y, tr.z, tr.w,
+                               d.ctr, sh);
 }
 
 }  // namespace rhdk

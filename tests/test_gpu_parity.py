@@ -76,6 +76,19 @@ def rhd3d_mixed_bc_beta_tau(precision):
 
 
 @case
+def rhd3d_two_full_x_tiles(precision):
+    """128 cells in x: two full 64-wide tiles, so the faces on a tile edge (inside the
+    grid and at a reflecting wall) come from the extra work items of the tiled kernels."""
+    spec = ri.default_spec(nx=128, ny=9, nz=6, dx=1 / 128, dy=1 / 9, dz=1 / 6, c_light=40.0,
+                           exchange="full", beta_tau=True, theta_E=0.51, theta_F=0.51,
+                           bc=("reflect", "reflect", "outflow", "outflow", "periodic", "periodic"),
+                           precision=precision)
+    st = ri.smooth_random_state(spec, seed=8, amp=0.1, f_amp=0.4, kappa=(1.0, 4.0), v_amp=0.2,
+                                with_j=True)
+    return spec, st, 12.0, 2
+
+
+@case
 def rad_only_absorb_2d_wave(precision):
     pb = ri.radiation_wave(2, 16)
     spec = dict(pb["spec"], precision=precision)

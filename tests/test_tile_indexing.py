@@ -29,73 +29,128 @@ def map_index(q, n, lo, hi):
     return out
 
 
+def balanced_chunk(L, zc):
+    chunks = (L + zc - 1) // zc
+    return (L + chunks - 1) // chunks
+
+
+def ring_rc(e, BY):
+    """LDS (row, column) of ring cell e of the corrector's plane buffer."""
+    W = BX + 4
+    if e < 4 * W:
+        q, c = divmod(e, W)
+        return (q if q < 2 else BY + q), c
+    k = e - 4 * W
+    s = k & 3
+    return 2 + (k >> 2), (s if s < 2 else BX + s)
+
+
 def replay(n, bc, BY, zc):
     n0, n1, n2 = n
-    TX, TY = BX - 2, BY - 2
     N = n0 * n1 * n2
     ps = (n0 + 4, n1 + 4, n2 + 4)
     NP = ps[0] * ps[1] * ps[2]
     padded = lambda x, y, z: (x + 2) + ps[0] * ((y + 2) + ps[1] * (z + 2))
     mapped = lambda x, y, z: (map_index(x, n0, bc[0], bc[1])
                               + n0 * (map_index(y, n1, bc[2], bc[3]) + n1 * map_index(z, n2, bc[4], bc[5])))
+
+    def check_mapped(x, y, z):
+        for q, lim in ((x, n0), (y, n1), (z, n2)):
+            q = np.asarray(q)
+            assert q.min() >= -3 and q.max() <= lim + 2, "boundary mapping defined on [-3, n + 2]"
+        a = mapped(x, y, z)
+        assert a.min() >= 0 and a.max() < N
+
     ty, tx = np.meshgrid(np.arange(BY), np.arange(BX), indexing="ij")
     tx, ty = tx.ravel(), ty.ravel()
+    ntx = (n0 + BX - 1) // BX
+    zcp, zcc = balanced_chunk(n2 + 4, zc), balanced_chunk(n2, zc)
+    assert zcp <= zc and zcc <= zc
 
-    # predictor
+    # predictor: main tiles and the ghost-column blocks
     writes = np.zeros(NP, dtype=np.int64)
-    grid = ((n0 + 4 + TX - 1) // TX, (n1 + 4 + TY - 1) // TY, (n2 + 4 + zc - 1) // zc)
+    grid = (ntx + 1, (n1 + 4 + BY - 1) // BY, (n2 + 4 + zcp - 1) // zcp)
     for bz in range(grid[2]):
         for by in range(grid[1]):
+            y0 = -2 + by * BY
+            z0 = -2 + bz * zcp
+            z1 = min(z0 + zcp, n2 + 2)
             for bx in range(grid[0]):
-                x = -2 + bx * TX + tx - 1
-                y = -2 + by * TY + ty - 1
-                xl = np.minimum(x, n0 + 2)
-                yl = np.minimum(y, n1 + 2)
-                out_xy = (tx >= 1) & (tx <= TX) & (ty >= 1) & (ty <= TY) & (x < n0 + 2) & (y < n1 + 2)
-                z0 = -2 + bz * zc
-                z1 = min(z0 + zc, n2 + 2)
+                if bx >= ntx:
+                    ylim = min(y0 + BY, n1 + 2)
+                    e = np.arange(4 * BY * (z1 - z0))
+                    g, r, pl = e & 3, (e >> 2) % BY, (e >> 2) // BY
+                    x = np.where(g < 2, g - 2, n0 + g - 2)
+                    keep = y0 + r < ylim
+                    x, yy, zz = x[keep], (y0 + r)[keep], (z0 + pl)[keep]
+                    if x.size:
+                        for dx, dy, dz in ((0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0),
+                                           (0, 0, -1), (0, 0, 1)):
+                            check_mapped(x + dx, yy + dy, zz + dz)
+                        np.add.at(writes, padded(x, yy, zz), 1)
+                    continue
+                x0 = bx * BX
+                x, y = x0 + tx, y0 + ty
+                xl, yl = np.minimum(x, n0 + 2), np.minimum(y, n1 + 2)
+                out_xy = (x < n0) & (y < n1 + 2)
+                # a closure that feeds a face of an output cell is never clamped
+                need = (x <= n0) & (y <= n1 + 2)
+                assert np.array_equal(xl[need], x[need]) and np.array_equal(yl[need], y[need])
+                hrow = tx % BY
+                xh = np.where(tx < BY, x0 - 1, np.minimum(x0 + BX, n0 + 2))
+                yh = np.minimum(y0 + hrow, n1 + 2)
+                ybot, ytop = y0 - 1, min(y0 + BY, n1 + 2)
                 for t in range(z0 - 1, z1 + 1):
-                    a = mapped(xl, yl, t)
-                    assert a.min() >= 0 and a.max() < N
+                    check_mapped(xl, yl, t)
                     if t > z0:
-                        a2 = mapped(xl, yl, t - 1)
-                        assert a2.min() >= 0 and a2.max() < N
+                        check_mapped(x[out_xy], y[out_xy], t - 1)
                         p = padded(x[out_xy], y[out_xy], t - 1)
-                        assert p.min() >= 0 and p.max() < NP
                         np.add.at(writes, p, 1)
-    region = np.zeros(ps[::-1], dtype=np.int64)
-    region[...] = 1
-    assert np.array_equal(writes.reshape(ps[::-1]), region), "predictor writes each padded cell once"
+                    if z0 <= t < z1:
+                        w0 = ty == 0
+                        check_mapped(xl[w0], np.full(w0.sum(), ybot), t)
+                        w1 = ty == BY - 1
+                        check_mapped(xl[w1], np.full(w1.sum(), ytop), t)
+                        wh = (ty == 1) & (tx < 2 * BY)
+                        check_mapped(xh[wh], yh[wh], t)
+                        assert sorted(zip(hrow[wh], tx[wh] < BY)) == sorted(
+                            [(r, True) for r in range(BY)] + [(r, False) for r in range(BY)])
+    assert np.all(writes == 1), "predictor writes each padded cell once"
 
     # corrector
     writes = np.zeros(N, dtype=np.int64)
-    grid = ((n0 + TX - 1) // TX, (n1 + TY - 1) // TY, (n2 + zc - 1) // zc)
-    RX, RY = BX + 2, BY + 2
+    grid = (ntx, (n1 + BY - 1) // BY, (n2 + zcc - 1) // zcc)
+    W = BX + 4
+    ring_cells = 4 * W + 4 * BY
+    slots = np.zeros((BY + 4) * W, dtype=np.int64)
+    for e in range(ring_cells):
+        r, c = ring_rc(e, BY)
+        slots[r * W + c] += 1
+    slots[((ty + 2) * W + tx + 2)] += 1
+    assert np.all(slots == 1), "ring and interior fill every LDS slot of a plane once"
     for bz in range(grid[2]):
         for by in range(grid[1]):
             for bx in range(grid[0]):
-                x0, y0 = bx * TX, by * TY
-                x = x0 + tx - 1
-                y = y0 + ty - 1
-                out_xy = (tx >= 1) & (tx <= TX) & (ty >= 1) & (ty <= TY) & (x < n0) & (y < n1)
-                z0 = bz * zc
-                z1 = min(z0 + zc, n2)
-                xl = np.clip(x, -2, n0 + 1)
-                yl = np.clip(y, -2, n1 + 1)
-                for t in [z0 - 2, z0 - 1] + list(range(z0, z1 + 2)):
+                x0, y0 = bx * BX, by * BY
+                x, y = x0 + tx, y0 + ty
+                out_xy = (x < n0) & (y < n1)
+                z0 = bz * zcc
+                z1 = min(z0 + zcc, n2)
+                xl, yl = np.clip(x, -2, n0 + 1), np.clip(y, -2, n1 + 1)
+                need = (x <= n0) & (y <= n1)
+                assert np.array_equal(xl[need], x[need]) and np.array_equal(yl[need], y[need])
+                ring = [ring_rc(e, BY) for e in range(ring_cells)]
+                gx = np.clip(np.array([x0 - 2 + c for r, c in ring]), -2, n0 + 1)
+                gy = np.clip(np.array([y0 - 2 + r for r, c in ring]), -2, n1 + 1)
+                for t in range(z0 - 2, z1 + 2):
                     p = padded(xl, yl, t)
                     assert p.min() >= 0 and p.max() < NP, (t, z0, z1)
-                for t in range(z0 - 1, z1 + 1):
-                    idx = np.arange(RX * RY)
-                    gx = np.clip(x0 - 2 + idx % RX, -2, n0 + 1)
-                    gy = np.clip(y0 - 2 + idx // RX, -2, n1 + 1)
+                for t in range(z0, z1):
                     p = padded(gx, gy, t)
                     assert p.min() >= 0 and p.max() < NP
-                    if t > z0:
-                        a = x[out_xy] + n0 * (y[out_xy] + n1 * (t - 1))
-                        if a.size:
-                            assert a.min() >= 0 and a.max() < N
-                        np.add.at(writes, a, 1)
+                for t in range(z0 + 1, z1 + 1):
+                    a = x[out_xy] + n0 * (y[out_xy] + n1 * (t - 1))
+                    np.add.at(writes, a, 1)
     assert np.all(writes == 1), "corrector writes each interior cell once"
 
 
@@ -106,7 +161,9 @@ def replay(n, bc, BY, zc):
     ((3, 3, 3), (2, 2, 2, 2, 2, 2)),
     ((2, 5, 2), (0, 0, 1, 1, 0, 0)),
     ((128, 17, 33), (0, 0, 2, 2, 1, 1)),
+    ((64, 16, 9), (2, 2, 1, 1, 0, 0)),
+    ((130, 4, 3), (1, 1, 0, 0, 2, 2)),
 ])
-@pytest.mark.parametrize("BY,zc", [(4, 16), (8, 16), (16, 5), (8, 1)])
+@pytest.mark.parametrize("BY,zc", [(4, 16), (8, 16), (16, 5), (8, 1), (4, 7)])
 def test_tiled_kernel_indexing(n, bc, BY, zc):
     replay(n, bc, BY, zc)
