@@ -200,7 +200,7 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
 
 /* Select the kernels of the radiation subcycle: variant RHD_KERNELS_*, tile_rows the
    rows of a 64-wide tile (4, 8 or 16; FP64 handles 4 or 8), zchunk the z-planes one tile
-   walks (>= 1). Defaults after rhd_create: tiled, 8 rows, 16 planes. Results do not
+   walks (>= 1). Defaults after rhd_create: tiled, 8 rows, 8 planes. Results do not
    depend on the choice beyond rounding. RHD_EINVAL for values outside these sets. */
 int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk);
 

@@ -272,7 +272,7 @@ def rhd_get_timing(h):
     return t.as_dict()
 
 
-def rhd_set_kernel_variant(h, variant, tile_rows=8, zchunk=16):
+def rhd_set_kernel_variant(h, variant, tile_rows=8, zchunk=8):
     _check(lib().rhd_set_kernel_variant(h, int(variant), int(tile_rows), int(zchunk)), h)
 
 
@@ -289,7 +289,7 @@ def _bcheck(rc, b=None):
         raise RhdError(rc, lib().rhd_batch_last_error(b).decode(errors="replace"))
 
 
-def rhd_batch_create(max_solves, tile_rows=8, zchunk=16, stream=None):
+def rhd_batch_create(max_solves, tile_rows=8, zchunk=8, stream=None):
     b = ctypes.c_void_p()
     _bcheck(lib().rhd_batch_create(ctypes.c_void_p(stream) if stream else None, int(max_solves),
                                    int(tile_rows), int(zchunk), ctypes.byref(b)))
@@ -423,7 +423,7 @@ class Solver:
     def step(self, dt_gas, chat, nsub):
         rhd_step(self.h, dt_gas, chat, nsub)
 
-    def set_kernel_variant(self, variant, tile_rows=8, zchunk=16):
+    def set_kernel_variant(self, variant, tile_rows=8, zchunk=8):
         rhd_set_kernel_variant(self.h, variant, tile_rows, zchunk)
 
     def autotune(self, chat, dt_rad, reps=3):

@@ -100,7 +100,7 @@ struct rhd {
   bool in_batch = false;
   int variant = RHD_KERNELS_TILED;
   int tile_rows = 8;
-  int zchunk = 16;
+  int zchunk = 8;
   Timer timer;
   char err[512] = "no error";
 };
@@ -735,7 +735,7 @@ int autotune_impl(rhd_t* h, double chat, double dt_rad, int reps) {
   cands[nc++] = {RHD_KERNELS_PER_CELL, 8, 16};
   if (three_d) {
     const int rows_list[3] = {4, 8, 16};
-    const int zc_list[4] = {8, 16, 32, 64};
+    const int zc_list[4] = {6, 8, 12, 16};
     for (int r : rows_list) {
       if (r == 16 && !h->mixed) continue;
       for (int z : zc_list) cands[nc++] = {RHD_KERNELS_TILED, r, z};
@@ -1111,7 +1111,7 @@ struct rhd_batch {
   bool own_stream = false;
   int max_solves = 0;
   int rows = 8;
-  int zchunk = 16;
+  int zchunk = 8;
   int precision = -1;  // -1 unset, 0 FP64, 1 mixed
   std::vector<rhd_t*> members;
   std::vector<double> chat;

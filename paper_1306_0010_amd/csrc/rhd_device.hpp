@@ -137,16 +137,29 @@ template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T>
 __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+// IEEE minNum / maxNum: one v_min / v_max (or a v_min3 / v_max3 for a nest), for values
+// that are finite by construction.
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
 
-// Monotonised-central limited slope.
-template <typename T>
-__device__ __forceinline__ T mc_slope(T dm, T dp) {
-  if (dm * dp <= T(0)) return T(0);
-  T a = fabs(T(0.5) * (dm + dp));
-  T b = T(2) * fabs(dm);
-  T e = T(2) * fabs(dp);
-  T m = tmin(a, tmin(b, e));
-  return dm > T(0) ? m : -m;
+// Monotonised-central limited slope: minmod(2 dm, 2 dp, (dm + dp)/2), zero unless the
+// one-sided differences dm and dp share a sign.
+__device__ __forceinline__ double mc_slope(double dm, double dp) {
+  if (dm * dp <= 0.0) return 0.0;
+  const double a = fabs(0.5 * (dm + dp));
+  const double b = 2.0 * fabs(dm);
+  const double e = 2.0 * fabs(dp);
+  const double m = tmin(a, tmin(b, e));
+  return dm > 0.0 ? m : -m;
+}
+
+// FP32: minmod(a, b) is the median of (a, b, 0), and the three-argument minmod is
+// minmod(a, minmod(b, c)), so the limiter is two v_med3_f32 with no branch.
+__device__ __forceinline__ float mc_slope(float dm, float dp) {
+  const float inner = __builtin_amdgcn_fmed3f(2.0f * dp, 0.5f * (dm + dp), 0.0f);
+  return __builtin_amdgcn_fmed3f(2.0f * dm, inner, 0.0f);
 }
 
 // Sum of v over the wavefront; lane 0 adds it to *ctr. Every lane must call it.
@@ -214,11 +227,20 @@ __device__ __forceinline__ M1State<T> m1_state(const T U[4], T inv_c, T chat) {
     m.f[2] *= r;
     ff = T(1);
   }
-  m.s = sqrt_(T(4) - T(3) * ff);
-  const T two_s = T(2) + m.s;
-  const T r2 = rcp(m.s * two_s);
-  m.dir = T(3) * m.s * r2;
-  m.chat_s = chat * two_s * r2;
+  const T q = T(4) - T(3) * ff;  // s^2, in [1, 4]
+  if constexpr (sizeof(T) == 4) {
+    // one reciprocal square root gives s and 1/s, one reciprocal 3/(2 + s)
+    const T rs = rsqrt_(q);
+    m.s = q * rs;
+    m.dir = T(3) * rcp(T(2) + m.s);
+    m.chat_s = chat * rs;
+  } else {
+    m.s = sqrt_(q);
+    const T two_s = T(2) + m.s;
+    const T r2 = rcp(m.s * two_s);
+    m.dir = T(3) * m.s * r2;
+    m.chat_s = chat * two_s * r2;
+  }
   m.iso = (m.s - T(1)) * T(1.0 / 3.0);
   return m;
 }
@@ -232,14 +254,14 @@ template <typename T>
 __device__ __forceinline__ void m1_dir(const M1State<T>& m, int d, T c, T inv_c, T chat,
                                        T Phi[4], T& lmin, T& lmax) {
   const T fd = d == 0 ? m.f[0] : (d == 1 ? m.f[1] : m.f[2]);
-  const T scale = chat * c * m.E;
+  const T scale = (chat * c) * m.E;
   const T a = m.dir * fd;
-  Phi[0] = chat * m.F[d] * inv_c;
+  Phi[0] = (chat * inv_c) * m.F[d];
   Phi[1] = scale * (a * m.f[0] + (d == 0 ? m.iso : T(0)));
   Phi[2] = scale * (a * m.f[1] + (d == 1 ? m.iso : T(0)));
   Phi[3] = scale * (a * m.f[2] + (d == 2 ? m.iso : T(0)));
   T rad = T(2.0 / 3.0) * (m.s - T(1)) * (m.s - a * fd);
-  rad = tmax(rad, T(0));
+  rad = vmax(rad, T(0));
   const T r = sqrt_(rad);
   lmin = (fd - r) * m.chat_s;
   lmax = (fd + r) * m.chat_s;
@@ -268,8 +290,8 @@ __device__ __forceinline__ FaceSide<T> face_side(const T U[4], int d, T c, T inv
 // S_R = max(lambda_3(U_L), lambda_3(U_R)); the central flux when both bounds vanish.
 template <typename T>
 __device__ __forceinline__ void hll(const FaceSide<T>& L, const FaceSide<T>& R, T flux[4]) {
-  const T SLm = tmin(tmin(L.lmin, R.lmin), T(0));
-  const T SRp = tmax(tmax(L.lmax, R.lmax), T(0));
+  const T SLm = vmin(vmin(L.lmin, R.lmin), T(0));
+  const T SRp = vmax(vmax(L.lmax, R.lmax), T(0));
   const T den = SRp - SLm;
   if (den > T(0)) {
     const T id = rcp(den);
@@ -299,23 +321,63 @@ struct Frozen {
   T j;
 };
 
+// The gas data of one cell as loaded, before any arithmetic, so that a load can be
+// issued well ahead of its use; neg has bit d set where a reflecting boundary flips v_d.
 template <typename T>
-__device__ __forceinline__ Frozen<T> frozen_at(const GasView<T>& g, int a, const int s[3],
-                                               bool need_v) {
-  Frozen<T> fz;
-  const T rho = g.rho[a];
-  fz.rkF = rho * (g.kF ? g.kF[a] : g.kF_s);
-  fz.rkP = rho * (g.kP ? g.kP[a] : g.kP_s);
+struct FrozenRaw {
+  T rho, kF, kP, m[3], j;
+  int neg;
+};
+
+__device__ __forceinline__ int neg_mask(const int s[3]) {
+  return (s[0] < 0 ? 1 : 0) | (s[1] < 0 ? 2 : 0) | (s[2] < 0 ? 4 : 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T flip(T v, int neg, int bit) {
+  return (neg & bit) ? -v : v;
+}
+
+template <typename T>
+__device__ __forceinline__ FrozenRaw<T> frozen_load(const GasView<T>& g, int a, const int s[3],
+                                                    bool need_v) {
+  FrozenRaw<T> r;
+  r.rho = g.rho[a];
+  r.kF = g.kF ? g.kF[a] : g.kF_s;
+  r.kP = g.kP ? g.kP[a] : g.kP_s;
   if (need_v) {
-    const T ir = T(1) / rho;
-    fz.v[0] = T(s[0]) * g.m[0][a] * ir;
-    fz.v[1] = T(s[1]) * g.m[1][a] * ir;
-    fz.v[2] = T(s[2]) * g.m[2][a] * ir;
+    r.m[0] = g.m[0][a];
+    r.m[1] = g.m[1][a];
+    r.m[2] = g.m[2][a];
+  } else {
+    r.m[0] = r.m[1] = r.m[2] = T(0);
+  }
+  r.j = g.j ? g.j[a] : T(0);
+  r.neg = neg_mask(s);
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ Frozen<T> frozen_make(const FrozenRaw<T>& r, bool need_v) {
+  Frozen<T> fz;
+  fz.rkF = r.rho * r.kF;
+  fz.rkP = r.rho * r.kP;
+  if (need_v) {
+    const T ir = rcp(r.rho);
+    fz.v[0] = flip(r.m[0], r.neg, 1) * ir;
+    fz.v[1] = flip(r.m[1], r.neg, 2) * ir;
+    fz.v[2] = flip(r.m[2], r.neg, 4) * ir;
   } else {
     fz.v[0] = fz.v[1] = fz.v[2] = T(0);
   }
-  fz.j = g.j ? g.j[a] : T(0);
+  fz.j = r.j;
   return fz;
+}
+
+template <typename T>
+__device__ __forceinline__ Frozen<T> frozen_at(const GasView<T>& g, int a, const int s[3],
+                                               bool need_v) {
+  return frozen_make(frozen_load(g, a, s, need_v), need_v);
 }
 
 // New (E_r, F) of a stage of length h from the old state Uo, the flux divergence and
@@ -367,15 +429,33 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
   out[3] = Fn[2];
 }
 
+// U^m of the boundary-mapped cell (i, j, k) as loaded; neg marks the flux components a
+// reflecting boundary flips (apply with unflip_rad before use).
 template <typename T>
-__device__ __forceinline__ void load_rad_mapped(const RadPtrs<T>& R, const Geom& G, int i, int j,
-                                                int k, T U[4]) {
+__device__ __forceinline__ void load_rad_raw(const RadPtrs<T>& R, const Geom& G, int i, int j,
+                                             int k, T U[4], int& neg) {
   int s[3];
   const int a = mapped_cell(G, i, j, k, s);
   U[0] = R.E[a];
-  U[1] = T(s[0]) * R.F[0][a];
-  U[2] = T(s[1]) * R.F[1][a];
-  U[3] = T(s[2]) * R.F[2][a];
+  U[1] = R.F[0][a];
+  U[2] = R.F[1][a];
+  U[3] = R.F[2][a];
+  neg = neg_mask(s);
+}
+
+template <typename T>
+__device__ __forceinline__ void unflip_rad(T U[4], int neg) {
+  U[1] = flip(U[1], neg, 1);
+  U[2] = flip(U[2], neg, 2);
+  U[3] = flip(U[3], neg, 4);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rad_mapped(const RadPtrs<T>& R, const Geom& G, int i, int j,
+                                                int k, T U[4]) {
+  int neg;
+  load_rad_raw(R, G, i, j, k, U, neg);
+  unflip_rad(U, neg);
 }
 
 // Radiation predictor at one cell (i, j, k) of the padded region: first-order HLL fluxes

@@ -124,7 +124,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
                                                       const GasView<T>& gas, const Geom& G,
                                                       const RadConst<T>& K, T h, int zc, int bx,
                                                       int by, int bz, PredictShared<T, BY>& sh) {
-  static_assert(BY >= 2, "the extra work items need two wavefronts");
+  static_assert(BY >= 4, "the extra work items need four wavefronts");
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
   const int ntx = (n0 + TILE_BX - 1) / TILE_BX;
@@ -149,21 +149,33 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   // every read stays within [-3, n + 2], where the boundary mapping is defined
   const int xl = min(x, n0 + 2), yl = min(y, n1 + 2);
   const bool out_xy = x < n0 && y < n1 + 2;
-  // extra items: wave 0 brings the y data of row y0 - 1; wave BY - 1 the y data of row
-  // y0 + BY and the high y faces; lanes < 2 BY of wave 1 the x data of cells x0 - 1 and
-  // x0 + 64 of row lane mod BY, and lanes < BY of wave 1 the high x faces
+  // extra items, one per wavefront on different SIMDs (wave w runs on SIMD w mod 4):
+  // before the first barrier wave 0 brings the y data of row y0 - 1, wave 1 that of row
+  // y0 + BY and lanes < 2 BY of wave 2 the x data of cells x0 - 1 and x0 + 64 of row
+  // lane mod BY; between the barriers wave 3 takes the high y faces and lanes < BY of
+  // wave 0 the high x faces
+  const int hrole = ty == 0 ? 1 : (ty == 1 ? 2 : ((ty == 2 && tx < 2 * BY) ? 3 : 0));
   const int hrow = tx % BY;
-  const int xh = tx < BY ? x0 - 1 : min(x0 + TILE_BX, n0 + 2);
-  const int yh = min(y0 + hrow, n1 + 2);
-  const int ybot = y0 - 1, ytop = min(y0 + BY, n1 + 2);
+  const int hx = hrole == 3 ? (tx < BY ? x0 - 1 : min(x0 + TILE_BX, n0 + 2)) : xl;
+  const int hy = hrole == 1 ? y0 - 1 : (hrole == 2 ? min(y0 + BY, n1 + 2) : min(y0 + hrow, n1 + 2));
+  const bool need_v = K.beta != 0;
   const T c = K.c, ic = K.inv_c, chat = K.chat;
+
+  // loads run one plane ahead of their use: U^m of the own cell, the extra item's cell
+  // and the gas data of the cell being updated
+  T Un[4], Hn[4] = {T(0), T(0), T(0), T(0)};
+  int nU, nH = 0;
+  load_rad_raw(Um, G, xl, yl, z0 - 1, Un, nU);
+  if (hrole) load_rad_raw(Um, G, hx, hy, z0, Hn, nH);
+  FrozenRaw<T> gn = {};
 
   FaceSide<T> zprev;  // z data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
   T divprev[4] = {T(0), T(0), T(0), T(0)};
   for (int t = z0 - 1; t <= z1; ++t) {
-    T U[4];
-    load_rad_mapped(Um, G, xl, yl, t, U);
+    T U[4] = {Un[0], Un[1], Un[2], Un[3]};
+    unflip_rad(U, nU);
+    if (t < z1) load_rad_raw(Um, G, xl, yl, t + 1, Un, nU);
     const M1State<T> m = m1_state(U, ic, chat);
     // z face t-1/2, then plane t-1 is complete: its z faces are t-3/2 and t-1/2
     const FaceSide<T> fzs = side_dir(m, U, 2, c, ic, chat);
@@ -173,9 +185,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       T d[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
-      int s[3];
-      const int a = mapped_cell(G, x, y, t - 1, s);
-      const Frozen<T> gz = frozen_at(gas, a, s, K.beta != 0);
+      const Frozen<T> gz = frozen_make(gn, need_v);
       T out[4];
       bool ef, fc;
       rad_update(K, h, zprev.U, zprev.U, d, gz, out, ef, fc);
@@ -185,6 +195,10 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       Uh.F[1][p] = out[2];
       Uh.F[2][p] = out[3];
     }
+    if (t >= z0 && t < z1) {
+      int s[3];
+      gn = frozen_load(gas, mapped_cell(G, xl, yl, t, s), s, need_v);
+    }
     zprev = fzs;
 #pragma unroll
     for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
@@ -192,22 +206,30 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       // x and y faces of plane t
       sh.sx.put(ty, tx + 1, side_dir(m, U, 0, c, ic, chat));
       sh.sy.put(ty + 1, tx, side_dir(m, U, 1, c, ic, chat));
-      if (ty == 0) sh.sy.put(0, tx, side_at(Um, G, xl, ybot, t, 1, c, ic, chat));
-      if (ty == BY - 1) sh.sy.put(BY + 1, tx, side_at(Um, G, xl, ytop, t, 1, c, ic, chat));
-      if (ty == 1 && tx < 2 * BY)
-        sh.sx.put(hrow, tx < BY ? 0 : TILE_BX + 1, side_at(Um, G, xh, yh, t, 0, c, ic, chat));
+      if (hrole) {
+        T H[4] = {Hn[0], Hn[1], Hn[2], Hn[3]};
+        unflip_rad(H, nH);
+        const FaceSide<T> hs = face_side(H, hrole == 3 ? 0 : 1, c, ic, chat);
+        if (hrole == 1)
+          sh.sy.put(0, tx, hs);
+        else if (hrole == 2)
+          sh.sy.put(BY + 1, tx, hs);
+        else
+          sh.sx.put(hrow, tx < BY ? 0 : TILE_BX + 1, hs);
+        if (t + 1 < z1) load_rad_raw(Um, G, hx, hy, t + 1, Hn, nH);
+      }
       __syncthreads();
       T fl[4], fb[4];
       hll(sh.sx.get(ty, tx), sh.sx.get(ty, tx + 1), fl);
       hll(sh.sy.get(ty, tx), sh.sy.get(ty + 1, tx), fb);
       put4(sh.fx[ty][tx], fl);
       put4(sh.fy[ty][tx], fb);
-      if (ty == 1 && tx < BY) {
+      if (ty == 0 && tx < BY) {
         T f[4];
         hll(sh.sx.get(tx, TILE_BX), sh.sx.get(tx, TILE_BX + 1), f);
         put4(sh.fx[tx][TILE_BX], f);
       }
-      if (ty == BY - 1) {
+      if (ty == 3) {
         T f[4];
         hll(sh.sy.get(BY, tx), sh.sy.get(BY + 1, tx), f);
         put4(sh.fy[BY][tx], f);
@@ -253,7 +275,8 @@ template <int BY>
 struct CorrectRing {
   static constexpr int W = TILE_BX + 4;
   static constexpr int cells = 4 * W + 4 * BY;  // two rows below and above, two columns each side
-  static constexpr int per_thread = (cells + TILE_BX * BY - 1) / (TILE_BX * BY);
+  static constexpr int threads = TILE_BX * BY;
+  static constexpr int per_thread = (cells + threads - 1) / threads;
   // LDS position (row r, column c) of ring cell e
   __host__ __device__ static void rc(int e, int& r, int& c) {
     if (e < 4 * W) {
@@ -305,37 +328,43 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   const int tid = tx + TILE_BX * ty;
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
   const int x0 = bx * TILE_BX, y0 = by * BY;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool out_xy = x < n0 && y < n1;
   const int z0 = bz * zc;
   const int z1 = min(z0 + zc, n2);
   const int zs = G.ps[0] * G.ps[1];
-  // the half-step arrays hold valid values on [-2, n + 2) in every dimension
-  const int pcol = padded_cell(G, clamp_i(x, -2, n0 + 1), clamp_i(y, -2, n1 + 1), 0);
+  const T c = K.c, ic = K.inv_c, chat = K.chat;
+  // the ring of the LDS plane, loaded one plane ahead; the half-step arrays hold valid
+  // values on [-2, n + 2) in every dimension
   int rpos[RP], rcol[RP];
 #pragma unroll
   for (int s = 0; s < RP; ++s) {
-    const int e = tid + s * TILE_BX * BY;
+    const int e = tid + s * Ring::threads;
     rpos[s] = -1;
     rcol[s] = 0;
     if (e < Ring::cells) {
-      int r, c;
-      Ring::rc(e, r, c);
-      rpos[s] = r * (TILE_BX + 4) + c;
-      rcol[s] = padded_cell(G, clamp_i(x0 - 2 + c, -2, n0 + 1), clamp_i(y0 - 2 + r, -2, n1 + 1), 0);
+      int r, cc;
+      Ring::rc(e, r, cc);
+      rpos[s] = r * (TILE_BX + 4) + cc;
+      rcol[s] = padded_cell(G, clamp_i(x0 - 2 + cc, -2, n0 + 1), clamp_i(y0 - 2 + r, -2, n1 + 1), 0);
     }
   }
-  const T c = K.c, ic = K.inv_c, chat = K.chat;
   V4<T>* const sUf = &sh.U[0][0];
-
-  T Uzm[4], Uz0[4], Uzp[4], Upp[4];
-  load_padded4(Uh, pcol + (z0 - 2) * zs, Uzm);
-  load_padded4(Uh, pcol + (z0 - 1) * zs, Uz0);
-  load_padded4(Uh, pcol + z0 * zs, Uzp);
   T ring[RP][4];
 #pragma unroll
   for (int s = 0; s < RP; ++s)
     if (rpos[s] >= 0) load_padded4(Uh, rcol[s] + z0 * zs, ring[s]);
+
+  const int x = x0 + tx, y = y0 + ty;
+  const bool out_xy = x < n0 && y < n1;
+  const int pcol = padded_cell(G, clamp_i(x, -2, n0 + 1), clamp_i(y, -2, n1 + 1), 0);
+  T Uzm[4], Uz0[4], Uzp[4], Upp[4];
+  load_padded4(Uh, pcol + (z0 - 2) * zs, Uzm);
+  load_padded4(Uh, pcol + (z0 - 1) * zs, Uz0);
+  load_padded4(Uh, pcol + z0 * zs, Uzp);
+  // U^m and the gas data of the cell updated at the next plane, loaded one plane ahead
+  const bool need_v = K.beta != 0;
+  const int s1[3] = {1, 1, 1};
+  FrozenRaw<T> gn = {};
+  T Uon[4] = {T(0), T(0), T(0), T(0)};
   FaceSide<T> zplus;  // high-z face data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
   T divprev[4] = {T(0), T(0), T(0), T(0)};
@@ -366,18 +395,24 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
 #pragma unroll
         for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
         const int a = x + n0 * (y + n1 * (t - 1));
-        const int s[3] = {1, 1, 1};
-        const Frozen<T> gz = frozen_at(gas, a, s, K.beta != 0);
-        T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+        const Frozen<T> gz = frozen_make(gn, need_v);
         T out[4];
         bool ef, fc;
-        rad_update(K, h, Uo, Uzm, d, gz, out, ef, fc);
+        rad_update(K, h, Uon, Uzm, d, gz, out, ef, fc);
         nef += ef ? 1ull : 0ull;
         nfc += fc ? 1ull : 0ull;
         Um.E[a] = out[0];
         Um.F[0][a] = out[1];
         Um.F[1][a] = out[2];
         Um.F[2][a] = out[3];
+      }
+      if (t >= z0 && t < z1 && out_xy) {
+        const int a = x + n0 * (y + n1 * t);
+        gn = frozen_load(gas, a, s1, need_v);
+        Uon[0] = Um.E[a];
+        Uon[1] = Um.F[0][a];
+        Uon[2] = Um.F[1][a];
+        Uon[3] = Um.F[2][a];
       }
       if (t < z1) zplus = face_side(pz, 2, c, ic, chat);
 #pragma unroll
@@ -402,6 +437,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
       }
       put4(sh.fx[ty][tx], fl);
       put4(sh.fy[ty][tx], fb);
+      // extra items on waves of different SIMDs (wave w runs on SIMD w mod 4)
       if (ty == 0 && tx < BY) {
         // high x face of row tx: cells x0 + 62 ... x0 + 65
         T a[4], b[4], cc[4], d[4], f[4];

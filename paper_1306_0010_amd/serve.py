@@ -51,7 +51,7 @@ def _percentiles(lat):
 
 
 def serve_batched(requests, make_problem, budget_bytes=16 << 30, max_slots=64, tile_rows=8,
-                  zchunk=16, keep_results=False):
+                  zchunk=8, keep_results=False):
     """Serve ``requests`` (dicts with 'id', 'arrival' in seconds, 'steps') with
     continuous batching. ``make_problem(req)`` returns the problem dict (spec, state,
     chat). Returns a summary dict and, with keep_results, the final states by id."""
@@ -150,4 +150,4 @@ def serve_serial(requests, make_problem, keep_results=False, variant=None):
     return summary, results
 
 
-DEFAULT_VARIANT = (RHD_KERNELS_TILED, 8, 16)
+DEFAULT_VARIANT = (RHD_KERNELS_TILED, 8, 8)

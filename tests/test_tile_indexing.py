@@ -96,10 +96,21 @@ def replay(n, bc, BY, zc):
                 # a closure that feeds a face of an output cell is never clamped
                 need = (x <= n0) & (y <= n1 + 2)
                 assert np.array_equal(xl[need], x[need]) and np.array_equal(yl[need], y[need])
+                # extra items: wave 0 brings the y data of row y0 - 1, wave 1 that of row
+                # y0 + BY, lanes < 2 BY of wave 2 the x data of cells x0 - 1 and x0 + 64
+                hrole = np.where(ty == 0, 1, np.where(ty == 1, 2, np.where((ty == 2) & (tx < 2 * BY), 3, 0)))
                 hrow = tx % BY
-                xh = np.where(tx < BY, x0 - 1, np.minimum(x0 + BX, n0 + 2))
-                yh = np.minimum(y0 + hrow, n1 + 2)
-                ybot, ytop = y0 - 1, min(y0 + BY, n1 + 2)
+                hx = np.where(hrole == 3, np.where(tx < BY, x0 - 1, np.minimum(x0 + BX, n0 + 2)), xl)
+                hy = np.where(hrole == 1, y0 - 1,
+                              np.where(hrole == 2, min(y0 + BY, n1 + 2), np.minimum(y0 + hrow, n1 + 2)))
+                slots = sorted([("sy", 0, int(c)) for c in tx[hrole == 1]]
+                               + [("sy", BY + 1, int(c)) for c in tx[hrole == 2]]
+                               + [("sx", int(r), 0 if t < BY else BX + 1)
+                                  for r, t in zip(hrow[hrole == 3], tx[hrole == 3])])
+                # every LDS slot outside the tile is written once per plane
+                assert slots == sorted([("sx", r, 0) for r in range(BY)] + [("sx", r, BX + 1) for r in range(BY)]
+                                       + [("sy", 0, c) for c in range(BX)] + [("sy", BY + 1, c) for c in range(BX)])
+                live = hrole > 0
                 for t in range(z0 - 1, z1 + 1):
                     check_mapped(xl, yl, t)
                     if t > z0:
@@ -107,14 +118,7 @@ def replay(n, bc, BY, zc):
                         p = padded(x[out_xy], y[out_xy], t - 1)
                         np.add.at(writes, p, 1)
                     if z0 <= t < z1:
-                        w0 = ty == 0
-                        check_mapped(xl[w0], np.full(w0.sum(), ybot), t)
-                        w1 = ty == BY - 1
-                        check_mapped(xl[w1], np.full(w1.sum(), ytop), t)
-                        wh = (ty == 1) & (tx < 2 * BY)
-                        check_mapped(xh[wh], yh[wh], t)
-                        assert sorted(zip(hrow[wh], tx[wh] < BY)) == sorted(
-                            [(r, True) for r in range(BY)] + [(r, False) for r in range(BY)])
+                        check_mapped(hx[live], hy[live], t)
     assert np.all(writes == 1), "predictor writes each padded cell once"
 
     # corrector
