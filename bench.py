@@ -13,7 +13,10 @@ region except the one v_max value per step.
 
 Prints one JSON line: the radiation zone-update rate (cells x subcycles per second),
 the roofline of the dominant kernel from HIP-event timings of its launches inside the
-timed region, and the FP64 CPU oracle timed on a bounded sample of the same input.
+timed region (against the FP32 VALU roof, which bounds it, with its algorithmic HBM
+bandwidth beside it), the same for 200 subcycles of the 256^3 concentrated-source grid,
+the served-batch latencies, and the FP64 CPU oracle timed on a bounded sample of the
+same input.
 """
 from __future__ import annotations
 
@@ -30,6 +33,14 @@ if ROOT not in sys.path:
 
 METRIC = "radiation zone-updates/s + % HBM peak; p50/p99 latency of batched solves"
 HBM_PEAK_GBS = 8000.0
+# FP32 VALU lane slots per second without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz (an FMA is one slot; a transcendental takes four, as it issues at quarter rate)
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
+# tile shapes (rows, z chunk) that rhd_autotune picked for the two grids on MI355X
+TILE_C2 = (8, 8)
+TILE_C3 = (8, 16)
 
 
 def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):
@@ -54,6 +65,87 @@ def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):
     return table[kernel] * es
 
 
+def algorithmic_slots_per_cell(kernel, spec, has_j):
+    """FP32 VALU lane slots the arithmetic of one radiation stage takes per cell, counted
+    from its formulas: every add, multiply, FMA, min, max, median and compare is one slot,
+    a reciprocal or (reciprocal) square root four. Closure of one state along one
+    direction: 31 + 4 transcendentals; HLL flux: 24 + 1; MC slope: 7 per field; face
+    states: 8 per direction; divergence: 24; update (E_r, F with theta damping, floor and
+    clamp): 35 + 1, plus 19 for the O(beta tau) terms, 2 for an emissivity and 9 for
+    absorption-only damping."""
+    T = 4
+    closure_state = 14 + 3 * T  # reduced flux, s, 3/(2+s), chat/s, (s-1)/3
+    closure_dir = 17 + 1 * T    # physical flux and the two extreme eigenvalues
+    hll = 24 + 1 * T
+    update = 35 + 1 * T + (19 + T if spec["beta_tau"] else 0) + (2 if has_j else 0) \
+        + (9 + T if spec["exchange"] == "absorb_only" else 0)
+    div = 24
+    if kernel == "rad_predict":
+        return closure_state + 3 * closure_dir + 3 * hll + div + update
+    if kernel == "rad_correct":
+        return 3 * (4 * 7 + 8) + 6 * (closure_state + closure_dir) + 3 * hll + div + update
+    return None
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed hardware-counter record, if it was taken
+    on the kernel sources as they are now; None otherwise."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    entry = rec.get("kernels", {}).get(workload, {}).get(kernel)
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def kernel_table(timing, spec, has_j, kappa_field):
+    kernels = {}
+    total = sum(v["total_ms"] for v in timing.values())
+    for name, t in timing.items():
+        if t["calls"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["calls"]
+        b = algorithmic_bytes_per_cell(name, spec, has_j, kappa_field) * t["cells"]
+        k = {"calls": t["calls"], "avg_us": 1e3 * avg_ms, "share": t["total_ms"] / max(1e-30, total),
+             "cells_per_launch": t["cells"], "algorithmic_GBps": b / (avg_ms * 1e-3) / 1e9}
+        sl = algorithmic_slots_per_cell(name, spec, has_j)
+        if sl is not None:
+            k["algorithmic_Tslots_per_s"] = sl * t["cells"] / (avg_ms * 1e-3) / 1e12
+            k["slots_per_cell"] = sl
+        kernels[name] = k
+    return kernels
+
+
+def roofline(kernels, spec, has_j, kappa_field, workload):
+    """The dominant kernel against the FP32 VALU roof (it is bound by arithmetic), with
+    its algorithmic HBM bandwidth beside it."""
+    rad = {k: v for k, v in kernels.items() if k.startswith("rad_")}
+    dom = max(rad, key=lambda k: rad[k]["share"])
+    k = rad[dom]
+    bpc = algorithmic_bytes_per_cell(dom, spec, has_j, kappa_field)
+    traffic = measured_traffic(dom, workload)
+    return {"bound": "alu", "achieved": k["algorithmic_Tslots_per_s"], "peak": VALU_PEAK_TSLOTS,
+            "unit": "TFLOP/s", "frac": k["algorithmic_Tslots_per_s"] / VALU_PEAK_TSLOTS,
+            "traffic": traffic, "kernel": dom, "avg_us": k["avg_us"],
+            "slots_per_cell": k["slots_per_cell"], "cells_per_launch": k["cells_per_launch"],
+            "unit_note": "FP32 VALU lane slots (non-packed; transcendental = 4)",
+            "hbm_algorithmic": {"achieved_GBps": k["algorithmic_GBps"], "peak_GBps": HBM_PEAK_GBS,
+                                "frac": k["algorithmic_GBps"] / HBM_PEAK_GBS,
+                                "bytes_per_cell": bpc}}
+
+
 def cpu_baseline(pb, nz_slab=16):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the same
     input: the first nz_slab z-planes of the 128^3 box as a periodic slab, one full
@@ -72,6 +164,47 @@ def cpu_baseline(pb, nz_slab=16):
             "sample": f"one gas step (exchange, gas VL, {ns} radiation subcycles, correction) on "
                       f"a {spec['nx']}x{spec['ny']}x{nz_slab} periodic slab cut from the same "
                       f"128^3 input, FP64, {el:.1f} s"}
+
+
+def c3_measurement(P, ri, stream, subcycles, tune):
+    """The concentrated-source grid (256^3, outflow, static gas with a Gaussian core,
+    central emitting cells, chat = c = 1): one call of `subcycles` radiation subcycles
+    with the state resident on the device, per-kernel HIP-event timing inside it."""
+    import torch
+    pb = ri.c3_point_source(256)
+    spec, chat = pb["spec"], pb["chat"]
+    dt_rad = pb["dt"]
+    ncell = spec["nx"] * spec["ny"] * spec["nz"]
+    with P.Solver(spec, stream=stream.cuda_stream) as s:
+        s.set_state(pb["state"])
+        if tune:
+            tile = s.autotune(chat, dt_rad, 3) + ("autotune",)
+        else:
+            tile = (P.RHD_KERNELS_TILED,) + TILE_C3 + ("fixed",)
+            s.set_kernel_variant(*tile[:3])
+        s.step(dt_rad * 4, chat, 4)  # warm-up
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(dt_rad * subcycles, chat, subcycles)
+        s.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diag = s.diagnostics()
+        # per-kernel HIP-event timing in a pass of its own
+        P.rhd_set_timing(s.h, 1)
+        nt = min(subcycles, 50)
+        s.step(dt_rad * nt, chat, nt)
+        s.sync()
+        timing = P.rhd_get_timing(s.h)
+    kernels = kernel_table(timing, spec, True, False)
+    out = {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]],
+           "subcycles": subcycles, "value": ncell * subcycles / el, "unit": "zone-updates/s",
+           "elapsed_s": el, "roofline": roofline(kernels, spec, True, False, pb["name"]),
+           "kernels": {k: v for k, v in kernels.items() if k.startswith("rad_")},
+           "nonfinite": diag["nonfinite"]}
+    out["kernels_choice"] = {"tile_rows": tile[1], "zchunk": tile[2], "picked_by": tile[3]}
+    return out
 
 
 def serving(count, load):
@@ -112,6 +245,13 @@ def main():
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
+                         "of the shapes the tuner picked for these grids before")
+    ap.add_argument("--c3-subcycles", type=int, default=200,
+                    help="radiation subcycles of the 256^3 point-source measurement (0 skips it)")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="run only the 256^3 point-source measurement and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB once "
                          "(device to device): the reference dispatch for scaling hardware "
@@ -136,6 +276,11 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
+    if args.c3_only:
+        print(json.dumps(c3_measurement(P, ri, stream, max(1, args.c3_subcycles),
+                                        args.autotune)), flush=True)
+        return
+
     pb = ri.c2_linear_box(args.n, precision=args.precision)
     spec, chat = pb["spec"], pb["chat"]
     ncell = spec["nx"] * spec["ny"] * spec["nz"]
@@ -148,11 +293,23 @@ def main():
         solver.step(dt, chat, ns)
         return ns
 
+    if args.autotune:
+        dt0, ns0 = solver.suggest_dt(chat)
+        tile = solver.autotune(chat, dt0 / ns0, 3) + ("autotune",)
+    else:
+        tile = (P.RHD_KERNELS_TILED,) + TILE_C2 + ("fixed",)
+        solver.set_kernel_variant(*tile[:3])
+
     if args.copy_calibration_mib > 0:
+        # two reference dispatches of known size: a device-to-device copy and an
+        # elementwise kernel reading one buffer and writing another
         nb = args.copy_calibration_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -161,8 +318,6 @@ def main():
     solver.sync()
     torch.cuda.synchronize()
 
-    if not args.no_kernel_timing:
-        P.rhd_set_timing(h, 1)
     subcycles = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -171,8 +326,17 @@ def main():
     torch.cuda.synchronize()
     solver.sync()
     elapsed = time.perf_counter() - t0
-    timing = P.rhd_get_timing(h) if not args.no_kernel_timing else {}
     diag = solver.diagnostics()
+    timing = {}
+    if not args.no_kernel_timing:
+        # per-kernel HIP-event timing in a pass of its own, so that the event records
+        # do not sit between the kernels of the timed region
+        P.rhd_set_timing(h, 1)
+        for _ in range(args.steps):
+            one_step()
+        solver.sync()
+        timing = P.rhd_get_timing(h)
+        P.rhd_set_timing(h, 0)
     solver.close()
 
     value = ncell * subcycles / elapsed
@@ -197,28 +361,19 @@ def main():
                    "gas_step_zone_updates_per_s": ncell * args.steps / elapsed},
     }
 
+    out["config"]["kernels"] = {"variant": "tiled" if tile[0] == P.RHD_KERNELS_TILED else "per_cell",
+                                "tile_rows": tile[1], "zchunk": tile[2], "picked_by": tile[3]}
     if timing:
-        kernels = {}
-        for name, t in timing.items():
-            if t["calls"] == 0:
-                continue
-            avg_ms = t["total_ms"] / t["calls"]
-            b = algorithmic_bytes_per_cell(name, spec, False, False) * t["cells"]
-            kernels[name] = {"calls": t["calls"], "avg_us": 1e3 * avg_ms,
-                             "share": t["total_ms"] / max(1e-30, sum(v["total_ms"] for v in timing.values())),
-                             "algorithmic_GBps": b / (avg_ms * 1e-3) / 1e9}
-        dom = max(kernels, key=lambda k: kernels[k]["share"])
-        achieved = kernels[dom]["algorithmic_GBps"]
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": dom, "avg_us": kernels[dom]["avg_us"],
-                           "bytes_per_cell": algorithmic_bytes_per_cell(dom, spec, False, False)}
+        kernels = kernel_table(timing, spec, False, False)
+        out["roofline"] = roofline(kernels, spec, False, False, pb["name"])
         out["kernels"] = kernels
-        out["gpu_time_share_ms_per_step"] = sum(t["total_ms"] for t in timing.values()) / args.steps
+        out["kernel_ms_per_step"] = sum(t["total_ms"] for t in timing.values()) / args.steps
 
     out["diagnostics"] = {k: diag[k] for k in ("nonfinite", "rad_fclamp", "rad_efloor",
                                                "gas_rhofloor", "gas_pfloor", "exch_theta1",
                                                "exch_bisect", "newton_max")}
+    if args.c3_subcycles > 0 and args.precision == "mixed":
+        out["c3_point_source"] = c3_measurement(P, ri, stream, args.c3_subcycles, args.autotune)
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
