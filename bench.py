@@ -15,7 +15,7 @@ Prints one JSON line: the radiation zone-update rate (cells x subcycles per seco
 the roofline of the dominant kernel from HIP-event timings of its launches inside the
 timed region (against the FP32 VALU roof, which bounds it, with its algorithmic HBM
 bandwidth beside it), the same for 200 subcycles of the 256^3 concentrated-source grid,
-the served-batch latencies, and the FP64 CPU oracle timed on a bounded sample of the
+full gas steps of the 256^3 dusty shell, the served-batch latencies, and the FP64 CPU oracle timed on a bounded sample of the
 same input.
 """
 from __future__ import annotations
@@ -207,6 +207,40 @@ def c3_measurement(P, ri, stream, subcycles, tune):
     return out
 
 
+def c4_measurement(P, ri, stream, steps):
+    """The dusty-shell grid (256^3, isothermal gas, outflow faces, radiative equilibrium,
+    lognormal shell and a central source, chat = 20 v_max at t = 0): `steps` full gas
+    steps with CFL-limited subcycles, the state resident on the device."""
+    import torch
+    pb = ri.c4_dusty_shell(256)
+    spec = pb["spec"]
+    ncell = spec["nx"] * spec["ny"] * spec["nz"]
+    with P.Solver(spec, stream=stream.cuda_stream) as s:
+        s.set_state(pb["state"])
+        s.suggest_dt(1.0)
+        chat = pb["chat_over_vmax"] * s.diagnostics()["vmax"]
+        s.set_kernel_variant(P.RHD_KERNELS_TILED, *TILE_C3)
+        dt, ns = s.suggest_dt(chat)
+        s.step(dt, chat, ns)  # warm-up step
+        s.sync()
+        torch.cuda.synchronize()
+        sub = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dt, ns = s.suggest_dt(chat)
+            s.step(dt, chat, ns)
+            sub += ns
+        s.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diag = s.diagnostics()
+    return {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]], "gas_steps": steps,
+            "subcycles_per_step": sub / steps, "chat": chat, "value": ncell * sub / el,
+            "unit": "zone-updates/s", "gas_step_zone_updates_per_s": ncell * steps / el,
+            "elapsed_s": el, "nonfinite": diag["nonfinite"],
+            "tile": {"tile_rows": TILE_C3[0], "zchunk": TILE_C3[1]}}
+
+
 def serving(count, load):
     """The served-batch workload: a stream of independent periodic boxes (32^3..192^3,
     kappa log-uniform in [1, 1e3], chat/a0 in [5, 50], 20 gas steps each). The
@@ -250,6 +284,8 @@ def main():
                          "of the shapes the tuner picked for these grids before")
     ap.add_argument("--c3-subcycles", type=int, default=200,
                     help="radiation subcycles of the 256^3 point-source measurement (0 skips it)")
+    ap.add_argument("--c4-steps", type=int, default=5,
+                    help="gas steps of the 256^3 dusty-shell measurement (0 skips it)")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the 256^3 point-source measurement and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -374,6 +410,8 @@ def main():
                                                "exch_bisect", "newton_max")}
     if args.c3_subcycles > 0 and args.precision == "mixed":
         out["c3_point_source"] = c3_measurement(P, ri, stream, args.c3_subcycles, args.autotune)
+    if args.c4_steps > 0 and args.precision == "mixed":
+        out["c4_dusty_shell"] = c4_measurement(P, ri, stream, args.c4_steps)
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:

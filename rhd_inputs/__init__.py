@@ -177,7 +177,9 @@ def c4_dusty_shell(n=256, seed=BASE_SEED + 4, precision="mixed"):
     and FWHM 0.05 with seeded lognormal density (sigma_ln rho = 1) so that the shell
     column gives tau ~ 20 at kappa = 1; central Gaussian source j of width 2 cells
     and luminosity set so that L kappa / (4 pi 0.3^2 c) = 20; c = 1e4; chat is 20x
-    the initial signal speed and stays fixed."""
+    the initial signal speed and stays fixed. The log-density is a Gaussian random
+    field of unit RMS made of random-phase modes with integer wavenumbers 2 .. n/8
+    (at least 4), so it varies over eight cells or more."""
     h = 1.0 / n
     spec = default_spec(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, c_light=1e4, iso_cs=1.0,
                         isothermal=True, exchange="none", theta_F=1.0, bc="outflow",
@@ -188,7 +190,7 @@ def c4_dusty_shell(n=256, seed=BASE_SEED + 4, precision="mixed"):
     sig_sh = 0.05 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
     smooth = 1.0 + 375.8 * np.exp(-((r - 0.3) ** 2) / (2 * sig_sh ** 2))
     rng = np.random.default_rng(seed)
-    g = rng.standard_normal(smooth.shape)
+    g = random_phase_field(smooth.shape, 2, max(4, n // 8), 1.0, rng)
     lognorm = np.exp(1.0 * g - 0.5)
     rho = np.where(smooth > 2.0, smooth * lognorm, smooth)
     st["rho"][:] = rho

@@ -22,6 +22,13 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
 NORM = {"fp64": "max", "mixed": "l1"}
+# Cases whose radiation flux reaches the realizability limit f = 1 in many cells (the
+# dusty shell clamps F in ~2e3 cell-stages of its first step). At f = 1 the extreme M1
+# eigenvalues have a square-root branch point: a rounding difference delta in f moves
+# them by chat sqrt(2 delta), i.e. by ~1e-8 chat for delta of a few FP64 ulp. The speeds
+# enter the HLL dissipation term, so FP64 results agree to ~sqrt(eps) times the share of
+# that term instead of ~eps; 1e-10 bounds it with a margin of three over what is seen.
+FP64_TOL_BRANCH_POINT = {"dusty_shell_32": 1e-10}
 
 
 def announce(name):
@@ -89,6 +96,18 @@ def rhd3d_two_full_x_tiles(precision):
 
 
 @case
+def dusty_shell_32(precision):
+    """The dusty-shell workload at 32^3: isothermal gas, outflow faces, radiative
+    equilibrium, lognormal shell and a central Gaussian source; chat is 20 v_max. One gas
+    step: the source accelerates the central gas to several times the sound speed within
+    it, so a second step at the same dt would exceed the CFL limit."""
+    pb = ri.c4_dusty_shell(32, precision=precision)
+    spec, st = pb["spec"], pb["state"]
+    _, _, vmax = oracle.suggest_dt(spec, st, 1.0)
+    return spec, st, pb["chat_over_vmax"] * vmax, 1
+
+
+@case
 def rad_only_absorb_2d_wave(precision):
     pb = ri.radiation_wave(2, 16)
     spec = dict(pb["spec"], precision=precision)
@@ -143,7 +162,10 @@ def test_step_matches_oracle(name, precision, variant):
     dt, ns = step_sizes(spec, st, chat)
     ref, cnt = oracle.step(spec, st, dt, chat, ns, steps=steps)
     gpu, diag = run_gpu(spec, st, steps, chat, dt, ns, VARIANTS[variant])
-    assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"{name} {precision}")
+    tol = TOL[precision]
+    if precision == "fp64":
+        tol = FP64_TOL_BRANCH_POINT.get(name, tol)
+    assert_parity(spec, gpu, ref, tol, NORM[precision], label=f"{name} {precision}")
     assert diag["nonfinite"] == 0 and diag["steps"] == steps and diag["subcycles"] == steps * ns
     if precision == "fp64":
         # same branch decisions: exchange fallbacks, floors and clamps
