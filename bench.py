@@ -34,7 +34,9 @@ if ROOT not in sys.path:
 METRIC = "radiation zone-updates/s + % HBM peak; p50/p99 latency of batched solves"
 HBM_PEAK_GBS = 8000.0
 # FP32 VALU lane slots per second without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz (an FMA is one slot; a transcendental takes four, as it issues at quarter rate)
+# 2.4 GHz (an FMA is one slot; a reciprocal or square root takes two: dependent chains of
+# v_rcp/v_sqrt/v_rsq_f32 interleaved with FMAs run at 1/2.9 of the FMA-only rate on
+# gfx950, i.e. about 1.9 slots each)
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
@@ -68,12 +70,12 @@ def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):
 def algorithmic_slots_per_cell(kernel, spec, has_j):
     """FP32 VALU lane slots the arithmetic of one radiation stage takes per cell, counted
     from its formulas: every add, multiply, FMA, min, max, median and compare is one slot,
-    a reciprocal or (reciprocal) square root four. Closure of one state along one
+    a reciprocal or (reciprocal) square root two. Closure of one state along one
     direction: 31 + 4 transcendentals; HLL flux: 24 + 1; MC slope: 7 per field; face
     states: 8 per direction; divergence: 24; update (E_r, F with theta damping, floor and
-    clamp): 35 + 1, plus 19 for the O(beta tau) terms, 2 for an emissivity and 9 for
-    absorption-only damping."""
-    T = 4
+    clamp): 35 + 1, plus 19 + 1 for the O(beta tau) terms, 2 for an emissivity and 9 + 1
+    for absorption-only damping."""
+    T = 2
     closure_state = 14 + 3 * T  # reduced flux, s, 3/(2+s), chat/s, (s-1)/3
     closure_dir = 17 + 1 * T    # physical flux and the two extreme eigenvalues
     hll = 24 + 1 * T
@@ -140,7 +142,7 @@ def roofline(kernels, spec, has_j, kappa_field, workload):
             "unit": "TFLOP/s", "frac": k["algorithmic_Tslots_per_s"] / VALU_PEAK_TSLOTS,
             "traffic": traffic, "kernel": dom, "avg_us": k["avg_us"],
             "slots_per_cell": k["slots_per_cell"], "cells_per_launch": k["cells_per_launch"],
-            "unit_note": "FP32 VALU lane slots (non-packed; transcendental = 4)",
+            "unit_note": "FP32 VALU lane slots (non-packed; reciprocal/square root = 2)",
             "hbm_algorithmic": {"achieved_GBps": k["algorithmic_GBps"], "peak_GBps": HBM_PEAK_GBS,
                                 "frac": k["algorithmic_GBps"] / HBM_PEAK_GBS,
                                 "bytes_per_cell": bpc}}
