@@ -248,7 +248,9 @@ def serving(count, load):
     kappa log-uniform in [1, 1e3], chat/a0 in [5, 50], 20 gas steps each). The
     one-at-a-time capacity is measured first with every request queued at t = 0; the
     Poisson arrivals are then scaled so that the offered load is ``load`` times that
-    capacity, and the same stream is served with continuous batching and one at a time."""
+    capacity, and the same stream is served with packed-tile batching, with concurrent
+    per-solve streams and one at a time. The capacity of each mode (all requests queued
+    at t = 0) closes the measurement."""
     import rhd_inputs as ri
     from paper_1306_0010_amd import serve
 
@@ -259,12 +261,21 @@ def serving(count, load):
     service = cap["elapsed_s"] / count
     timed = [dict(r, arrival=r["arrival"] * service) for r in reqs]
     batched, _ = serve.serve_batched(timed, make)
+    concurrent, _ = serve.serve_concurrent(timed, make, variant=serve.DEFAULT_VARIANT)
     serial, _ = serve.serve_serial(timed, make, variant=serve.DEFAULT_VARIANT)
+    # capacity: every request queued at t = 0
+    cap_b, _ = serve.serve_batched(at_zero, make)
+    cap_c, _ = serve.serve_concurrent(at_zero, make, variant=serve.DEFAULT_VARIANT)
+    capacity = {m: c["zone_updates_per_s"] for m, c in
+                (("batched", cap_b), ("concurrent", cap_c), ("one_at_a_time", cap))}
     return {"requests": count, "offered_load": load,
             "one_at_a_time_capacity_requests_per_s": 1.0 / service,
-            "batched": batched, "one_at_a_time": serial,
+            "batched": batched, "concurrent": concurrent, "one_at_a_time": serial,
             "batched_over_one_at_a_time_zone_updates": batched["zone_updates_per_s"]
-            / serial["zone_updates_per_s"]}
+            / serial["zone_updates_per_s"],
+            "concurrent_over_one_at_a_time_zone_updates": concurrent["zone_updates_per_s"]
+            / serial["zone_updates_per_s"],
+            "capacity_zone_updates_per_s": capacity}
 
 
 def main():

@@ -14,6 +14,11 @@ Latency is measured from a request's arrival to its result on the host. Synthesi
 request's initial state on the host is not counted: the clock stops while it runs, as
 if the client had sent a ready state.
 
+``serve_concurrent`` serves the same stream with the same admission rule, but each
+admitted solve keeps its own handle and stream: the server advances the active solves one
+gas step each in turn, so the steps of different solves run on the device at the same
+time and a solve with few subcycles is not held back by one with many.
+
 ``serve_serial`` runs the same requests one at a time with one handle each, for
 comparison.
 """
@@ -116,6 +121,71 @@ def serve_batched(requests, make_problem, budget_bytes=16 << 30, max_slots=64, t
                "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
                "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": peak_active,
                "batch_steps": steps_taken, "budget_bytes": budget_bytes, "max_slots": max_slots}
+    return summary, results
+
+
+def serve_concurrent(requests, make_problem, budget_bytes=16 << 30, max_slots=16,
+                     variant=None, keep_results=False):
+    """Serve ``requests`` with continuous batching over independent handles, one stream
+    each. Between rounds the server admits waiting requests in arrival order while the
+    memory budget and the slot count allow; in each round every active solve computes its
+    step size (which waits for its own previous step only) and enqueues one gas step.
+    Returns a summary dict and, with keep_results, the final states by id."""
+    order = [dict(r) for r in sorted(requests, key=lambda r: r["arrival"])]
+    clock = _Clock()
+    waiting = list(order)
+    active = []  # dicts: req, solver, fp, done, cells, chat
+    used = 0
+    lat, results, zone_updates, peak_active, steps_taken = {}, {}, 0, 0, 0
+    try:
+        while waiting or active:
+            now = clock.now()
+            while waiting and waiting[0]["arrival"] <= now and len(active) < max_slots:
+                req = waiting[0]
+                if "_problem" not in req:
+                    req["_problem"] = clock.exclude(lambda: make_problem(req))
+                pb = req["_problem"]
+                fp = rhd_footprint_bytes(params_from_spec(pb["spec"]))
+                if used + fp > budget_bytes and active:
+                    break
+                waiting.pop(0)
+                del req["_problem"]
+                s = Solver(pb["spec"])
+                if variant is not None:
+                    s.set_kernel_variant(*variant)
+                s.set_state(pb["state"])
+                used += fp
+                active.append({"req": req, "solver": s, "fp": fp, "done": 0, "chat": pb["chat"],
+                               "cells": int(np.prod(s.shape))})
+                peak_active = max(peak_active, len(active))
+            if not active:
+                wait = waiting[0]["arrival"] - clock.now()
+                if wait > 0:
+                    time.sleep(wait)
+                continue
+            for a in list(active):
+                dt, ns = a["solver"].suggest_dt(a["chat"])
+                a["solver"].step(dt, a["chat"], ns)
+                a["done"] += 1
+                steps_taken += 1
+                zone_updates += a["cells"] * ns
+                if a["done"] >= a["req"]["steps"]:
+                    out = a["solver"].get_state()  # waits for this solve's stream
+                    lat[a["req"]["id"]] = clock.now() - a["req"]["arrival"]
+                    if keep_results:
+                        results[a["req"]["id"]] = out
+                    a["solver"].close()
+                    used -= a["fp"]
+                    active.remove(a)
+    finally:
+        for a in active:
+            a["solver"].close()
+    elapsed = clock.now()
+    p50, p99 = _percentiles(list(lat.values()))
+    summary = {"mode": "concurrent", "requests": len(lat), "zone_updates": zone_updates,
+               "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
+               "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": peak_active,
+               "gas_steps": steps_taken, "budget_bytes": budget_bytes, "max_slots": max_slots}
     return summary, results
 
 

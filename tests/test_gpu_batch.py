@@ -183,3 +183,26 @@ def test_served_results_equal_one_at_a_time_results():
     for r in reqs:
         assert_parity(make(r)["spec"], ra[r["id"]], rb[r["id"]], 1e-6, "max",
                       label=f"request {r['id']} served vs one at a time")
+
+
+def test_concurrent_served_results_equal_one_at_a_time_results():
+    """Serving with one handle and stream per admitted solve, steps of different solves in
+    flight together, a memory budget and a slot limit: every request gets exactly its
+    one-at-a-time result (same kernels, same tile shape, so bit for bit)."""
+    announce("serve small stream concurrently")
+    reqs = ri.c5_requests(count=7, seed=6, sizes=(16, 24, 32, 40))
+    for i, r in enumerate(reqs):
+        r["steps"] = 3
+        r["arrival"] = 0.002 * i
+    make = lambda r: ri.c5_problem(r)
+    fp = [P.rhd_footprint_bytes(P.params_from_spec(make(r)["spec"])) for r in reqs]
+    budget = int(sum(sorted(fp)[-3:]))
+    a, ra = serve.serve_concurrent(reqs, make, budget_bytes=budget, max_slots=4,
+                                   variant=serve.DEFAULT_VARIANT, keep_results=True)
+    b, rb = serve.serve_serial(reqs, make, keep_results=True, variant=serve.DEFAULT_VARIANT)
+    assert a["requests"] == b["requests"] == 7
+    assert a["zone_updates"] == b["zone_updates"]
+    assert 1 <= a["peak_active"] <= 4
+    for r in reqs:
+        for k in ri.FIELDS:
+            assert np.array_equal(ra[r["id"]][k], rb[r["id"]][k]), (r["id"], k)
