@@ -8,6 +8,7 @@
 //   -> gas source correction -> FP64 ledger with non-finite check.
 #include "rhd_device.hpp"
 #include "rhd_tile.hpp"
+#include "rhd_gas_tile.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -454,6 +455,34 @@ rhdk::GasConst<T> gas_const(const rhd_t* h) {
 }
 
 // Steps 2-3 of a gas step (Sec. 3.1): the implicit exchange and the gas Van Leer step.
+// The gas Van Leer stages with the tiled kernels (3D grids), on the radiation stages'
+// tile shape.
+template <typename T, int BY>
+int launch_gas_tiled(rhd_t* h, double dt) {
+  const rhdk::Geom& G = h->G;
+  const rhdk::TileGrid tg = rhdk::tile_grid<BY>(G.n, h->zchunk);
+  const dim3 block(rhdk::TILE_BX, BY, 1);
+  const rhdk::GasConst<T> GK = gas_const<T>(h);
+  auto gas = gas_ptrs<T>(h->b.gas);
+  auto gh = gas_ptrs<T>(h->b.gh);
+  auto rad = rad_ptrs<T>(h->b.rad);
+  const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
+  int ti = tbegin(h, KC_GAS_PREDICT, h->NP);
+  hipLaunchKernelGGL((rhdk::k_gas_predict_tile<T, BY>), dim3(tg.pred[0], tg.pred[1], tg.pred[2]),
+                     block, 0, h->stream, gas, gh, rad, kFp, T(h->kF_s), G, GK, T(0.5 * dt),
+                     tg.zc_pred);
+  tend(h, ti);
+  ti = tbegin(h, KC_GAS_CORRECT, h->N);
+  hipLaunchKernelGGL((rhdk::k_gas_correct_tile<T, BY>), dim3(tg.corr[0], tg.corr[1], tg.corr[2]),
+                     block, 0, h->stream, gas, gh, rad, kFp, T(h->kF_s), G, GK, T(dt),
+                     tg.zc_corr, as<T>(h->b.sn[0]), as<T>(h->b.sn[1]), as<T>(h->b.sn[2]),
+                     as<T>(h->b.sn[3]), as<T>(h->b.wh[0]), as<T>(h->b.wh[1]), as<T>(h->b.wh[2]),
+                     as<T>(h->b.wh[3]), h->b.ctr);
+  tend(h, ti);
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
+
 template <typename T>
 int enqueue_pre(rhd_t* h, double dt, double chat) {
   const rhd_params& p = h->p;
@@ -488,7 +517,24 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
   }
 
   // gas Van Leer step with S_e,gas at first order
-  if (!rad_only) {
+  if (!rad_only && G.act[0] && G.act[1] && G.act[2] && h->variant == RHD_KERNELS_TILED) {
+    int rc = RHD_OK;
+    switch (h->tile_rows) {
+      case 4:
+        rc = launch_gas_tiled<T, 4>(h, dt);
+        break;
+      case 8:
+        rc = launch_gas_tiled<T, 8>(h, dt);
+        break;
+      default:
+        if constexpr (sizeof(T) == 4) {
+          rc = launch_gas_tiled<T, 16>(h, dt);
+        } else {
+          return fail(h, RHD_EINVAL, "tile rows %d not available in FP64", h->tile_rows);
+        }
+    }
+    if (rc) return rc;
+  } else if (!rad_only) {
     const rhdk::GasConst<T> GK = gas_const<T>(h);
     dim3 grid, block;
     region_launch(G.ps, grid, block);

@@ -709,16 +709,13 @@ __device__ __forceinline__ void load_gas_mapped(const GasPtrs<T>& Gp, const Geom
   U[4] = Gp.E[a];
 }
 
-// Gas predictor: first-order fluxes of U^n and S_e,gas(U^n, U_r^n), half step, on the
-// interior plus two ghost layers.
+// Gas predictor at one cell (i, j, k) of the padded region: first-order fluxes of U^n and
+// S_e,gas(U^n, U_r^n), half step, result written to the padded half-step arrays.
 template <typename T>
-__global__ void __launch_bounds__(256) k_gas_predict(GasPtrs<T> Un, GasPtrs<T> Uh, RadPtrs<T> Ur,
-                                                     const T* kF, T kF_s, Geom G, GasConst<T> K,
-                                                     T h) {
-  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
-  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
-  const int k = int(blockIdx.z) - G.g[2];
-  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+__device__ __forceinline__ void gas_predict_cell(const GasPtrs<T>& Un, const GasPtrs<T>& Uh,
+                                                 const RadPtrs<T>& Ur, const T* kF, T kF_s,
+                                                 const Geom& G, const GasConst<T>& K, T h, int i,
+                                                 int j, int k) {
   T U0[5], W0[5];
   load_gas_mapped(Un, G, i, j, k, U0);
   gas_prim(K, U0, W0);
@@ -757,6 +754,19 @@ __global__ void __launch_bounds__(256) k_gas_predict(GasPtrs<T> Un, GasPtrs<T> U
   Uh.m[1][p] = out[2];
   Uh.m[2][p] = out[3];
   Uh.E[p] = out[4];
+}
+
+// Gas predictor: first-order fluxes of U^n and S_e,gas(U^n, U_r^n), half step, on the
+// interior plus two ghost layers.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gas_predict(GasPtrs<T> Un, GasPtrs<T> Uh, RadPtrs<T> Ur,
+                                                     const T* kF, T kF_s, Geom G, GasConst<T> K,
+                                                     T h) {
+  const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
+  const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
+  const int k = int(blockIdx.z) - G.g[2];
+  if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
+  gas_predict_cell(Un, Uh, Ur, kF, kF_s, G, K, h, i, j, k);
 }
 
 // Gas corrector: MC-limited reconstruction of the primitives of U^{n+1/2}, Riemann

@@ -1,7 +1,9 @@
 """CPU replay of the index arithmetic of the tiled radiation kernels
 (paper_1306_0010_amd/csrc/rhd_tile.hpp) for every thread, block and plane: every
 global read and write stays inside its buffer, and every output cell is written
-exactly once. The replay mirrors the kernels' integer expressions line by line."""
+exactly once. The replay mirrors the kernels' integer expressions line by line. The
+tiled gas kernels (rhd_gas_tile.hpp) use the same grid, tile, ring, halo and z-chunk
+expressions with five fields per cell, so the replay covers their indexing too."""
 import numpy as np
 import pytest
 
