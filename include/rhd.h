@@ -45,6 +45,7 @@ extern "C" {
 #define RHD_ENOMEM       -4   /* device allocation failed                                   */
 #define RHD_EDEVICE      -5   /* a HIP call failed; rhd_last_error() has the HIP message    */
 #define RHD_ESTATE       -6   /* call out of order (e.g. rhd_step before rhd_set_state)     */
+#define RHD_ETIMEOUT     -7   /* rhd_server_wait: the request did not finish in time         */
 
 /* boundary kinds for rhd_params.bc[6] = {x-, x+, y-, y+, z-, z+} */
 #define RHD_BC_PERIODIC   0
@@ -244,7 +245,10 @@ int rhd_batch_remove(rhd_batch_t* b, rhd_t* h);
    member's result does not depend, bit for bit, on which other solves share the batch;
    it equals what rhd_step gives the handle alone to rounding (the kernels differ).
    nsub_out and dt_out (each NULL or room for rhd_batch_size() values, member order)
-   receive each member's nsub and dt_gas. Allocates nothing. */
+   receive each member's nsub and dt_gas. A member whose v_max is not finite and positive
+   (RHD_ENONFINITE) or that needs more than 4096 subcycles (RHD_EINVAL) stops the call
+   before anything is enqueued; nsub_out then holds -1 for that member and 0 for the
+   others, so the caller can remove it and step again. Allocates nothing. */
 int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out);
 
 /* Number of members. */
@@ -258,6 +262,88 @@ void rhd_batch_destroy(rhd_batch_t* b);
 
 /* Message of the last failure of a batch call (b may be NULL for rhd_batch_create). */
 const char* rhd_batch_last_error(const rhd_batch_t* b);
+
+/* ---- served form: independent solves submitted over time ------------------------------ */
+
+/* A server owns a worker thread that solves independent 3D problems on the HIP device
+   that was current at rhd_server_create. Requests wait in submission order; the worker
+   admits the oldest ones while the sum of their rhd_footprint_bytes stays within the
+   budget and at most max_slots run, and advances every running request one gas step per
+   round through batches (rhd_batch_*, one per precision) with tiles of tile_rows x zchunk.
+   A request leaves as soon as it has taken its steps: its state is copied to host memory,
+   its device memory and slot are freed and the next requests are admitted. Every call
+   below may come from any host thread. None of this is from the paper: it serves many
+   solves of the paper's step (Sec. 3.1) on one device. */
+typedef struct rhd_server rhd_server_t;
+
+#define RHD_REQ_QUEUED     0  /* waiting for memory or a slot                               */
+#define RHD_REQ_RUNNING    1
+#define RHD_REQ_DONE       2  /* its steps taken; the final state waits for rhd_server_fetch */
+#define RHD_REQ_FAILED     3  /* stopped with error `error` (state as computed, fetchable)   */
+#define RHD_REQ_CANCELLED  4
+
+typedef struct {
+  int status;                 /* RHD_REQ_*                                                  */
+  int error;                  /* RHD_* code of a failed request, else RHD_OK                */
+  int steps_done;             /* gas steps taken                                            */
+  long long zone_updates;     /* cells x radiation subcycles taken                          */
+  double t_submit, t_start, t_done;  /* seconds on the server's steady clock since its
+                                        creation; t_start / t_done are -1 until reached     */
+} rhd_request_info;
+
+typedef struct {
+  long long submitted, completed, failed, cancelled, rejected;
+  long long zone_updates;     /* over all requests                                          */
+  long long rounds;           /* batch steps the worker took                                */
+  long long bytes_in_use, peak_bytes;  /* sum of the running requests' footprints          */
+  int running, queued, peak_running;
+} rhd_server_stats;
+
+/* Create a server. RHD_EINVAL for budget_bytes <= 0, max_slots < 1 or a tile shape the
+   batches reject (tile_rows 4, 8 or 16; zchunk >= 1). On failure *out is NULL. */
+int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int zchunk,
+                      rhd_server_t** out);
+
+/* Queue a request: parameters and initial state as for rhd_create, rhd_set_state and
+   rhd_set_emission (j may be NULL), then `steps` gas steps, each with the CFL step and
+   subcycle count rhd_suggest_dt gives at the reduced speed of light chat. The host arrays
+   are copied before the call returns. *id receives the request's id (ids count up from
+   1). RHD_EINVAL for invalid parameters, a grid that is not 3D, steps < 1 or chat <= 0;
+   RHD_ENOMEM when the request's footprint alone exceeds the budget, so that it could
+   never be admitted (nothing is queued then). */
+int rhd_server_submit(rhd_server_t* s, const rhd_params* p, const double* rho,
+                      const double* mom, const double* E, const double* Er, const double* Fr,
+                      const double* kappaP, const double* kappaF, int kappa_scalar,
+                      const double* j, int steps, double chat, long long* id);
+
+/* Status and timing of a request, without waiting. RHD_EINVAL for an unknown id. */
+int rhd_server_poll(rhd_server_t* s, long long id, rhd_request_info* info);
+
+/* Wait until the request is done, failed or cancelled, then as rhd_server_poll.
+   timeout_s < 0 waits without limit; RHD_ETIMEOUT when the time runs out first. */
+int rhd_server_wait(rhd_server_t* s, long long id, double timeout_s, rhd_request_info* info);
+
+/* Copy the final state of a finished request (host FP64 arrays as rhd_get_state; any may
+   be NULL) and its diagnostics (may be NULL), then forget the request. Returns RHD_OK for
+   a done request, the request's error for a failed one (the state is copied as computed),
+   RHD_ESTATE for a queued, running or cancelled one, RHD_EINVAL for an unknown id. */
+int rhd_server_fetch(rhd_server_t* s, long long id, double* rho, double* mom, double* E,
+                     double* Er, double* Fr, rhd_diag* diag);
+
+/* Cancel a request. A queued one is dropped at once; a running one leaves its batch
+   before the next round, which frees its memory and slot; the other requests' results do
+   not change. A finished request is forgotten. RHD_EINVAL for an unknown id. */
+int rhd_server_cancel(rhd_server_t* s, long long id);
+
+/* Counters of the server's life so far. */
+int rhd_server_get_stats(rhd_server_t* s, rhd_server_stats* out);
+
+/* Stop the worker after its current round, drop every request and free everything.
+   No other call on this server may be in progress or follow. NULL is ignored. */
+void rhd_server_destroy(rhd_server_t* s);
+
+/* Message of the last failure of a server call (s may be NULL for rhd_server_create). */
+const char* rhd_server_last_error(const rhd_server_t* s);
 
 /* Device bytes the handle holds (state, opacities, emission and scratch). */
 long long rhd_device_bytes(const rhd_t* h);

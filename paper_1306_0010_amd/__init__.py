@@ -23,8 +23,12 @@ RHD_ENONFINITE = -3
 RHD_ENOMEM = -4
 RHD_EDEVICE = -5
 RHD_ESTATE = -6
+RHD_ETIMEOUT = -7
 ERROR_NAMES = {RHD_EINVAL: "RHD_EINVAL", RHD_ECFL: "RHD_ECFL", RHD_ENONFINITE: "RHD_ENONFINITE",
-               RHD_ENOMEM: "RHD_ENOMEM", RHD_EDEVICE: "RHD_EDEVICE", RHD_ESTATE: "RHD_ESTATE"}
+               RHD_ENOMEM: "RHD_ENOMEM", RHD_EDEVICE: "RHD_EDEVICE", RHD_ESTATE: "RHD_ESTATE",
+               RHD_ETIMEOUT: "RHD_ETIMEOUT"}
+RHD_REQ_QUEUED, RHD_REQ_RUNNING, RHD_REQ_DONE, RHD_REQ_FAILED, RHD_REQ_CANCELLED = range(5)
+REQ_STATUS_NAMES = ("queued", "running", "done", "failed", "cancelled")
 
 RHD_BC_PERIODIC, RHD_BC_OUTFLOW, RHD_BC_REFLECT = 0, 1, 2
 RHD_ISOTHERMAL = 1 << 0
@@ -44,7 +48,10 @@ EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_
             "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
             "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant", "rhd_autotune",
             "rhd_batch_create", "rhd_batch_add", "rhd_batch_remove", "rhd_batch_step",
-            "rhd_batch_size", "rhd_batch_sync", "rhd_batch_destroy", "rhd_batch_last_error")
+            "rhd_batch_size", "rhd_batch_sync", "rhd_batch_destroy", "rhd_batch_last_error",
+            "rhd_server_create", "rhd_server_submit", "rhd_server_poll", "rhd_server_wait",
+            "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats", "rhd_server_destroy",
+            "rhd_server_last_error")
 
 
 class RhdError(RuntimeError):
@@ -94,6 +101,27 @@ class rhd_timing(ctypes.Structure):
                                               "total_ms": float(self.total_ms[k]),
                                               "cells": int(self.cells[k])}
                 for k in range(self.nkernels)}
+
+
+class rhd_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("error", ctypes.c_int), ("steps_done", ctypes.c_int),
+                ("zone_updates", ctypes.c_longlong), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": REQ_STATUS_NAMES[self.status], "error": int(self.error),
+                "steps_done": int(self.steps_done), "zone_updates": int(self.zone_updates),
+                "t_submit": self.t_submit, "t_start": self.t_start, "t_done": self.t_done}
+
+
+class rhd_server_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_longlong) for name in
+                ("submitted", "completed", "failed", "cancelled", "rejected", "zone_updates",
+                 "rounds", "bytes_in_use", "peak_bytes")] + [
+        (name, ctypes.c_int) for name in ("running", "queued", "peak_running")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 _lib = None
@@ -161,6 +189,24 @@ def lib():
     L.rhd_batch_destroy.restype = None
     L.rhd_batch_last_error.argtypes = [vp]
     L.rhd_batch_last_error.restype = ctypes.c_char_p
+    L.rhd_server_create.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(vp)]
+    L.rhd_server_submit.argtypes = [vp, P, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, dp,
+                                    ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_longlong)]
+    L.rhd_server_poll.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(rhd_request_info)]
+    L.rhd_server_wait.argtypes = [vp, ctypes.c_longlong, ctypes.c_double,
+                                  ctypes.POINTER(rhd_request_info)]
+    L.rhd_server_fetch.argtypes = [vp, ctypes.c_longlong, dp, dp, dp, dp, dp,
+                                   ctypes.POINTER(rhd_diag)]
+    L.rhd_server_cancel.argtypes = [vp, ctypes.c_longlong]
+    L.rhd_server_get_stats.argtypes = [vp, ctypes.POINTER(rhd_server_stats)]
+    L.rhd_server_destroy.argtypes = [vp]
+    L.rhd_server_destroy.restype = None
+    L.rhd_server_last_error.argtypes = [vp]
+    L.rhd_server_last_error.restype = ctypes.c_char_p
+    for name in ("rhd_server_create", "rhd_server_submit", "rhd_server_poll", "rhd_server_wait",
+                 "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
                  "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
                  "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
@@ -330,6 +376,76 @@ def rhd_batch_last_error(b=None):
     return lib().rhd_batch_last_error(b).decode(errors="replace")
 
 
+def _scheck(rc, s=None):
+    if rc != RHD_OK:
+        raise RhdError(rc, lib().rhd_server_last_error(s).decode(errors="replace"))
+
+
+def rhd_server_create(budget_bytes, max_slots, tile_rows=8, zchunk=8):
+    s = ctypes.c_void_p()
+    _scheck(lib().rhd_server_create(int(budget_bytes), int(max_slots), int(tile_rows), int(zchunk),
+                                    ctypes.byref(s)))
+    return s.value
+
+
+def rhd_server_submit(s, params, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar, j, steps, chat):
+    """Queue a request; returns its id. The arrays are copied before the call returns."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in (rho, mom, E, Er, Fr, kappaP, kappaF, j)]
+    ptrs = [_dptr(a) if a is not None else None for a in arrs]
+    rid = ctypes.c_longlong()
+    _scheck(lib().rhd_server_submit(s, ctypes.byref(params), *ptrs[:7], int(kappa_scalar), ptrs[7],
+                                    int(steps), float(chat), ctypes.byref(rid)), s)
+    return rid.value
+
+
+def rhd_server_poll(s, rid):
+    info = rhd_request_info()
+    _scheck(lib().rhd_server_poll(s, int(rid), ctypes.byref(info)), s)
+    return info.as_dict()
+
+
+def rhd_server_wait(s, rid, timeout_s=-1.0):
+    """Blocks (without holding the GIL) until the request has finished; RhdError with
+    code RHD_ETIMEOUT when timeout_s runs out first."""
+    info = rhd_request_info()
+    _scheck(lib().rhd_server_wait(s, int(rid), float(timeout_s), ctypes.byref(info)), s)
+    return info.as_dict()
+
+
+def rhd_server_fetch(s, rid, N):
+    """(state dict, diagnostics dict, code) of a finished request, which is then forgotten.
+    code is RHD_OK for a done request and the request's error for a failed one; RhdError
+    for a request without a result."""
+    out = {"rho": np.empty(N), "mom": np.empty(3 * N), "E": np.empty(N), "Er": np.empty(N),
+           "Fr": np.empty(3 * N)}
+    d = rhd_diag()
+    rc = lib().rhd_server_fetch(s, int(rid), _dptr(out["rho"]), _dptr(out["mom"]), _dptr(out["E"]),
+                                _dptr(out["Er"]), _dptr(out["Fr"]), ctypes.byref(d))
+    if rc in (RHD_EINVAL, RHD_ESTATE):
+        _scheck(rc, s)
+    return out, d.as_dict(), rc
+
+
+def rhd_server_cancel(s, rid):
+    _scheck(lib().rhd_server_cancel(s, int(rid)), s)
+
+
+def rhd_server_get_stats(s):
+    st = rhd_server_stats()
+    _scheck(lib().rhd_server_get_stats(s, ctypes.byref(st)), s)
+    return st.as_dict()
+
+
+def rhd_server_destroy(s):
+    if s:
+        lib().rhd_server_destroy(s)
+
+
+def rhd_server_last_error(s=None):
+    return lib().rhd_server_last_error(s).decode(errors="replace")
+
+
 def rhd_device_bytes(h):
     return int(lib().rhd_device_bytes(h))
 
@@ -378,6 +494,33 @@ def params_from_spec(spec):
     return p
 
 
+def _flat_state(st, shape):
+    """The flat host arrays of a state dict, as rhd_set_state takes them."""
+    flat = lambda k: np.ascontiguousarray(np.broadcast_to(st[k], shape), dtype=np.float64).ravel()
+    kP = np.asarray(st["kP"], dtype=np.float64)
+    kF = np.asarray(st["kF"], dtype=np.float64)
+    scalar = kP.size == 1 or (np.all(kP == kP.flat[0]) and np.all(kF == kF.flat[0]))
+    if scalar:
+        kPa, kFa = np.array([kP.flat[0]]), np.array([kF.flat[0]])
+    else:
+        kPa, kFa = flat("kP"), flat("kF")
+    return {"rho": flat("rho"), "mom": np.concatenate([flat("mx"), flat("my"), flat("mz")]),
+            "E": flat("E"), "Er": flat("Er"),
+            "Fr": np.concatenate([flat("Fx"), flat("Fy"), flat("Fz")]),
+            "kP": kPa, "kF": kFa, "scalar": int(scalar),
+            "j": flat("j") if st.get("j") is not None else None}
+
+
+def _shaped_state(raw, shape):
+    """A state dict of (nz, ny, nx) arrays from the flat arrays rhd_get_state fills."""
+    N = int(np.prod(shape))
+    return {"rho": raw["rho"].reshape(shape), "mx": raw["mom"][:N].reshape(shape),
+            "my": raw["mom"][N:2 * N].reshape(shape), "mz": raw["mom"][2 * N:].reshape(shape),
+            "E": raw["E"].reshape(shape), "Er": raw["Er"].reshape(shape),
+            "Fx": raw["Fr"][:N].reshape(shape), "Fy": raw["Fr"][N:2 * N].reshape(shape),
+            "Fz": raw["Fr"][2 * N:].reshape(shape)}
+
+
 class Solver:
     """One handle: state in, steps, state out. ``state`` dicts hold float64 arrays of
     shape (nz, ny, nx) named rho, mx, my, mz, E, Er, Fx, Fy, Fz, kP, kF and optionally j."""
@@ -407,18 +550,10 @@ class Solver:
             pass
 
     def set_state(self, st):
-        flat = lambda k: np.ascontiguousarray(np.broadcast_to(st[k], self.shape), dtype=np.float64).ravel()
-        mom = np.concatenate([flat("mx"), flat("my"), flat("mz")])
-        Fr = np.concatenate([flat("Fx"), flat("Fy"), flat("Fz")])
-        kP = np.asarray(st["kP"], dtype=np.float64)
-        kF = np.asarray(st["kF"], dtype=np.float64)
-        scalar = kP.size == 1 or (np.all(kP == kP.flat[0]) and np.all(kF == kF.flat[0]))
-        if scalar:
-            kPa, kFa = np.array([kP.flat[0]]), np.array([kF.flat[0]])
-        else:
-            kPa, kFa = flat("kP"), flat("kF")
-        rhd_set_state(self.h, flat("rho"), mom, flat("E"), flat("Er"), Fr, kPa, kFa, scalar)
-        rhd_set_emission(self.h, flat("j") if st.get("j") is not None else None)
+        a = _flat_state(st, self.shape)
+        rhd_set_state(self.h, a["rho"], a["mom"], a["E"], a["Er"], a["Fr"], a["kP"], a["kF"],
+                      a["scalar"])
+        rhd_set_emission(self.h, a["j"])
 
     def step(self, dt_gas, chat, nsub):
         rhd_step(self.h, dt_gas, chat, nsub)
@@ -433,13 +568,7 @@ class Solver:
         return rhd_suggest_dt(self.h, chat)
 
     def get_state(self):
-        raw = rhd_get_state(self.h, self.N)
-        N, sh = self.N, self.shape
-        return {"rho": raw["rho"].reshape(sh), "mx": raw["mom"][:N].reshape(sh),
-                "my": raw["mom"][N:2 * N].reshape(sh), "mz": raw["mom"][2 * N:].reshape(sh),
-                "E": raw["E"].reshape(sh), "Er": raw["Er"].reshape(sh),
-                "Fx": raw["Fr"][:N].reshape(sh), "Fy": raw["Fr"][N:2 * N].reshape(sh),
-                "Fz": raw["Fr"][2 * N:].reshape(sh)}
+        return _shaped_state(rhd_get_state(self.h, self.N), self.shape)
 
     def diagnostics(self):
         return rhd_get_diagnostics(self.h)
@@ -453,3 +582,59 @@ class Solver:
 
     def sync(self):
         rhd_sync(self.h)
+
+
+class Server:
+    """The native server (rhd_server_*): submit independent 3D solves from any thread,
+    wait for them and fetch their final states. Its worker thread admits requests in
+    submission order within the memory budget and slot count and advances the running
+    ones one gas step per round."""
+
+    def __init__(self, budget_bytes, max_slots, tile_rows=8, zchunk=8):
+        self.s = rhd_server_create(budget_bytes, max_slots, tile_rows, zchunk)
+        self._shapes = {}
+
+    def submit(self, spec, state, chat, steps):
+        shape = (spec["nz"], spec["ny"], spec["nx"])
+        a = _flat_state(state, shape)
+        rid = rhd_server_submit(self.s, params_from_spec(spec), a["rho"], a["mom"], a["E"],
+                                a["Er"], a["Fr"], a["kP"], a["kF"], a["scalar"], a["j"], steps,
+                                chat)
+        self._shapes[rid] = shape
+        return rid
+
+    def poll(self, rid):
+        return rhd_server_poll(self.s, rid)
+
+    def wait(self, rid, timeout_s=-1.0):
+        return rhd_server_wait(self.s, rid, timeout_s)
+
+    def fetch(self, rid):
+        """(state dict, diagnostics, code) of a finished request; see rhd_server_fetch."""
+        shape = self._shapes[rid]
+        raw, diag, rc = rhd_server_fetch(self.s, rid, int(np.prod(shape)))
+        del self._shapes[rid]
+        return _shaped_state(raw, shape), diag, rc
+
+    def cancel(self, rid):
+        rhd_server_cancel(self.s, rid)
+
+    def stats(self):
+        return rhd_server_get_stats(self.s)
+
+    def close(self):
+        if self.s:
+            rhd_server_destroy(self.s)
+            self.s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,9 +6,10 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "rhd.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "rhd_device.hpp"),
-        os.path.join(os.path.dirname(HERE), "include", "rhd.h")]
+SOURCES = [os.path.join(HERE, "csrc", "rhd.hip"), os.path.join(HERE, "csrc", "rhd_server.hip")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in
+                  ("rhd_device.hpp", "rhd_tile.hpp", "rhd_gas_tile.hpp")] + [
+    os.path.join(os.path.dirname(HERE), "include", "rhd.h")]
 LIB = os.path.join(HERE, "librhd.so")
 ARCH = "gfx950"
 
@@ -32,7 +33,7 @@ def hipcc():
 def build(verbose=False):
     """Compile unconditionally; returns the path of the library."""
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-pthread", "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

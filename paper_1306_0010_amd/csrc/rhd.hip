@@ -1270,13 +1270,20 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
     rhd_t* h = b->members[i];
     const double vmax = b->h_vmax[i];
     h->vmax_last = vmax;
+    // a member that cannot step is named in nsub_out (-1) before anything is enqueued
+    auto reject = [&](int code) {
+      if (nsub_out)
+        for (int k = 0; k < S; ++k) nsub_out[k] = k == i ? -1 : 0;
+      return code;
+    };
     if (!(vmax > 0.0) || !std::isfinite(vmax))
-      return bfail(b, RHD_ENONFINITE, "member %d: v_max is %g", i, vmax);
+      return reject(bfail(b, RHD_ENONFINITE, "member %d: v_max is %g", i, vmax));
     dt[i] = h->p.cfl * h->dxmin / vmax;
     const double r = std::ceil(b->chat[i] / vmax);
     nsub[i] = r < 1.0 ? 1 : (r > BATCH_MAX_ROUNDS ? BATCH_MAX_ROUNDS + 1 : int(r));
     if (nsub[i] > BATCH_MAX_ROUNDS)
-      return bfail(b, RHD_EINVAL, "member %d needs %d subcycles (limit %d)", i, nsub[i], BATCH_MAX_ROUNDS);
+      return reject(bfail(b, RHD_EINVAL, "member %d needs %d subcycles (limit %d)", i, nsub[i],
+                          BATCH_MAX_ROUNDS));
   }
   // 2. exchange and gas step of every member
   for (int i = 0; i < S; ++i) {

@@ -19,6 +19,11 @@ admitted solve keeps its own handle and stream: the server advances the active s
 gas step each in turn, so the steps of different solves run on the device at the same
 time and a solve with few subcycles is not held back by one with many.
 
+``serve_native`` hands the same stream to the native server (``rhd_server_*``): the
+client only submits each request at its arrival and collects the results, while the
+server's own worker thread admits, batches, steps and retires the solves. The initial
+states are synthesised before the clock starts.
+
 ``serve_serial`` runs the same requests one at a time with one handle each, for
 comparison.
 """
@@ -28,9 +33,9 @@ import time
 
 import numpy as np
 
-from . import (RHD_KERNELS_TILED, Solver, params_from_spec, rhd_batch_add, rhd_batch_create,
-               rhd_batch_destroy, rhd_batch_remove, rhd_batch_step, rhd_batch_sync,
-               rhd_footprint_bytes)
+from . import (RHD_KERNELS_TILED, RhdError, Server, Solver, params_from_spec, rhd_batch_add,
+               rhd_batch_create, rhd_batch_destroy, rhd_batch_remove, rhd_batch_step,
+               rhd_batch_sync, rhd_footprint_bytes)
 
 
 class _Clock:
@@ -186,6 +191,44 @@ def serve_concurrent(requests, make_problem, budget_bytes=16 << 30, max_slots=16
                "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
                "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": peak_active,
                "gas_steps": steps_taken, "budget_bytes": budget_bytes, "max_slots": max_slots}
+    return summary, results
+
+
+def serve_native(requests, make_problem, budget_bytes=16 << 30, max_slots=64, tile_rows=8,
+                 zchunk=8, keep_results=False):
+    """Serve ``requests`` through the native server. A request's latency runs from its
+    arrival to the moment the server holds its final state in host memory (its
+    ``t_done``). Returns a summary dict and, with keep_results, the final states by id."""
+    order = sorted(requests, key=lambda r: r["arrival"])
+    problems = {r["id"]: make_problem(r) for r in order}
+    lat, results, zone_updates = {}, {}, 0
+    with Server(budget_bytes, max_slots, tile_rows, zchunk) as srv:
+        t0 = time.perf_counter()
+        ids = []
+        for req in order:
+            wait = req["arrival"] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            pb = problems[req["id"]]
+            late = (time.perf_counter() - t0) - req["arrival"]
+            ids.append((srv.submit(pb["spec"], pb["state"], pb["chat"], req["steps"]), req, late))
+        for rid, req, late in ids:
+            info = srv.wait(rid)
+            out, _, rc = srv.fetch(rid)
+            if rc:
+                raise RhdError(rc, f"request {req['id']} failed")
+            lat[req["id"]] = late + info["t_done"] - info["t_submit"]
+            zone_updates += info["zone_updates"]
+            if keep_results:
+                results[req["id"]] = out
+        elapsed = time.perf_counter() - t0
+        st = srv.stats()
+    p50, p99 = _percentiles(list(lat.values()))
+    summary = {"mode": "native_server", "requests": len(lat), "zone_updates": zone_updates,
+               "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
+               "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": st["peak_running"],
+               "batch_steps": st["rounds"], "peak_bytes": st["peak_bytes"],
+               "budget_bytes": budget_bytes, "max_slots": max_slots}
     return summary, results
 
 
