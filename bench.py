@@ -243,37 +243,60 @@ def c4_measurement(P, ri, stream, steps):
             "tile": {"tile_rows": TILE_C3[0], "zchunk": TILE_C3[1]}}
 
 
+def progress(msg):
+    """A progress line on stderr; stdout carries only the result line."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def serving(count, load):
     """The served-batch workload: a stream of independent periodic boxes (32^3..192^3,
     kappa log-uniform in [1, 1e3], chat/a0 in [5, 50], 20 gas steps each). The
     one-at-a-time capacity is measured first with every request queued at t = 0; the
     Poisson arrivals are then scaled so that the offered load is ``load`` times that
     capacity, and the same stream is served with packed-tile batching, with concurrent
-    per-solve streams and one at a time. The capacity of each mode (all requests queued
-    at t = 0) closes the measurement."""
+    per-solve streams, through the native server and one at a time. The capacity of each
+    mode (all requests queued at t = 0) closes the measurement."""
     import rhd_inputs as ri
     from paper_1306_0010_amd import serve
 
     reqs = ri.c5_requests(count=count, load=load)
-    make = lambda r: ri.c5_problem(r)
+    problems = {}  # each request's initial state is synthesised once and reused
+
+    def make(r):
+        if r["id"] not in problems:
+            problems[r["id"]] = ri.c5_problem(r)
+        return problems[r["id"]]
+
     at_zero = [dict(r, arrival=0.0) for r in reqs]
     cap, _ = serve.serve_serial(at_zero, make, variant=serve.DEFAULT_VARIANT)
     service = cap["elapsed_s"] / count
+    progress(f"serving: one-at-a-time capacity measured ({cap['elapsed_s']:.1f} s)")
     timed = [dict(r, arrival=r["arrival"] * service) for r in reqs]
     batched, _ = serve.serve_batched(timed, make)
+    progress("serving: batched stream done")
     concurrent, _ = serve.serve_concurrent(timed, make, variant=serve.DEFAULT_VARIANT)
+    progress("serving: concurrent stream done")
+    native, _ = serve.serve_native(timed, make)
+    progress("serving: native-server stream done")
     serial, _ = serve.serve_serial(timed, make, variant=serve.DEFAULT_VARIANT)
+    progress("serving: one-at-a-time stream done")
     # capacity: every request queued at t = 0
     cap_b, _ = serve.serve_batched(at_zero, make)
     cap_c, _ = serve.serve_concurrent(at_zero, make, variant=serve.DEFAULT_VARIANT)
+    cap_n, _ = serve.serve_native(at_zero, make)
+    progress("serving: capacities measured")
     capacity = {m: c["zone_updates_per_s"] for m, c in
-                (("batched", cap_b), ("concurrent", cap_c), ("one_at_a_time", cap))}
+                (("batched", cap_b), ("concurrent", cap_c), ("native_server", cap_n),
+                 ("one_at_a_time", cap))}
     return {"requests": count, "offered_load": load,
             "one_at_a_time_capacity_requests_per_s": 1.0 / service,
-            "batched": batched, "concurrent": concurrent, "one_at_a_time": serial,
+            "batched": batched, "concurrent": concurrent, "native_server": native,
+            "one_at_a_time": serial,
             "batched_over_one_at_a_time_zone_updates": batched["zone_updates_per_s"]
             / serial["zone_updates_per_s"],
             "concurrent_over_one_at_a_time_zone_updates": concurrent["zone_updates_per_s"]
+            / serial["zone_updates_per_s"],
+            "native_server_over_one_at_a_time_zone_updates": native["zone_updates_per_s"]
             / serial["zone_updates_per_s"],
             "capacity_zone_updates_per_s": capacity}
 
@@ -387,6 +410,7 @@ def main():
         timing = P.rhd_get_timing(h)
         P.rhd_set_timing(h, 0)
     solver.close()
+    progress(f"headline workload timed ({elapsed:.2f} s)")
 
     value = ncell * subcycles / elapsed
     out = {
@@ -423,12 +447,15 @@ def main():
                                                "exch_bisect", "newton_max")}
     if args.c3_subcycles > 0 and args.precision == "mixed":
         out["c3_point_source"] = c3_measurement(P, ri, stream, args.c3_subcycles, args.autotune)
+        progress("256^3 point source timed")
     if args.c4_steps > 0 and args.precision == "mixed":
         out["c4_dusty_shell"] = c4_measurement(P, ri, stream, args.c4_steps)
+        progress("256^3 dusty shell timed")
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
+        progress("oracle timed on the host")
     print(json.dumps(out), flush=True)
 
 
