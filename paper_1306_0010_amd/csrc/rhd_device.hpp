@@ -155,11 +155,16 @@ __device__ __forceinline__ double mc_slope(double dm, double dp) {
   return dm > 0.0 ? m : -m;
 }
 
-// FP32: minmod(a, b) is the median of (a, b, 0), and the three-argument minmod is
-// minmod(a, minmod(b, c)), so the limiter is two v_med3_f32 with no branch.
-__device__ __forceinline__ float mc_slope(float dm, float dp) {
-  const float inner = __builtin_amdgcn_fmed3f(2.0f * dp, 0.5f * (dm + dp), 0.0f);
-  return __builtin_amdgcn_fmed3f(2.0f * dm, inner, 0.0f);
+// Half the limited slope, the offset from the cell value to its face states. FP32:
+// minmod(a, b) is the median of (a, b, 0), the three-argument minmod is
+// minmod(a, minmod(b, c)), and halving every argument of a median halves it exactly,
+// so the half slope is minmod(dm, dp, (dm + dp)/4): two v_med3_f32, no branch.
+__device__ __forceinline__ double mc_half_slope(double dm, double dp) {
+  return 0.5 * mc_slope(dm, dp);
+}
+__device__ __forceinline__ float mc_half_slope(float dm, float dp) {
+  const float inner = __builtin_amdgcn_fmed3f(dp, 0.25f * (dm + dp), 0.0f);
+  return __builtin_amdgcn_fmed3f(dm, inner, 0.0f);
 }
 
 // Sum of v over the wavefront; lane 0 adds it to *ctr. Every lane must call it.
@@ -550,13 +555,13 @@ __global__ void __launch_bounds__(256) k_rad_correct(RadPtrs<T> Um, RadPtrs<T> U
       T Lm[4], Rm[4], Lp[4], Rp[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const T sm = mc_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
-        const T s0 = mc_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
-        const T sp = mc_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
-        Lm[q] = Um1[q] + T(0.5) * sm;
-        Rm[q] = Uc[q] - T(0.5) * s0;
-        Lp[q] = Uc[q] + T(0.5) * s0;
-        Rp[q] = Up1[q] - T(0.5) * sp;
+        const T sm = mc_half_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
+        const T s0 = mc_half_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
+        const T sp = mc_half_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
+        Lm[q] = Um1[q] + sm;
+        Rm[q] = Uc[q] - s0;
+        Lp[q] = Uc[q] + s0;
+        Rp[q] = Up1[q] - sp;
       }
       T fl[4], fr[4];
       rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
@@ -810,13 +815,13 @@ __global__ void __launch_bounds__(256) k_gas_correct(GasPtrs<T> Un, GasPtrs<T> U
       T Lm[5], Rm[5], Lp[5], Rp[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const T sm = mc_slope(W[1][q] - W[0][q], W[2][q] - W[1][q]);
-        const T s0 = mc_slope(W[2][q] - W[1][q], W[3][q] - W[2][q]);
-        const T sp = mc_slope(W[3][q] - W[2][q], W[4][q] - W[3][q]);
-        Lm[q] = W[1][q] + T(0.5) * sm;
-        Rm[q] = W[2][q] - T(0.5) * s0;
-        Lp[q] = W[2][q] + T(0.5) * s0;
-        Rp[q] = W[3][q] - T(0.5) * sp;
+        const T sm = mc_half_slope(W[1][q] - W[0][q], W[2][q] - W[1][q]);
+        const T s0 = mc_half_slope(W[2][q] - W[1][q], W[3][q] - W[2][q]);
+        const T sp = mc_half_slope(W[3][q] - W[2][q], W[4][q] - W[3][q]);
+        Lm[q] = W[1][q] + sm;
+        Rm[q] = W[2][q] - s0;
+        Lp[q] = W[2][q] + s0;
+        Rp[q] = W[3][q] - sp;
       }
       T fl[5], fr[5];
       gas_riemann(K, Lm, Rm, d, fl);

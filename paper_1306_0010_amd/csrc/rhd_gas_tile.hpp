@@ -259,8 +259,9 @@ __global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_gas_pr
                                                                    T kF_s, Geom G, GasConst<T> K,
                                                                    T h, int zc) {
   __shared__ GasPredictShared<T, BY> sh;
-  gas_predict_tile_body<T, BY>(Un, Uh, Ur, kF, kF_s, G, K, h, zc, int(blockIdx.x),
-                               int(blockIdx.y), int(blockIdx.z), sh);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  gas_predict_tile_body<T, BY>(Un, Uh, Ur, kF, kF_s, G, K, h, zc, bx, by, bz, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -284,10 +285,8 @@ __device__ __forceinline__ void gas_face_flux(const GasConst<T>& K, const T a[5]
   T L[5], R[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    const T sb = mc_slope(b[q] - a[q], c[q] - b[q]);
-    const T sc = mc_slope(c[q] - b[q], d[q] - c[q]);
-    L[q] = b[q] + T(0.5) * sb;
-    R[q] = c[q] - T(0.5) * sc;
+    L[q] = b[q] + mc_half_slope(b[q] - a[q], c[q] - b[q]);
+    R[q] = c[q] - mc_half_slope(c[q] - b[q], d[q] - c[q]);
   }
   gas_riemann(K, L, R, dir, f);
 }
@@ -367,9 +366,9 @@ __device__ __forceinline__ void gas_correct_tile_body(
       T mz[5], pz[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const T sz = mc_slope(Wz0[q] - Wzm[q], Wzp[q] - Wz0[q]);
-        mz[q] = Wz0[q] - T(0.5) * sz;
-        pz[q] = Wz0[q] + T(0.5) * sz;
+        const T sz = mc_half_slope(Wz0[q] - Wzm[q], Wzp[q] - Wz0[q]);
+        mz[q] = Wz0[q] - sz;
+        pz[q] = Wz0[q] + sz;
       }
       T fz[5] = {T(0), T(0), T(0), T(0), T(0)};
       if (t > z0 - 1) gas_riemann(K, zplus, mz, 2, fz);
@@ -472,9 +471,10 @@ __global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_gas_co
     T h, int zc, T* sn0, T* sn1, T* sn2, T* sn3, T* wh0, T* wh1, T* wh2, T* wh3,
     unsigned long long* ctr) {
   __shared__ GasCorrectShared<T, BY> sh;
-  gas_correct_tile_body<T, BY>(Un, Uh, Ur, kF, kF_s, G, K, h, zc, int(blockIdx.x),
-                               int(blockIdx.y), int(blockIdx.z), sn0, sn1, sn2, sn3, wh0, wh1,
-                               wh2, wh3, ctr, sh);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  gas_correct_tile_body<T, BY>(Un, Uh, Ur, kF, kF_s, G, K, h, zc, bx, by, bz, sn0, sn1, sn2,
+                               sn3, wh0, wh1, wh2, wh3, ctr, sh);
 }
 
 }  // namespace rhdk

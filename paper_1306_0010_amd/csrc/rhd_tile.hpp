@@ -19,6 +19,9 @@
 namespace rhdk {
 
 constexpr int TILE_BX = 64;
+// Minimum wavefronts per SIMD the FP32 predictor is compiled for (HIP's second launch
+// bound): 4 leaves it 128 VGPRs; more waves spill.
+constexpr int PREDICT_WAVES_FP32 = 4;
 
 __host__ __device__ __forceinline__ int clamp_i(int q, int lo, int hi) {
   return q < lo ? lo : (q > hi ? hi : q);
@@ -29,6 +32,27 @@ __host__ __device__ __forceinline__ int clamp_i(int q, int lo, int hi) {
 __host__ __device__ __forceinline__ int balanced_chunk(int L, int zc) {
   const int chunks = (L + zc - 1) / zc;
   return (L + chunks - 1) / chunks;
+}
+
+// XCD-aware tile order. The dispatcher hands workgroup L (x fastest over the grid) to
+// XCD L mod 8, and each XCD has its own L2. Tile L of a launch of N is therefore
+// renumbered so that every XCD gets one contiguous range of tiles in x-fastest order:
+// the x and y neighbours of a tile, whose rows hold its halo cells, then run on the same
+// XCD at about the same time and the shared cache lines come from its L2 instead of
+// memory. The map is a permutation of [0, N).
+__host__ __device__ __forceinline__ int xcd_tile(int L, int N) {
+  const int j = L & 7, k = L >> 3, q = N >> 3, r = N & 7;
+  return j * q + (j < r ? j : r) + k;
+}
+
+// Tile coordinates of this block of a 3D tile grid in the XCD-aware order.
+__device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
+  const int gx = int(gridDim.x), gy = int(gridDim.y);
+  const int L = int(blockIdx.x) + gx * (int(blockIdx.y) + gy * int(blockIdx.z));
+  const int T = xcd_tile(L, gx * gy * int(gridDim.z));
+  bx = T % gx;
+  by = (T / gx) % gy;
+  bz = T / (gx * gy);
 }
 
 template <typename T>
@@ -111,13 +135,59 @@ __device__ __forceinline__ FaceSide<T> side_at(const RadPtrs<T>& Um, const Geom&
 // within [-2, n2 + 2). Block bx = ntx evaluates the four ghost columns x = -2, -1, n0,
 // n0 + 1 of the same y-z range cell by cell.
 
+// Inside a row the x faces need no LDS: a row is one wavefront, and lane i takes the
+// closure data of lane i - 1 and the flux of lane i + 1 by a cross-lane shift. Only the
+// two faces on the row's ends go through LDS. Keeping the x data out of LDS halves the
+// block's LDS, so that four blocks fit on a CU instead of two.
 template <typename T, int BY>
 struct PredictShared {
-  SideTile<T, BY, TILE_BX + 2> sx;  // [r][c]: x data of cell (x0 - 1 + c, y0 + r)
   SideTile<T, BY + 2, TILE_BX> sy;  // [r][c]: y data of cell (x0 + c, y0 - 1 + r)
-  V4<T> fx[BY][TILE_BX + 1];        // [r][i]: flux through the low x face of (x0 + i, y0 + r)
+  SideTile<T, BY, 4> sxe;           // [r][k]: x data of cells x0 - 1, x0, x0 + 63, x0 + 64
+  V4<T> fxe[BY][2];                 // [r][k]: flux through the x face x0 (k = 0), x0 + 64 (1)
   V4<T> fy[BY + 1][TILE_BX];        // [j][c]: flux through the low y face of (x0 + c, y0 + j)
 };
+
+// Cross-lane shifts within a wavefront (DPP wave_shr:1 / wave_shl:1): lane i receives
+// the value of lane i - 1 (from_left) or lane i + 1 (from_right); the lane at the end,
+// which has no such neighbour, keeps `edge`. Every lane of the wavefront must be active.
+__device__ __forceinline__ float lane_from_left(float v, float edge) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_right(float v, float edge) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_shift64(double v, double edge, bool left) {
+  const long long a = __double_as_longlong(v), e = __double_as_longlong(edge);
+  const int lo = int(a & 0xffffffffLL), hi = int(a >> 32);
+  const int elo = int(e & 0xffffffffLL), ehi = int(e >> 32);
+  const int rlo = left ? __builtin_amdgcn_update_dpp(elo, lo, 0x138, 0xF, 0xF, false)
+                       : __builtin_amdgcn_update_dpp(elo, lo, 0x130, 0xF, 0xF, false);
+  const int rhi = left ? __builtin_amdgcn_update_dpp(ehi, hi, 0x138, 0xF, 0xF, false)
+                       : __builtin_amdgcn_update_dpp(ehi, hi, 0x130, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(rhi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(rlo)));
+}
+__device__ __forceinline__ double lane_from_left(double v, double edge) {
+  return lane_shift64(v, edge, true);
+}
+__device__ __forceinline__ double lane_from_right(double v, double edge) {
+  return lane_shift64(v, edge, false);
+}
+
+template <typename T>
+__device__ __forceinline__ FaceSide<T> side_from_left(const FaceSide<T>& s) {
+  FaceSide<T> q;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    q.U[k] = lane_from_left(s.U[k], s.U[k]);
+    q.Phi[k] = lane_from_left(s.Phi[k], s.Phi[k]);
+  }
+  q.lmin = lane_from_left(s.lmin, s.lmin);
+  q.lmax = lane_from_left(s.lmax, s.lmax);
+  return q;
+}
 
 template <typename T, int BY>
 __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
@@ -152,8 +222,8 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   // extra items, one per wavefront on different SIMDs (wave w runs on SIMD w mod 4):
   // before the first barrier wave 0 brings the y data of row y0 - 1, wave 1 that of row
   // y0 + BY and lanes < 2 BY of wave 2 the x data of cells x0 - 1 and x0 + 64 of row
-  // lane mod BY; between the barriers wave 3 takes the high y faces and lanes < BY of
-  // wave 0 the high x faces
+  // lane mod BY; between the barriers wave 3 takes the high y faces and lanes < 2 BY of
+  // wave 0 the x faces on the two ends of row lane mod BY
   const int hrole = ty == 0 ? 1 : (ty == 1 ? 2 : ((ty == 2 && tx < 2 * BY) ? 3 : 0));
   const int hrow = tx % BY;
   const int hx = hrole == 3 ? (tx < BY ? x0 - 1 : min(x0 + TILE_BX, n0 + 2)) : xl;
@@ -203,8 +273,13 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
 #pragma unroll
     for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     if (t >= z0 && t < z1) {
-      // x and y faces of plane t
-      sh.sx.put(ty, tx + 1, side_dir(m, U, 0, c, ic, chat));
+      // x faces of plane t inside the row (lane 0's is redone below), y data to LDS
+      T fl[4];
+      {
+        const FaceSide<T> sxo = side_dir(m, U, 0, c, ic, chat);
+        hll(side_from_left(sxo), sxo, fl);
+        if (tx == 0 || tx == TILE_BX - 1) sh.sxe.put(ty, tx == 0 ? 1 : 2, sxo);
+      }
       sh.sy.put(ty + 1, tx, side_dir(m, U, 1, c, ic, chat));
       if (hrole) {
         T H[4] = {Hn[0], Hn[1], Hn[2], Hn[3]};
@@ -215,19 +290,19 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
         else if (hrole == 2)
           sh.sy.put(BY + 1, tx, hs);
         else
-          sh.sx.put(hrow, tx < BY ? 0 : TILE_BX + 1, hs);
+          sh.sxe.put(hrow, tx < BY ? 0 : 3, hs);
         if (t + 1 < z1) load_rad_raw(Um, G, hx, hy, t + 1, Hn, nH);
       }
       __syncthreads();
-      T fl[4], fb[4];
-      hll(sh.sx.get(ty, tx), sh.sx.get(ty, tx + 1), fl);
+      T fb[4];
       hll(sh.sy.get(ty, tx), sh.sy.get(ty + 1, tx), fb);
-      put4(sh.fx[ty][tx], fl);
       put4(sh.fy[ty][tx], fb);
-      if (ty == 0 && tx < BY) {
+      if (ty == 0 && tx < 2 * BY) {
+        // x face x0 (lanes < BY) or x0 + 64 (lanes BY .. 2 BY - 1) of row lane mod BY
+        const int k = tx < BY ? 0 : 1;
         T f[4];
-        hll(sh.sx.get(tx, TILE_BX), sh.sx.get(tx, TILE_BX + 1), f);
-        put4(sh.fx[tx][TILE_BX], f);
+        hll(sh.sxe.get(hrow, 2 * k), sh.sxe.get(hrow, 2 * k + 1), f);
+        put4(sh.fxe[hrow][k], f);
       }
       if (ty == 3) {
         T f[4];
@@ -235,8 +310,15 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
         put4(sh.fy[BY][tx], f);
       }
       __syncthreads();
-      T fr[4], ft[4];
-      get4(sh.fx[ty][tx + 1], fr);
+      T fr[4], ft[4], fe[4], f0[4];
+      get4(sh.fxe[ty][1], fe);
+      get4(sh.fxe[ty][0], f0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fr[q] = lane_from_right(fl[q], fe[q]);
+      if (tx == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fl[q] = f0[q];
+      }
       get4(sh.fy[ty + 1][tx], ft);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -246,12 +328,13 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
 }
 
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_FP32 : 2) k_rad_predict_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
                                                                    GasView<T> gas, Geom G,
                                                                    RadConst<T> K, T h, int zc) {
   __shared__ PredictShared<T, BY> sh;
-  rad_predict_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, int(blockIdx.x), int(blockIdx.y),
-                               int(blockIdx.z), sh);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  rad_predict_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, bx, by, bz, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,10 +347,13 @@ __global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_rad_pr
 // within [0, n). The current plane of U^{m+1/2} sits in LDS with a two-cell ring; the
 // ring's cells of the next plane are loaded while the current one is processed.
 
+// As in the predictor, the x faces inside a row use cross-lane shifts: lane i limits its
+// own cell only and takes the high-side state of lane i - 1 and the flux of lane i + 1,
+// so every x slope is evaluated once; the two faces on the row's ends go through LDS.
 template <typename T, int BY>
 struct CorrectShared {
   V4<T> U[BY + 4][TILE_BX + 4];  // [r][c]: U^{m+1/2} of cell (x0 - 2 + c, y0 - 2 + r)
-  V4<T> fx[BY][TILE_BX + 1];     // [r][i]: flux through the low x face of (x0 + i, y0 + r)
+  V4<T> fxe[BY][2];              // [r][k]: flux through the x face x0 (k = 0), x0 + 64 (1)
   V4<T> fy[BY + 1][TILE_BX];     // [j][c]: flux through the low y face of (x0 + c, y0 + j)
 };
 
@@ -293,15 +379,15 @@ struct CorrectRing {
 };
 
 // MC-limited face states of a cell with neighbours um (below) and up (above) along one
-// direction: lo on its low face, hi on its high face; s is the limited slope.
+// direction: lo on its low face, hi on its high face.
 template <typename T>
 __device__ __forceinline__ void mc_states(const T um[4], const T u[4], const T up[4], T lo[4],
-                                          T hi[4], T s[4]) {
+                                          T hi[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    s[q] = mc_slope(u[q] - um[q], up[q] - u[q]);
-    lo[q] = u[q] - T(0.5) * s[q];
-    hi[q] = u[q] + T(0.5) * s[q];
+    const T hs = mc_half_slope(u[q] - um[q], up[q] - u[q]);
+    lo[q] = u[q] - hs;
+    hi[q] = u[q] + hs;
   }
 }
 
@@ -310,9 +396,9 @@ __device__ __forceinline__ void mc_states(const T um[4], const T u[4], const T u
 template <typename T>
 __device__ __forceinline__ void face_flux4(const T a[4], const T b[4], const T cc[4], const T d[4],
                                            int dir, T c, T ic, T chat, T f[4]) {
-  T lo[4], hi[4], s[4], bh[4], cl[4];
-  mc_states(a, b, cc, lo, bh, s);
-  mc_states(b, cc, d, cl, hi, s);
+  T lo[4], hi[4], bh[4], cl[4];
+  mc_states(a, b, cc, lo, bh);
+  mc_states(b, cc, d, cl, hi);
   hll(face_side(bh, dir, c, ic, chat), face_side(cl, dir, c, ic, chat), f);
 }
 
@@ -385,8 +471,8 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
     if (t < z1) load_padded4(Uh, pcol + (t + 2) * zs, Upp);
     // z: limited states of the own cell; the low z face pairs them with plane t-1
     {
-      T mz[4], pz[4], sz[4];
-      mc_states(Uzm, Uz0, Uzp, mz, pz, sz);
+      T mz[4], pz[4];
+      mc_states(Uzm, Uz0, Uzp, mz, pz);
       T fz[4] = {T(0), T(0), T(0), T(0)};
       if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, chat), fz);
       if (t > z0 && out_xy) {
@@ -422,11 +508,14 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
       __syncthreads();
       T fl[4], fb[4];
       {
-        T a[4], b[4], d[4];
-        get4(sh.U[ty + 2][tx], a);
+        // lane 0's low x face is replaced by the row-end item below
+        T b[4], d[4], lo[4], hi[4], bh[4];
         get4(sh.U[ty + 2][tx + 1], b);
         get4(sh.U[ty + 2][tx + 3], d);
-        face_flux4(a, b, Uz0, d, 0, c, ic, chat, fl);
+        mc_states(b, Uz0, d, lo, hi);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bh[q] = lane_from_left(hi[q], hi[q]);
+        hll(face_side(bh, 0, c, ic, chat), face_side(lo, 0, c, ic, chat), fl);
       }
       {
         T a[4], b[4], d[4];
@@ -435,18 +524,19 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[ty + 3][tx + 2], d);
         face_flux4(a, b, Uz0, d, 1, c, ic, chat, fb);
       }
-      put4(sh.fx[ty][tx], fl);
       put4(sh.fy[ty][tx], fb);
       // extra items on waves of different SIMDs (wave w runs on SIMD w mod 4)
-      if (ty == 0 && tx < BY) {
-        // high x face of row tx: cells x0 + 62 ... x0 + 65
+      if (ty == 0 && tx < 2 * BY) {
+        // x face x0 (lanes < BY: cells x0 - 2 ... x0 + 1) or x0 + 64 (lanes BY .. 2 BY - 1:
+        // cells x0 + 62 ... x0 + 65) of row lane mod BY
+        const int r = tx % BY, k = tx < BY ? 0 : 1, c0 = k ? TILE_BX : 0;
         T a[4], b[4], cc[4], d[4], f[4];
-        get4(sh.U[tx + 2][TILE_BX], a);
-        get4(sh.U[tx + 2][TILE_BX + 1], b);
-        get4(sh.U[tx + 2][TILE_BX + 2], cc);
-        get4(sh.U[tx + 2][TILE_BX + 3], d);
+        get4(sh.U[r + 2][c0], a);
+        get4(sh.U[r + 2][c0 + 1], b);
+        get4(sh.U[r + 2][c0 + 2], cc);
+        get4(sh.U[r + 2][c0 + 3], d);
         face_flux4(a, b, cc, d, 0, c, ic, chat, f);
-        put4(sh.fx[tx][TILE_BX], f);
+        put4(sh.fxe[r][k], f);
       }
       if (ty == BY - 1) {
         // high y face of column tx: rows y0 + BY - 2 ... y0 + BY + 1
@@ -458,8 +548,15 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         put4(sh.fy[BY][tx], f);
       }
       __syncthreads();
-      T fr[4], ft[4];
-      get4(sh.fx[ty][tx + 1], fr);
+      T fr[4], ft[4], fe[4], f0[4];
+      get4(sh.fxe[ty][1], fe);
+      get4(sh.fxe[ty][0], f0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fr[q] = lane_from_right(fl[q], fe[q]);
+      if (tx == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fl[q] = f0[q];
+      }
       get4(sh.fy[ty + 1][tx], ft);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -482,8 +579,9 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um
                                                                    RadConst<T> K, T h, int zc,
                                                                    unsigned long long* ctr) {
   __shared__ CorrectShared<T, BY> sh;
-  rad_correct_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, int(blockIdx.x), int(blockIdx.y),
-                               int(blockIdx.z), ctr, sh);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  rad_correct_tile_body<T, BY>(Um, Uh, gas, G, K, h, zc, bx, by, bz, ctr, sh);
 }
 
 // Tile counts of the two launches for a grid n and requested chunk length zc, with the
@@ -524,14 +622,16 @@ struct SolveDesc {
   unsigned long long* ctr;
 };
 
-// Tile i of a launch is (solve, bx, by, bz) = tiles[i]; blocks past ntiles exit at once,
-// so one grid size serves every round.
+// Tile i of a launch is (solve, bx, by, bz) = tiles[i], taken in the XCD-aware order over
+// the ntiles active blocks; blocks past ntiles exit at once, so one grid size serves
+// every round.
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? 4 : 2) k_rad_predict_batch(const SolveDesc<T>* __restrict__ sd,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_FP32 : 2) k_rad_predict_batch(const SolveDesc<T>* __restrict__ sd,
                                                                     const int4* __restrict__ tiles,
                                                                     const int* __restrict__ ntiles) {
-  if (int(blockIdx.x) >= *ntiles) return;
-  const int4 tr = tiles[blockIdx.x];
+  const int nt = *ntiles;
+  if (int(blockIdx.x) >= nt) return;
+  const int4 tr = tiles[xcd_tile(int(blockIdx.x), nt)];
   const SolveDesc<T> d = sd[tr.x];
   __shared__ PredictShared<T, BY> sh;
   rad_predict_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_pred, d.zc_pred, tr.y, tr.z, tr.w,
@@ -542,8 +642,9 @@ template <typename T, int BY>
 __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_batch(const SolveDesc<T>* __restrict__ sd,
                                                                     const int4* __restrict__ tiles,
                                                                     const int* __restrict__ ntiles) {
-  if (int(blockIdx.x) >= *ntiles) return;
-  const int4 tr = tiles[blockIdx.x];
+  const int nt = *ntiles;
+  if (int(blockIdx.x) >= nt) return;
+  const int4 tr = tiles[xcd_tile(int(blockIdx.x), nt)];
   const SolveDesc<T> d = sd[tr.x];
   __shared__ CorrectShared<T, BY> sh;
   rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, d.zc_corr, tr.y, tr.z, tr.w,

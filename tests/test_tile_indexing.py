@@ -99,7 +99,8 @@ def replay(n, bc, BY, zc):
                 need = (x <= n0) & (y <= n1 + 2)
                 assert np.array_equal(xl[need], x[need]) and np.array_equal(yl[need], y[need])
                 # extra items: wave 0 brings the y data of row y0 - 1, wave 1 that of row
-                # y0 + BY, lanes < 2 BY of wave 2 the x data of cells x0 - 1 and x0 + 64
+                # y0 + BY, lanes < 2 BY of wave 2 the x data of cells x0 - 1 and x0 + 64;
+                # lanes 0 and 63 of every row store their own x data
                 hrole = np.where(ty == 0, 1, np.where(ty == 1, 2, np.where((ty == 2) & (tx < 2 * BY), 3, 0)))
                 hrow = tx % BY
                 hx = np.where(hrole == 3, np.where(tx < BY, x0 - 1, np.minimum(x0 + BX, n0 + 2)), xl)
@@ -107,11 +108,16 @@ def replay(n, bc, BY, zc):
                               np.where(hrole == 2, min(y0 + BY, n1 + 2), np.minimum(y0 + hrow, n1 + 2)))
                 slots = sorted([("sy", 0, int(c)) for c in tx[hrole == 1]]
                                + [("sy", BY + 1, int(c)) for c in tx[hrole == 2]]
-                               + [("sx", int(r), 0 if t < BY else BX + 1)
-                                  for r, t in zip(hrow[hrole == 3], tx[hrole == 3])])
-                # every LDS slot outside the tile is written once per plane
-                assert slots == sorted([("sx", r, 0) for r in range(BY)] + [("sx", r, BX + 1) for r in range(BY)]
+                               + [("sxe", int(r), 0 if t < BY else 3)
+                                  for r, t in zip(hrow[hrole == 3], tx[hrole == 3])]
+                               + [("sxe", int(r), 1 if t == 0 else 2)
+                                  for r, t in zip(ty, tx) if t == 0 or t == BX - 1])
+                # every LDS slot of the halo and row-end data is written once per plane
+                assert slots == sorted([("sxe", r, k) for r in range(BY) for k in range(4)]
                                        + [("sy", 0, c) for c in range(BX)] + [("sy", BY + 1, c) for c in range(BX)])
+                # the row-end x faces: lanes < 2 BY of wave 0, face k of row lane mod BY
+                ends = sorted((int(t % BY), 0 if t < BY else 1) for t in tx[(ty == 0) & (tx < 2 * BY)])
+                assert ends == sorted((r, k) for r in range(BY) for k in range(2))
                 live = hrole > 0
                 for t in range(z0 - 1, z1 + 1):
                     check_mapped(xl, yl, t)
@@ -173,3 +179,19 @@ def replay(n, bc, BY, zc):
 @pytest.mark.parametrize("BY,zc", [(4, 16), (8, 16), (16, 5), (8, 1), (4, 7)])
 def test_tiled_kernel_indexing(n, bc, BY, zc):
     replay(n, bc, BY, zc)
+
+
+def xcd_tile(L, N):
+    """The kernels' XCD-aware renumbering of block L of a launch of N blocks."""
+    j, k, q, r = L & 7, L >> 3, N >> 3, N & 7
+    return j * q + min(j, r) + k
+
+
+@pytest.mark.parametrize("N", [1, 2, 7, 8, 9, 15, 16, 17, 63, 64, 65, 867, 2805, 4096, 10007])
+def test_xcd_tile_order_is_a_permutation(N):
+    T = [xcd_tile(L, N) for L in range(N)]
+    assert sorted(T) == list(range(N))
+    # every XCD (L mod 8) gets one contiguous range of tiles, in order
+    for j in range(8):
+        mine = T[j::8]
+        assert mine == list(range(mine[0], mine[0] + len(mine))) if mine else True
