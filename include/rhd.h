@@ -51,6 +51,12 @@ extern "C" {
 #define RHD_BC_PERIODIC   0
 #define RHD_BC_OUTFLOW    1   /* zero-gradient copy of the edge cell                        */
 #define RHD_BC_REFLECT    2   /* mirror image; the normal momentum and flux change sign     */
+#define RHD_BC_FIXED      3   /* fixed radiation state (rhd_set_boundary) in every ghost cell
+                                 beyond the face, in U^m and U^{m+1/2}; a cell beyond several
+                                 fixed faces takes the last in the order x, y, z. The gas
+                                 continues zero-gradient. Needs RHD_RAD_ONLY; such handles
+                                 run the per-cell radiation kernels and cannot join a batch.
+                                 For driven problems such as the Marshak wave (Sec. 4.2.3). */
 
 /* rhd_params.flags */
 #define RHD_ISOTHERMAL          (1u << 0)  /* P = rho iso_cs^2, no gas energy equation     */
@@ -64,6 +70,10 @@ extern "C" {
 #define RHD_RAD_ONLY            (1u << 4)  /* gas frozen: no gas transport, no correction  */
 #define RHD_PRECISION_MIXED     (1u << 5)  /* FP32 storage and stencils, FP64 exchange and
                                               ledger; without it everything is FP64        */
+#define RHD_GAS_CV_T3           (1u << 6)  /* heat capacity c_v = cv_alpha T^3 (Sec. 4.2.3):
+                                              a_R T^4 = (4 a_R / cv_alpha) e, so the exchange
+                                              (theta-scheme of Eq. source:energyupdate) is
+                                              linear in e. Needs RHD_RAD_ONLY, ideal gas   */
 
 typedef struct {
   int nx, ny, nz;               /* interior cells; a dimension with n = 1 is inactive      */
@@ -83,6 +93,7 @@ typedef struct {
   int bc[6];                    /* RHD_BC_* per face x-, x+, y-, y+, z-, z+; periodic faces
                                    come in pairs; reflecting faces need n >= 3             */
   unsigned flags;               /* RHD_* flags above                                        */
+  double cv_alpha;              /* alpha of c_v = alpha T^3 with RHD_GAS_CV_T3, else unused */
 } rhd_params;
 
 typedef struct {
@@ -148,6 +159,14 @@ int rhd_set_state_device(rhd_t* h, const double* rho, const double* mom, const d
    dE_r/dt, so that div F = j in a steady state (Sec. 4.3.6, Eq. radshell:sourceprofile).
    Synchronises. */
 int rhd_set_emission(rhd_t* h, const double* j);
+
+/* Radiation state U = (E_r, F_x, F_y, F_z) that the RHD_BC_FIXED face `face` (0..5 =
+   x-, x+, y-, y+, z-, z+) holds from the next rhd_step on; it stays until set again
+   (zero until the first call). A driven boundary sets it before each step, e.g. from
+   Eq. marshak:suolson and the Marshak condition c E_r + 2 F = 4 F_inc of Sec. 4.2.3.
+   RHD_EINVAL if the face is not a fixed face of an active dimension, or E_r <= 0, or a
+   value is not finite. Host-side only. */
+int rhd_set_boundary(rhd_t* h, int face, const double U[4]);
 
 /* Advance one gas step of dt_gas with nsub radiation subcycles of dt_gas/nsub each
    (Sec. 3.1 steps 2-6, Eq. algorithm:radtimestep). chat is the reduced speed of light
@@ -308,7 +327,8 @@ int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int 
    rhd_set_emission (j may be NULL), then `steps` gas steps, each with the CFL step and
    subcycle count rhd_suggest_dt gives at the reduced speed of light chat. The host arrays
    are copied before the call returns. *id receives the request's id (ids count up from
-   1). RHD_EINVAL for invalid parameters, a grid that is not 3D, steps < 1 or chat <= 0;
+   1). RHD_EINVAL for invalid parameters, a grid that is not 3D, a fixed face, steps < 1
+   or chat <= 0;
    RHD_ENOMEM when the request's footprint alone exceeds the budget, so that it could
    never be admitted (nothing is queued then). */
 int rhd_server_submit(rhd_server_t* s, const rhd_params* p, const double* rho,

@@ -23,12 +23,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rhd_oracle.c")
 LIB = os.path.join(HERE, "librhd_oracle.so")
 
-BC = {"periodic": 0, "outflow": 1, "reflect": 2}
+BC = {"periodic": 0, "outflow": 1, "reflect": 2, "fixed": 3}
 ISOTHERMAL = 1 << 0
 EXCH = {"full": 0 << 1, "absorb_only": 1 << 1, "none": 2 << 1}
 BETA_TAU = 1 << 3
 RAD_ONLY = 1 << 4
 PRECISION_MIXED = 1 << 5
+GAS_CV_T3 = 1 << 6
 
 STATE_FIELDS = ("rho", "mx", "my", "mz", "E", "Er", "Fx", "Fy", "Fz")
 
@@ -59,6 +60,8 @@ class Params(ctypes.Structure):
         ("er_floor", ctypes.c_double),
         ("bc", ctypes.c_int * 6),
         ("flags", ctypes.c_uint),
+        ("cv_alpha", ctypes.c_double),
+        ("bval", (ctypes.c_double * 4) * 6),
     ]
 
 
@@ -131,7 +134,13 @@ def make_params(spec):
         flags |= RAD_ONLY
     if spec["precision"] == "mixed":
         flags |= PRECISION_MIXED
+    if spec["cv_t3"]:
+        flags |= GAS_CV_T3
     p.flags = flags
+    p.cv_alpha = float(spec["cv_alpha"])
+    for f in range(6):
+        for q in range(4):
+            p.bval[f][q] = float(spec["bvals"][f][q])
     return p
 
 

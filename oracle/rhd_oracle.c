@@ -40,7 +40,14 @@
  *    raised to their floors;
  *  - emission j adds (chat/c) j to dE_r/dt, so that div F = j in a steady state;
  *  - in ABSORB_ONLY mode E_r is damped with kappa_P by the same theta-form as F,
- *    with theta_F, on each radiation stage.
+ *    with theta_F, on each radiation stage;
+ *  - a fixed (Dirichlet) radiation face, as the Marshak problem of Sec. 4.2.3 needs,
+ *    holds its state in every ghost cell beyond it, for U^m and for the predicted
+ *    U^{m+1/2} (the predictor does not evolve those ghosts), while the gas fields
+ *    continue zero-gradient there;
+ *  - with c_v = alpha T^3 (Sec. 4.2.3) the exchange keeps the theta-scheme form of
+ *    Eq. source:energyupdate with a_R T^4 = (4 a_R/alpha) e, which makes the update
+ *    linear in e; with chat = c it is the update printed with that problem.
  */
 #include "rhd_oracle.h"
 
@@ -139,7 +146,7 @@ static void fill_ghosts(const orc_params *p, const pgrid *G, double **f, const i
           double flip = 1.0;
           if (kind == ORC_BC_PERIODIC) {
             src = ((q % n) + n) % n;
-          } else if (kind == ORC_BC_OUTFLOW) {
+          } else if (kind == ORC_BC_OUTFLOW || kind == ORC_BC_FIXED) {
             src = q < 0 ? 0 : n - 1;
           } else { /* reflect */
             src = q < 0 ? -1 - q : 2 * n - 1 - q;
@@ -153,6 +160,37 @@ static void fill_ghosts(const orc_params *p, const pgrid *G, double **f, const i
             f[m][dst_at] = (comp[m] == d ? flip : 1.0) * f[m][src_at];
         }
   }
+}
+
+/*
+ * The fixed face whose radiation state the padded cell (i, j, k) holds, or -1: of the
+ * dimensions in which the cell lies beyond a fixed face, the last in the order x, y, z
+ * (the order fill_ghosts fills them in).
+ */
+static int fixed_face(const orc_params *p, const pgrid *G, int i, int j, int k) {
+  const int c[3] = {i, j, k};
+  int face = -1;
+  for (int d = 0; d < 3; ++d) {
+    if (G->g[d] == 0) continue;
+    if (c[d] < 0 && p->bc[2 * d] == ORC_BC_FIXED) face = 2 * d;
+    if (c[d] >= G->n[d] && p->bc[2 * d + 1] == ORC_BC_FIXED) face = 2 * d + 1;
+  }
+  return face;
+}
+
+/* Put the fixed faces' radiation states into the ghost cells of (E_r, F_x, F_y, F_z). */
+static void apply_fixed(const orc_params *p, const pgrid *G, double *const U[4]) {
+  int any = 0;
+  for (int f = 0; f < 6; ++f) any |= p->bc[f] == ORC_BC_FIXED;
+  if (!any) return;
+  for (int k = -G->g[2]; k < G->n[2] + G->g[2]; ++k)
+    for (int j = -G->g[1]; j < G->n[1] + G->g[1]; ++j)
+      for (int i = -G->g[0]; i < G->n[0] + G->g[0]; ++i) {
+        const int f = fixed_face(p, G, i, j, k);
+        if (f < 0) continue;
+        const long a = at(G, i, j, k);
+        for (int q = 0; q < 4; ++q) U[q][a] = p->bval[f][q];
+      }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -644,8 +682,12 @@ double orc_exchange_cell(double rho, double e, double Er, double kP, double dt,
                          double chat, const orc_params *p, double *Er_new, int *iters,
                          int *used_theta1, int *used_bisect) {
   const double c = p->c_light;
+  const int cv_t3 = (p->flags & ORC_GAS_CV_T3) != 0;
   double gm1_over = (p->gamma - 1.0) / (rho * p->r_gas);
-  double alpha = p->a_rad * gm1_over * gm1_over * gm1_over * gm1_over;
+  /* emission a_R T^4 as a function of e: alpha e^4 for the ideal gas, eps e when
+     c_v = cv_alpha T^3 (e = cv_alpha T^4 / 4, eps = 4 a_R / cv_alpha) */
+  double alpha = cv_t3 ? 0.0 : p->a_rad * gm1_over * gm1_over * gm1_over * gm1_over;
+  double eps = cv_t3 ? 4.0 * p->a_rad / p->cv_alpha : 0.0;
   double eta = c * rho * kP * dt;
   double Ebar = e + (c / chat) * Er;
   double theta = p->theta_E;
@@ -655,8 +697,9 @@ double orc_exchange_cell(double rho, double e, double Er, double kP, double dt,
   *used_bisect = 0;
   for (;;) {
     c4 = alpha * eta * theta;
-    c1 = 1.0 + (chat / c) * eta * theta;
-    c0 = (1.0 - theta) * eta * (alpha * e * e * e * e - Er) - (e + (chat / c) * eta * theta * Ebar);
+    c1 = 1.0 + (chat / c) * eta * theta + eps * eta * theta;
+    c0 = (1.0 - theta) * eta * (alpha * e * e * e * e + eps * e - Er) -
+         (e + (chat / c) * eta * theta * Ebar);
     if (c0 > 0.0 && theta < 1.0) {
       theta = 1.0;
       *used_theta1 = 1;
@@ -822,6 +865,7 @@ int orc_step(const orc_params *p, orc_fields *s, double dt_gas, double chat, int
     load_padded(p, &G, s->kF, kFp);
     fill_ghosts(p, &G, Ug, comp_gas, 5);
     fill_ghosts(p, &G, Ur, comp_rad, 4);
+    apply_fixed(p, &G, Ur);
     fill_ghosts(p, &G, &kFp, comp_scalar, 1);
     for (int q = 0; q < 4; ++q) {
       s_n[q] = (double *)calloc((size_t)N, sizeof(double));
@@ -871,7 +915,9 @@ int orc_step(const orc_params *p, orc_fields *s, double dt_gas, double chat, int
     for (int m = 0; m < nsub; ++m) {
       for (int q = 0; q < 4; ++q) load_padded(p, &G, rsrc[q], Um[q]);
       fill_ghosts(p, &G, Um, comp_rad, 4);
+      apply_fixed(p, &G, Um);
       rad_stage(p, &G, chat, 0.5 * hr, 0, 2, Um, Um, Um, &fg, Uh, NULL);
+      apply_fixed(p, &G, Uh);
       rad_stage(p, &G, chat, hr, 1, 0, Uh, Um, Uh, &fg, Un, cnt);
       for (int q = 0; q < 4; ++q) store_interior(p, &G, Un[q], rsrc[q]);
     }

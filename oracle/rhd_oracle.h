@@ -20,7 +20,11 @@ extern "C" {
 #endif
 
 /* boundary kinds, per face x-, x+, y-, y+, z-, z+ */
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2, ORC_BC_FIXED = 3 };
+/* ORC_BC_FIXED: every ghost cell beyond the face holds the radiation state
+   bval[face] = (E_r, F_x, F_y, F_z), in U^m and in the predicted U^{m+1/2} alike (a
+   cell beyond several fixed faces takes the last of them in the order x, y, z); gas
+   and frozen-gas fields continue zero-gradient there. */
 
 /* flag bits */
 #define ORC_ISOTHERMAL        (1u << 0)
@@ -31,6 +35,8 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2 };
 #define ORC_BETA_TAU          (1u << 3)   /* keep the O(beta tau) velocity terms      */
 #define ORC_RAD_ONLY          (1u << 4)   /* gas frozen: no gas transport             */
 #define ORC_PRECISION_MIXED   (1u << 5)   /* ignored by the oracle (always FP64)      */
+#define ORC_GAS_CV_T3         (1u << 6)   /* heat capacity c_v = cv_alpha T^3, so that
+                                             a_R T^4 = (4 a_R / cv_alpha) e            */
 
 typedef struct {
   int nx, ny, nz;                 /* interior cells; ny = nz = 1 for 1D           */
@@ -45,6 +51,8 @@ typedef struct {
   double rho_floor, p_floor, er_floor;
   int bc[6];
   unsigned flags;
+  double cv_alpha;                /* alpha of c_v = alpha T^3 (ORC_GAS_CV_T3)     */
+  double bval[6][4];              /* radiation state of each ORC_BC_FIXED face    */
 } orc_params;
 
 typedef struct {

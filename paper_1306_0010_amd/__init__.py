@@ -30,7 +30,7 @@ ERROR_NAMES = {RHD_EINVAL: "RHD_EINVAL", RHD_ECFL: "RHD_ECFL", RHD_ENONFINITE: "
 RHD_REQ_QUEUED, RHD_REQ_RUNNING, RHD_REQ_DONE, RHD_REQ_FAILED, RHD_REQ_CANCELLED = range(5)
 REQ_STATUS_NAMES = ("queued", "running", "done", "failed", "cancelled")
 
-RHD_BC_PERIODIC, RHD_BC_OUTFLOW, RHD_BC_REFLECT = 0, 1, 2
+RHD_BC_PERIODIC, RHD_BC_OUTFLOW, RHD_BC_REFLECT, RHD_BC_FIXED = 0, 1, 2, 3
 RHD_ISOTHERMAL = 1 << 0
 RHD_EXCHANGE_MASK = 3 << 1
 RHD_EXCHANGE_FULL = 0 << 1
@@ -39,11 +39,12 @@ RHD_EXCHANGE_NONE = 2 << 1
 RHD_BETA_TAU = 1 << 3
 RHD_RAD_ONLY = 1 << 4
 RHD_PRECISION_MIXED = 1 << 5
+RHD_GAS_CV_T3 = 1 << 6
 RHD_KERNELS_PER_CELL = 0
 RHD_KERNELS_TILED = 1
 
 EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_device",
-            "rhd_set_emission", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
+            "rhd_set_emission", "rhd_set_boundary", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
             "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics", "rhd_sync",
             "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
             "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant", "rhd_autotune",
@@ -75,6 +76,7 @@ class rhd_params(ctypes.Structure):
         ("er_floor", ctypes.c_double),
         ("bc", ctypes.c_int * 6),
         ("flags", ctypes.c_uint),
+        ("cv_alpha", ctypes.c_double),
     ]
 
 
@@ -158,6 +160,7 @@ def lib():
     L.rhd_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
     L.rhd_set_state_device.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
     L.rhd_set_emission.argtypes = [vp, dp]
+    L.rhd_set_boundary.argtypes = [vp, ctypes.c_int, dp]
     L.rhd_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     L.rhd_suggest_dt.argtypes = [vp, ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int)]
     L.rhd_ledger.argtypes = [vp, ctypes.c_double]
@@ -208,6 +211,7 @@ def lib():
                  "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
+                 "rhd_set_boundary",
                  "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
                  "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
                  "rhd_sync", "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant",
@@ -265,6 +269,13 @@ def rhd_set_emission(h, j):
         return
     a = np.ascontiguousarray(j, dtype=np.float64)
     _check(lib().rhd_set_emission(h, _dptr(a)), h)
+
+
+def rhd_set_boundary(h, face, U):
+    a = np.ascontiguousarray(U, dtype=np.float64)
+    if a.shape != (4,):
+        raise ValueError("U must hold (E_r, F_x, F_y, F_z)")
+    _check(lib().rhd_set_boundary(h, int(face), _dptr(a)), h)
 
 
 def rhd_step(h, dt_gas, chat, nsub):
@@ -467,7 +478,8 @@ def rhd_last_error(h=None):
 # problem description -> parameters, and a handle wrapper
 # ---------------------------------------------------------------------------
 
-_BC = {"periodic": RHD_BC_PERIODIC, "outflow": RHD_BC_OUTFLOW, "reflect": RHD_BC_REFLECT}
+_BC = {"periodic": RHD_BC_PERIODIC, "outflow": RHD_BC_OUTFLOW, "reflect": RHD_BC_REFLECT,
+       "fixed": RHD_BC_FIXED}
 _EXCH = {"full": RHD_EXCHANGE_FULL, "absorb_only": RHD_EXCHANGE_ABSORB_ONLY,
          "none": RHD_EXCHANGE_NONE}
 
@@ -490,7 +502,10 @@ def params_from_spec(spec):
         flags |= RHD_RAD_ONLY
     if spec["precision"] == "mixed":
         flags |= RHD_PRECISION_MIXED
+    if spec.get("cv_t3"):
+        flags |= RHD_GAS_CV_T3
     p.flags = flags
+    p.cv_alpha = float(spec.get("cv_alpha", 0.0))
     return p
 
 
@@ -557,6 +572,13 @@ class Solver:
 
     def step(self, dt_gas, chat, nsub):
         rhd_step(self.h, dt_gas, chat, nsub)
+
+    def set_boundary(self, bvals):
+        """Set every fixed face's radiation state from a 6 x 4 table (x-, x+, y-, y+, z-,
+        z+ by (E_r, F_x, F_y, F_z)); rows of other faces are ignored."""
+        for f in range(6):
+            if self.spec["bc"][f] == "fixed" and self.shape[2 - f // 2] > 1:
+                rhd_set_boundary(self.h, f, bvals[f])
 
     def set_kernel_variant(self, variant, tile_rows=8, zchunk=8):
         rhd_set_kernel_variant(self.h, variant, tile_rows, zchunk)

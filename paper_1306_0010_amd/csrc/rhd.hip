@@ -102,6 +102,8 @@ struct rhd {
   int variant = RHD_KERNELS_TILED;
   int tile_rows = 8;
   int zchunk = 8;
+  int fixed_mask = 0;          // bit f: face f is RHD_BC_FIXED (of an active dimension)
+  double bval[6][4] = {};      // radiation state of each fixed face (rhd_set_boundary)
   Timer timer;
   char err[512] = "no error";
 };
@@ -179,8 +181,10 @@ int validate(const rhd_params* p) {
     if (ns[d] > 1) {
       for (int s = 0; s < 2; ++s) {
         const int kind = p->bc[2 * d + s];
-        if (kind < RHD_BC_PERIODIC || kind > RHD_BC_REFLECT)
+        if (kind < RHD_BC_PERIODIC || kind > RHD_BC_FIXED)
           return fail(nullptr, RHD_EINVAL, "unknown boundary kind %d on face %d", kind, 2 * d + s);
+        if (kind == RHD_BC_FIXED && !(p->flags & RHD_RAD_ONLY))
+          return fail(nullptr, RHD_EINVAL, "fixed faces need RHD_RAD_ONLY (face %d)", 2 * d + s);
         if (kind == RHD_BC_REFLECT && ns[d] < 3)
           return fail(nullptr, RHD_EINVAL, "reflecting faces need at least 3 cells");
       }
@@ -203,7 +207,12 @@ int validate(const rhd_params* p) {
     return fail(nullptr, RHD_EINVAL, "floors must be >= 0");
   if ((p->flags & RHD_EXCHANGE_MASK) == (3u << 1))
     return fail(nullptr, RHD_EINVAL, "unknown exchange mode");
-  if (p->flags & ~((1u << 6) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  if (p->flags & ~((1u << 7) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  if (p->flags & RHD_GAS_CV_T3) {
+    if (!(p->flags & RHD_RAD_ONLY) || (p->flags & RHD_ISOTHERMAL))
+      return fail(nullptr, RHD_EINVAL, "RHD_GAS_CV_T3 needs RHD_RAD_ONLY and an ideal gas");
+    if (!(p->cv_alpha > 0.0)) return fail(nullptr, RHD_EINVAL, "cv_alpha must be > 0");
+  }
   (void)cells;
   return RHD_OK;
 }
@@ -410,7 +419,8 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
   auto view = gas_view<T>(h);
   const double hr = dt / nsub;
   const bool three_d = G.act[0] && G.act[1] && G.act[2];
-  if (three_d && h->variant == RHD_KERNELS_TILED) {
+  // fixed faces run the per-cell kernels, which read their states
+  if (three_d && h->variant == RHD_KERNELS_TILED && !h->fixed_mask) {
     for (int m = 0; m < nsub; ++m) {
       int rc = launch_tiled<T>(h, rad, rh, view, RK, T(0.5 * hr), T(hr));
       if (rc) return rc;
@@ -420,9 +430,13 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
   dim3 gp, bp, gc, bc;
   region_launch(G.ps, gp, bp);
   region_launch(G.n, gc, bc);
+  rhdk::FixedFaces<T> B{};
+  B.mask = h->fixed_mask;
+  for (int f = 0; f < 6; ++f)
+    for (int q = 0; q < 4; ++q) B.v[f][q] = T(h->bval[f][q]);
   for (int m = 0; m < nsub; ++m) {
     int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
-    hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK,
+    hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK, B,
                        T(0.5 * hr));
     tend(h, ti);
     ti = tbegin(h, KC_RAD_CORRECT, h->N);
@@ -506,6 +520,7 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
     X.r_gas = p.r_gas;
     X.theta = p.theta_E;
     X.rtol = p.newton_rtol;
+    X.eps_cv = (p.flags & RHD_GAS_CV_T3) ? 4.0 * p.a_rad / p.cv_alpha : 0.0;
     X.maxit = p.newton_maxit;
     const int ti = tbegin(h, KC_EXCHANGE, h->N);
     const int eb = std::min(EXCH_BLOCKS, blocks_for(h->N, rhdk::EXCH_THREADS));
@@ -851,6 +866,7 @@ void rhd_default_params(rhd_params* p, int nx, int ny, int nz) {
   p->er_floor = 1e-30;
   for (int f = 0; f < 6; ++f) p->bc[f] = RHD_BC_PERIODIC;
   p->flags = RHD_EXCHANGE_FULL;
+  p->cv_alpha = 0.0;
 }
 
 long long rhd_footprint_bytes(const rhd_params* p) {
@@ -869,6 +885,8 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
   h->mixed = (p->flags & RHD_PRECISION_MIXED) != 0;
   h->esize = h->mixed ? 4 : 8;
   h->G = make_geom(p);
+  for (int f = 0; f < 6; ++f)
+    if (h->G.act[f / 2] && p->bc[f] == RHD_BC_FIXED) h->fixed_mask |= 1 << f;
   long long N, NP;
   footprint(p, &N, &NP);
   h->N = int(N);
@@ -974,6 +992,18 @@ int rhd_set_emission(rhd_t* h, const double* j) {
   }
   return h->mixed ? upload_field<float>(h, j, h->b.j, h->N, true)
                   : upload_field<double>(h, j, h->b.j, h->N, true);
+}
+
+int rhd_set_boundary(rhd_t* h, int face, const double U[4]) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (face < 0 || face > 5 || !U) return fail(h, RHD_EINVAL, "face must be 0..5 and U non-NULL");
+  if (!(h->fixed_mask & (1 << face)))
+    return fail(h, RHD_EINVAL, "face %d is not a fixed face of an active dimension", face);
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(U[q])) return fail(h, RHD_EINVAL, "boundary state must be finite");
+  if (!(U[0] > 0.0)) return fail(h, RHD_EINVAL, "boundary E_r must be > 0");
+  for (int q = 0; q < 4; ++q) h->bval[face][q] = U[q];
+  return RHD_OK;
 }
 
 int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub) {
@@ -1136,8 +1166,13 @@ int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, i
     return fail(h, RHD_EINVAL, "chat and dt_rad must be > 0 and reps >= 1");
   if (chat * dt_rad > h->p.cfl * h->dxmin * (1.0 + 1e-12))
     return fail(h, RHD_ECFL, "chat dt_rad exceeds K0 dx");
-  int rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
-                    : autotune_impl<double>(h, chat, dt_rad, reps);
+  // fixed faces always run the per-cell kernels: nothing to choose
+  int rc = RHD_OK;
+  if (h->fixed_mask)
+    h->variant = RHD_KERNELS_PER_CELL;
+  else
+    rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
+                  : autotune_impl<double>(h, chat, dt_rad, reps);
   if (variant) *variant = h->variant;
   if (tile_rows) *tile_rows = h->tile_rows;
   if (zchunk) *zchunk = h->zchunk;
@@ -1407,6 +1442,7 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   if (int(b->members.size()) >= b->max_solves) return bfail(b, RHD_EINVAL, "batch is full");
   if (!h->have_state) return bfail(b, RHD_ESTATE, "member has no state");
   if (!(h->G.act[0] && h->G.act[1] && h->G.act[2])) return bfail(b, RHD_EINVAL, "members must be 3D");
+  if (h->fixed_mask) return bfail(b, RHD_EINVAL, "members cannot have fixed faces");
   if (!(chat > 0.0)) return bfail(b, RHD_EINVAL, "chat must be > 0");
   for (rhd_t* m : b->members)
     if (m == h) return bfail(b, RHD_EINVAL, "handle is already a member");

@@ -23,7 +23,7 @@
 
 namespace rhdk {
 
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_FIXED = 3 };
 
 enum {
   CTR_EXCH_THETA1 = 0,
@@ -81,6 +81,14 @@ struct RadConst {
   int absorb;  // absorption-only mode: E_r damped with kappa_P on each stage
 };
 
+// Radiation state (E_r, F_x, F_y, F_z) of each fixed (Dirichlet) face; bit f of mask
+// marks face f = x-, x+, y-, y+, z-, z+ as fixed.
+template <typename T>
+struct FixedFaces {
+  T v[6][4];
+  int mask;
+};
+
 template <typename T>
 struct GasConst {
   T c, inv_c;
@@ -110,7 +118,11 @@ __device__ __forceinline__ int map_index(int q, int n, int lo, int hi, int& sign
   per -= per >= n ? n : 0;
   const int clamp = low ? 0 : n - 1;
   const int mirror = low ? -1 - q : 2 * n - 1 - q;
-  const int r = kind == BC_PERIODIC ? per : (kind == BC_OUTFLOW ? clamp : (kind == BC_REFLECT ? mirror : q));
+  // a fixed face maps like an outflow face; its radiation state replaces the radiation
+  // fields where the radiation stages read them (fixed_face below)
+  const int r = kind == BC_PERIODIC
+                    ? per
+                    : ((kind == BC_OUTFLOW || kind == BC_FIXED) ? clamp : (kind == BC_REFLECT ? mirror : q));
   sign = kind == BC_REFLECT ? -sign : sign;
   return r;
 }
@@ -467,14 +479,61 @@ __device__ __forceinline__ void load_rad_mapped(const RadPtrs<T>& R, const Geom&
   unflip_rad(U, neg);
 }
 
+// The fixed face whose radiation state the cell (i, j, k) holds, or -1: of the
+// dimensions in which the cell lies beyond a fixed face, the last in the order x, y, z.
+__device__ __forceinline__ int fixed_face(const Geom& G, int mask, int i, int j, int k) {
+  int f = -1;
+  if ((mask & 1) && i < 0) f = 0;
+  if ((mask & 2) && i >= G.n[0]) f = 1;
+  if ((mask & 4) && j < 0) f = 2;
+  if ((mask & 8) && j >= G.n[1]) f = 3;
+  if ((mask & 16) && k < 0) f = 4;
+  if ((mask & 32) && k >= G.n[2]) f = 5;
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ void fixed_state(const FixedFaces<T>& B, int f, T U[4]) {
+#pragma unroll
+  for (int g = 0; g < 6; ++g)
+    if (g == f) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) U[q] = B.v[g][q];
+    }
+}
+
+// U^m of cell (i, j, k): the fixed state beyond a fixed face, else the mapped cell.
+template <typename T>
+__device__ __forceinline__ void load_rad_bc(const RadPtrs<T>& R, const Geom& G,
+                                            const FixedFaces<T>& B, int i, int j, int k, T U[4]) {
+  const int f = B.mask ? fixed_face(G, B.mask, i, j, k) : -1;
+  if (f >= 0)
+    fixed_state(B, f, U);
+  else
+    load_rad_mapped(R, G, i, j, k, U);
+}
+
 // Radiation predictor at one cell (i, j, k) of the padded region: first-order HLL fluxes
 // of U^m, half step, result written to the padded half-step arrays.
+// A ghost cell beyond a fixed face keeps the face's state in U^{m+1/2} too.
 template <typename T>
 __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
                                                  const GasView<T>& gas, const Geom& G,
-                                                 const RadConst<T>& K, T h, int i, int j, int k) {
+                                                 const RadConst<T>& K, const FixedFaces<T>& B,
+                                                 T h, int i, int j, int k) {
+  const int p = padded_cell(G, i, j, k);
+  const int fb = B.mask ? fixed_face(G, B.mask, i, j, k) : -1;
+  if (fb >= 0) {
+    T Ub[4];
+    fixed_state(B, fb, Ub);
+    Uh.E[p] = Ub[0];
+    Uh.F[0][p] = Ub[1];
+    Uh.F[1][p] = Ub[2];
+    Uh.F[2][p] = Ub[3];
+    return;
+  }
   T U0[4];
-  load_rad_mapped(Um, G, i, j, k, U0);
+  load_rad_bc(Um, G, B, i, j, k, U0);
   const M1State<T> m0 = m1_state(U0, K.inv_c, K.chat);
   T div[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -486,8 +545,8 @@ __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const Rad
     for (int q = 0; q < 4; ++q) own.U[q] = U0[q];
     m1_dir(m0, d, K.c, K.inv_c, K.chat, own.Phi, own.lmin, own.lmax);
     T Ul[4], Ur[4], fl[4], fr[4];
-    load_rad_mapped(Um, G, i - di, j - dj, k - dk, Ul);
-    load_rad_mapped(Um, G, i + di, j + dj, k + dk, Ur);
+    load_rad_bc(Um, G, B, i - di, j - dj, k - dk, Ul);
+    load_rad_bc(Um, G, B, i + di, j + dj, k + dk, Ur);
     hll(face_side(Ul, d, K.c, K.inv_c, K.chat), own, fl);
     hll(own, face_side(Ur, d, K.c, K.inv_c, K.chat), fr);
 #pragma unroll
@@ -499,7 +558,6 @@ __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const Rad
   T out[4];
   bool ef, fc;
   rad_update(K, h, U0, U0, div, fz, out, ef, fc);
-  const int p = padded_cell(G, i, j, k);
   Uh.E[p] = out[0];
   Uh.F[0][p] = out[1];
   Uh.F[1][p] = out[2];
@@ -510,12 +568,12 @@ __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const Rad
 // two ghost layers, written to the padded half-step arrays.
 template <typename T>
 __global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
-                                                     Geom G, RadConst<T> K, T h) {
+                                                     Geom G, RadConst<T> K, FixedFaces<T> B, T h) {
   const int i = int(blockIdx.x * blockDim.x + threadIdx.x) - G.g[0];
   const int j = int(blockIdx.y * blockDim.y + threadIdx.y) - G.g[1];
   const int k = int(blockIdx.z) - G.g[2];
   if (i >= G.n[0] + G.g[0] || j >= G.n[1] + G.g[1]) return;
-  rad_predict_cell(Um, Uh, gas, G, K, h, i, j, k);
+  rad_predict_cell(Um, Uh, gas, G, K, B, h, i, j, k);
 }
 
 template <typename T>
@@ -900,6 +958,7 @@ struct ExchConst {
   double c, chat, dt;
   double gm1, a_rad, r_gas;
   double theta, rtol;
+  double eps_cv;  // 4 a_R / alpha when c_v = alpha T^3 (a_R T^4 = eps_cv e), else 0
   int maxit;
 };
 
@@ -923,9 +982,12 @@ __device__ __forceinline__ double newton(double c4, double c1, double c0, double
 __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, double e,
                                                 double Er, double kP, double& Er_new, int& iters,
                                                 bool& th1, bool& bis) {
+  // emission a_R T^4 as a function of e: alpha e^4 (ideal gas), or eps_cv e when
+  // c_v = alpha T^3 (Sec. 4.2.3), which leaves a linear equation (c4 = 0)
   const double g = X.gm1 / (rho * X.r_gas);
   const double g2 = g * g;
-  const double alpha = X.a_rad * g2 * g2;
+  const double lin = X.eps_cv;
+  const double alpha = lin > 0.0 ? 0.0 : X.a_rad * g2 * g2;
   const double eta = X.c * rho * kP * X.dt;
   const double rc = X.chat / X.c;
   const double Ebar = e + Er / rc;
@@ -935,13 +997,13 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
   iters = 0;
   const double e2 = e * e;
   double c4 = alpha * eta * theta;
-  double c1 = 1.0 + rc * eta * theta;
-  double c0 = (1.0 - theta) * eta * (alpha * e2 * e2 - Er) - (e + rc * eta * theta * Ebar);
+  double c1 = 1.0 + (rc + lin) * eta * theta;
+  double c0 = (1.0 - theta) * eta * (alpha * e2 * e2 + lin * e - Er) - (e + rc * eta * theta * Ebar);
   if (c0 > 0.0 && theta < 1.0) {
     theta = 1.0;
     th1 = true;
     c4 = alpha * eta;
-    c1 = 1.0 + rc * eta;
+    c1 = 1.0 + (rc + lin) * eta;
     c0 = -(e + rc * eta * Ebar);
   }
   double x;

@@ -393,6 +393,8 @@ int rhd_server_submit(rhd_server_t* s, const rhd_params* p, const double* rho,
   const long long fp = rhd_footprint_bytes(p);
   if (fp < 0) return sfail(s, RHD_EINVAL, "invalid parameters");
   if (!(p->nx > 1 && p->ny > 1 && p->nz > 1)) return sfail(s, RHD_EINVAL, "the grid must be 3D");
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] == RHD_BC_FIXED) return sfail(s, RHD_EINVAL, "fixed faces cannot be served");
   if (steps < 1) return sfail(s, RHD_EINVAL, "steps must be >= 1");
   if (!(chat > 0.0)) return sfail(s, RHD_EINVAL, "chat must be > 0");
   if (!rho || !mom || !Er || !Fr || !kappaP || !kappaF)

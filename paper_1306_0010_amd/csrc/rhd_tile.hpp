@@ -210,7 +210,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       const int r = (e >> 2) % BY;
       const int p = (e >> 2) / BY;
       const int x = g < 2 ? g - 2 : n0 + g - 2;
-      if (y0 + r < ylim) rad_predict_cell(Um, Uh, gas, G, K, h, x, y0 + r, z0 + p);
+      if (y0 + r < ylim) rad_predict_cell(Um, Uh, gas, G, K, FixedFaces<T>{}, h, x, y0 + r, z0 + p);
     }
     return;
   }

@@ -43,6 +43,9 @@ def default_spec(**over):
         beta_tau=False,
         rad_only=False,
         precision="fp64",         # "fp64" | "mixed"
+        cv_t3=False,              # gas heat capacity c_v = cv_alpha T^3 (Marshak problem)
+        cv_alpha=0.0,
+        bvals=((0.0,) * 4,) * 6,  # (E_r, F_x, F_y, F_z) of each "fixed" face
     )
     for k, v in over.items():
         if k not in spec:
@@ -328,3 +331,81 @@ def sod_tube(N=200, gamma=1.4):
     P = np.where(left, 1.0, 0.1)
     st["E"] = P / (gamma - 1.0)
     return dict(name=f"sod_{N}", spec=spec, state=st, chat=1.0, t_end=0.2)
+
+
+# --------------------------------------------------------------------------
+# non-equilibrium Marshak wave (Sec. 4.2.3): the paper's own timing problem
+# --------------------------------------------------------------------------
+
+def _su_olson_integrands(chi, tau, eps):
+    """The two integrands of the semi-analytic Su & Olson solution quoted in
+    Sec. 4.2.3 (Eq. marshak:suolson), as functions of eta in (0, 1)."""
+    def gam_theta(g):
+        return g, np.arccos(np.sqrt(3.0 / (3.0 + 4.0 * g * g)))
+
+    def first(eta):
+        g, th = gam_theta(eta * np.sqrt(eps + 1.0 / (1.0 - eta * eta)))
+        return np.exp(-tau * eta * eta) * np.sin(chi * g + th) / (eta * np.sqrt(3.0 + 4.0 * g * g))
+
+    def second(eta):
+        g, th = gam_theta(np.sqrt((1.0 - eta) * (eps + 1.0 / eta)))
+        return (np.exp(-tau / (eps * eta)) * np.sin(chi * g + th)
+                / (eta * (1.0 + eps * eta) * np.sqrt(3.0 + 4.0 * g * g)))
+
+    return first, second
+
+
+def su_olson_u(chi, tau, eps=1.0, nq=None):
+    """u = c E_r / (4 F_inc) of the diffusion-approximation Marshak wave at optical
+    depth chi = sqrt(3) rho kappa x and time tau = eps c rho kappa t (Eq.
+    marshak:suolson). nq points of midpoint quadrature, as the paper evaluates it for
+    the boundary value; nq = None integrates adaptively (scipy.integrate.quad)."""
+    first, second = _su_olson_integrands(float(chi), float(tau), float(eps))
+    if nq is None:
+        import warnings
+        from scipy.integrate import IntegrationWarning, quad
+        with warnings.catch_warnings():
+            # the integrands oscillate near the ends of (0, 1) at chi > 0
+            warnings.simplefilter("ignore", IntegrationWarning)
+            i1 = quad(first, 0.0, 1.0, limit=2000)[0]
+            i2 = quad(second, 0.0, 1.0, limit=2000)[0]
+    else:
+        eta = (np.arange(nq) + 0.5) / nq
+        i1 = float(np.sum(first(eta))) / nq
+        i2 = float(np.sum(second(eta))) / nq
+    return (1.0 - 2.0 * math.sqrt(3.0) / math.pi * i1
+            - math.sqrt(3.0) / math.pi * math.exp(-float(tau)) * i2)
+
+
+MARSHAK_EBG = 1e-10  # background E_r standing for the cold medium (the closure needs E_r > 0)
+
+
+def marshak_problem(n=128, chi_max=100.0, eps=1.0, precision="fp64"):
+    """The non-equilibrium Marshak wave of Sec. 4.2.3 in units a_R = c = 1, F_inc = 1/4,
+    rho = kappa_0 = 1, chat = c: a 1D slab chi in [0, chi_max] (x = chi / sqrt(3)),
+    static gas (radiation only) with c_v = alpha T^3, alpha = 4 a_R / eps, a fixed
+    radiation state on both faces (set each step by marshak_boundary) and a cold start.
+    Then u = E_r and v = a_R T^4 = eps e. The cold medium starts at E_r = 1e-10,
+    F = 0, e = 1e-10 / eps (in equilibrium), since the M1 closure needs E_r > 0."""
+    L = chi_max / math.sqrt(3.0)
+    spec = default_spec(nx=n, dx=L / n, c_light=1.0, a_rad=1.0, cfl=0.4,
+                        theta_E=1.0, theta_F=0.51, er_floor=1e-30, rad_only=True,
+                        exchange="full", cv_t3=True, cv_alpha=4.0 / eps,
+                        bc=("fixed", "fixed", "periodic", "periodic", "periodic", "periodic"),
+                        precision=precision)
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=MARSHAK_EBG, kP=1.0, kF=1.0)
+    st["E"] = np.full_like(st["rho"], MARSHAK_EBG / eps)
+    return dict(name=f"marshak_{n}", spec=spec, state=st, chat=1.0, eps=eps,
+                dt=spec["cfl"] * spec["dx"], nsub=1)
+
+
+def marshak_boundary(t, eps=1.0, nq=4000):
+    """Radiation states of the two faces at time t: on the left E_r = u(0, tau) from the
+    midpoint quadrature of Eq. marshak:suolson and F from the Marshak condition
+    c E_r + 2 F = 4 F_inc (Eq. marshak:bc_ix1); on the right the cold medium."""
+    u0 = su_olson_u(0.0, eps * t, eps, nq=nq) if t > 0.0 else 0.0
+    E0 = max(u0, MARSHAK_EBG)
+    left = (E0, 0.5 * (1.0 - E0), 0.0, 0.0)
+    right = (MARSHAK_EBG, 0.0, 0.0, 0.0)
+    zero = (0.0, 0.0, 0.0, 0.0)
+    return (left, right, zero, zero, zero, zero)

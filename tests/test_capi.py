@@ -79,3 +79,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     with pytest.raises(P.RhdError) as e:
         P.rhd_default_params(4, 4, 4)
     assert "missing" in str(e.value)
+
+
+def test_fixed_faces_and_cv_t3_need_radiation_only():
+    """A fixed radiation face and the c_v = alpha T^3 gas are defined for a frozen gas
+    only (the Marshak problem of Sec. 4.2.3); both are refused otherwise, before any
+    device work."""
+    import rhd_inputs as ri
+    pb = ri.marshak_problem(32)
+    p = P.params_from_spec(pb["spec"])
+    assert P.rhd_footprint_bytes(p) > 0
+    for change in ({"rad_only": False}, {"cv_alpha": 0.0}, {"isothermal": True}):
+        spec = dict(pb["spec"], **change)
+        with pytest.raises(P.RhdError) as e:
+            P.rhd_create(P.params_from_spec(spec))
+        assert e.value.code == P.RHD_EINVAL
+    spec = dict(pb["spec"], cv_t3=False, rad_only=False)
+    with pytest.raises(P.RhdError) as e:
+        P.rhd_create(P.params_from_spec(spec))
+    assert e.value.code == P.RHD_EINVAL and "fixed" in str(e.value)
