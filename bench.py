@@ -148,7 +148,78 @@ def roofline(kernels, spec, has_j, kappa_field, workload):
                                 "bytes_per_cell": bpc}}
 
 
-def cpu_baseline(pb, nz_slab=16):
+MARSHAK_N = (32, 128, 512, 2048)
+MARSHAK_TAU = (1.0, 10.0, 100.0)
+
+
+def marshak_schedule(ri, n, tau_end):
+    """Steps and face states of the Marshak problem (Sec. 4.2.3, eps = 1, chi in
+    [0, 100]) on n cells up to tau_end: the boundary states are inputs, computed before
+    any clock starts."""
+    pb = ri.marshak_problem(n)
+    dt = pb["dt"]
+    steps = int(math.ceil(tau_end / dt - 1e-9))
+    hs = [min(dt, tau_end - k * dt) for k in range(steps)]
+    bvals = [ri.marshak_boundary(k * dt + 0.5 * hs[k]) for k in range(steps)]
+    return pb, hs, bvals
+
+
+def marshak_timing(P, ri, stream):
+    """The paper's own timing benchmark (Sec. 4.3): wall time of the 1D Marshak wave to
+    tau = 1, 10 and 100 for n = 32 ... 2048 cells, FP64 (mixed precision at 2048 as
+    well), state resident on the device, one gas step of nsub = 1 per CFL step driven
+    from Python, boundary states precomputed; best of two runs."""
+    import torch
+    rows = []
+    for prec in ("fp64", "mixed"):
+        for n in (MARSHAK_N if prec == "fp64" else MARSHAK_N[-1:]):
+            pb0 = ri.marshak_problem(n, precision=prec)
+            sched = {tau: marshak_schedule(ri, n, tau) for tau in MARSHAK_TAU}
+            for tau in MARSHAK_TAU:
+                _, hs, bvals = sched[tau]
+                el = float("inf")
+                for _ in range(2):  # best of two: the first run pays one-time costs
+                    with P.Solver(pb0["spec"], stream=stream.cuda_stream) as s:
+                        s.set_state(pb0["state"])
+                        s.sync()
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        for h, bv in zip(hs, bvals):
+                            s.set_boundary(bv)
+                            s.step(h, 1.0, 1)
+                        s.sync()
+                        el = min(el, time.perf_counter() - t0)
+                        u0 = float(s.get_state()["Er"][0, 0, 0])
+                rows.append({"n": n, "tau": tau, "precision": prec, "steps": len(hs),
+                             "seconds": el, "us_per_step": 1e6 * el / len(hs),
+                             "zone_updates_per_s": n * len(hs) / el, "u_first_cell": u0})
+    return {"workload": "marshak_wave_1d", "tau": list(MARSHAK_TAU), "n": list(MARSHAK_N),
+            "rows": rows}
+
+
+def cpu_baseline_marshak(ri, max_zone_updates=5e6):
+    """The FP64 oracle (as it stands, one thread) on the same Marshak runs, except those
+    of more than max_zone_updates (2048 cells to tau = 100: ~13 s alone)."""
+    import oracle
+    rows = []
+    for n in MARSHAK_N:
+        for tau in MARSHAK_TAU:
+            pb, hs, bvals = marshak_schedule(ri, n, tau)
+            if n * len(hs) > max_zone_updates:
+                continue
+            spec, st = dict(pb["spec"]), pb["state"]
+            t0 = time.perf_counter()
+            for h, bv in zip(hs, bvals):
+                spec["bvals"] = bv
+                st, _ = oracle.step(spec, st, h, 1.0, 1)
+            el = time.perf_counter() - t0
+            rows.append({"n": n, "tau": tau, "steps": len(hs), "seconds": el,
+                         "zone_updates_per_s": n * len(hs) / el,
+                         "u_first_cell": float(st["Er"][0, 0, 0])})
+    return {"kind": "oracle", "cores": 1, "rows": rows}
+
+
+def cpu_baseline(pb, nz_slab=32):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the same
     input: the first nz_slab z-planes of the 128^3 box as a periodic slab, one full
     gas step with its CFL subcycles."""
@@ -314,6 +385,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=1.2,
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-marshak", action="store_true",
+                    help="skip the Marshak-wave timing (the paper's own 1D benchmark)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
@@ -453,9 +526,15 @@ def main():
         progress("256^3 dusty shell timed")
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_load)
+    if not args.no_marshak:
+        out["marshak"] = marshak_timing(P, ri, stream)
+        progress("Marshak wave timed")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
         progress("oracle timed on the host")
+        if not args.no_marshak:
+            out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
+            progress("oracle timed on the Marshak wave")
     print(json.dumps(out), flush=True)
 
 
