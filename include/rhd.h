@@ -177,6 +177,22 @@ int rhd_set_boundary(rhd_t* h, int face, const double U[4]);
    are reported by rhd_sync and rhd_get_diagnostics. */
 int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub);
 
+/* Advance nsteps gas steps in one call: step k takes dt_gas[k] with nsub[k] radiation
+   subcycles at the reduced speed of light chat, and, when bvals is not NULL, each
+   RHD_BC_FIXED face holds bvals[24 k + 4 f .. 24 k + 4 f + 3] = (E_r, F_x, F_y, F_z) of
+   face f during step k (entries of other faces are ignored; with bvals NULL the states
+   of rhd_set_boundary stay). The result equals nsteps calls of rhd_set_boundary and
+   rhd_step, bit for bit, with the ledger taken once at the end; afterwards the fixed
+   faces keep the last step's states. A 1D RHD_RAD_ONLY grid of at most 4096 cells runs
+   1024 steps per launch of one workgroup (at such sizes separate launches cost more than
+   the arithmetic); on its first such call the handle allocates its step tables (device
+   and pinned host memory, 2 x 1024 steps). Other grids enqueue the steps one by one.
+   Every step is checked before anything is enqueued: RHD_EINVAL for nsteps < 0, NULL
+   arrays, dt_gas <= 0, nsub < 0, chat <= 0 or a fixed-face state with E_r <= 0 or a
+   non-finite value; RHD_ECFL as rhd_step. Asynchronous like rhd_step. */
+int rhd_run(rhd_t* h, int nsteps, const double* dt_gas, const int* nsub, double chat,
+            const double* bvals);
+
 /* Radiation-modified CFL step of the current state (Eqs. algorithm:ceff and
    algorithm:gastimestep): v_max = max(|v| + c_eff), dt_gas = K0 min(dx) / v_max,
    nsub = ceil(chat / v_max) (at least 1). Synchronises. */

@@ -44,7 +44,7 @@ RHD_KERNELS_PER_CELL = 0
 RHD_KERNELS_TILED = 1
 
 EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_device",
-            "rhd_set_emission", "rhd_set_boundary", "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
+            "rhd_set_emission", "rhd_set_boundary", "rhd_step", "rhd_run", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
             "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics", "rhd_sync",
             "rhd_device_bytes", "rhd_footprint_bytes", "rhd_destroy", "rhd_last_error",
             "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant", "rhd_autotune",
@@ -161,6 +161,7 @@ def lib():
     L.rhd_set_state_device.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
     L.rhd_set_emission.argtypes = [vp, dp]
     L.rhd_set_boundary.argtypes = [vp, ctypes.c_int, dp]
+    L.rhd_run.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int), ctypes.c_double, dp]
     L.rhd_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     L.rhd_suggest_dt.argtypes = [vp, ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int)]
     L.rhd_ledger.argtypes = [vp, ctypes.c_double]
@@ -211,7 +212,7 @@ def lib():
                  "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("rhd_create", "rhd_set_state", "rhd_set_state_device", "rhd_set_emission",
-                 "rhd_set_boundary",
+                 "rhd_set_boundary", "rhd_run",
                  "rhd_step", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",
                  "rhd_get_state_device", "rhd_get_diagnostics", "rhd_reset_diagnostics",
                  "rhd_sync", "rhd_set_timing", "rhd_get_timing", "rhd_set_kernel_variant",
@@ -280,6 +281,23 @@ def rhd_set_boundary(h, face, U):
 
 def rhd_step(h, dt_gas, chat, nsub):
     _check(lib().rhd_step(h, float(dt_gas), float(chat), int(nsub)), h)
+
+
+def rhd_run(h, dt_gas, nsub, chat, bvals=None):
+    """Many gas steps in one call: dt_gas and nsub per step; bvals None or an array of
+    shape (steps, 6, 4) of fixed-face states per step."""
+    dts = np.ascontiguousarray(dt_gas, dtype=np.float64).reshape(-1)
+    ns = np.ascontiguousarray(nsub, dtype=np.int32).reshape(-1)
+    if ns.shape != dts.shape:
+        raise ValueError("dt_gas and nsub need one entry per step")
+    bv = None
+    if bvals is not None:
+        bv = np.ascontiguousarray(bvals, dtype=np.float64)
+        if bv.shape != (dts.size, 6, 4):
+            raise ValueError("bvals must have shape (steps, 6, 4)")
+    _check(lib().rhd_run(h, int(dts.size), _dptr(dts),
+                         ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(chat),
+                         _dptr(bv) if bv is not None else None), h)
 
 
 def rhd_suggest_dt(h, chat):
@@ -572,6 +590,9 @@ class Solver:
 
     def step(self, dt_gas, chat, nsub):
         rhd_step(self.h, dt_gas, chat, nsub)
+
+    def run(self, dt_gas, nsub, chat, bvals=None):
+        rhd_run(self.h, dt_gas, nsub, chat, bvals)
 
     def set_boundary(self, bvals):
         """Set every fixed face's radiation state from a 6 x 4 table (x-, x+, y-, y+, z-,

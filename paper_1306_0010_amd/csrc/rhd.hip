@@ -48,6 +48,11 @@ struct Buffers {
   double* vmax = nullptr;            // 1
   unsigned long long* exch_partials = nullptr;  // EXCH_STATS x EXCH_BLOCKS
   unsigned long long* ctr = nullptr; // rhdk::CTR_COUNT
+  // step tables of rhd_run (two chunks each), made on its first fused call
+  void* run_dev = nullptr;
+  void* run_host = nullptr;          // pinned
+  hipEvent_t run_ev[2] = {nullptr, nullptr};
+  bool run_ev_used[2] = {false, false};
 };
 
 enum KernelClass {
@@ -59,11 +64,12 @@ enum KernelClass {
   KC_GAS_SOURCE,
   KC_LEDGER,
   KC_VMAX,
+  KC_RUN_1D,
   KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {"exchange",    "gas_predict",        "gas_correct",
                                             "rad_predict", "rad_correct",        "gas_source_correct",
-                                            "ledger",      "vmax"};
+                                            "ledger",      "vmax",               "run_1d"};
 
 // Event pairs around kernel launches, drained into per-kernel totals.
 struct Timer {
@@ -497,6 +503,22 @@ int launch_gas_tiled(rhd_t* h, double dt) {
   return RHD_OK;
 }
 
+rhdk::ExchConst exch_const(const rhd_t* h, double chat, double dt) {
+  const rhd_params& p = h->p;
+  rhdk::ExchConst X;
+  X.c = p.c_light;
+  X.chat = chat;
+  X.dt = dt;
+  X.gm1 = p.gamma - 1.0;
+  X.a_rad = p.a_rad;
+  X.r_gas = p.r_gas;
+  X.theta = p.theta_E;
+  X.rtol = p.newton_rtol;
+  X.eps_cv = (p.flags & RHD_GAS_CV_T3) ? 4.0 * p.a_rad / p.cv_alpha : 0.0;
+  X.maxit = p.newton_maxit;
+  return X;
+}
+
 template <typename T>
 int enqueue_pre(rhd_t* h, double dt, double chat) {
   const rhd_params& p = h->p;
@@ -511,17 +533,7 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
 
   // implicit energy exchange over dt_gas (FP64)
   if (mode == RHD_EXCHANGE_FULL && !iso) {
-    rhdk::ExchConst X;
-    X.c = p.c_light;
-    X.chat = chat;
-    X.dt = dt;
-    X.gm1 = p.gamma - 1.0;
-    X.a_rad = p.a_rad;
-    X.r_gas = p.r_gas;
-    X.theta = p.theta_E;
-    X.rtol = p.newton_rtol;
-    X.eps_cv = (p.flags & RHD_GAS_CV_T3) ? 4.0 * p.a_rad / p.cv_alpha : 0.0;
-    X.maxit = p.newton_maxit;
+    const rhdk::ExchConst X = exch_const(h, chat, dt);
     const int ti = tbegin(h, KC_EXCHANGE, h->N);
     const int eb = std::min(EXCH_BLOCKS, blocks_for(h->N, rhdk::EXCH_THREADS));
     hipLaunchKernelGGL(rhdk::k_exchange<T>, dim3(eb), dim3(rhdk::EXCH_THREADS), 0, h->stream, gas,
@@ -596,6 +608,84 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
   if (rc) return rc;
   if (nsub > 0 && (rc = enqueue_subcycles<T>(h, dt, chat, nsub))) return rc;
   return enqueue_post<T>(h, dt, chat);
+}
+
+constexpr int RUN_CHUNK = 1024;  // steps per launch of the fused 1D path
+
+bool run_fused(const rhd_t* h) {
+  return h->G.act[0] && !h->G.act[1] && !h->G.act[2] && h->N <= rhdk::RUN1D_MAX_CELLS &&
+         (h->p.flags & RHD_RAD_ONLY);
+}
+
+// Fixed-face states of step k of rhd_run: from the table when given, else the handle's.
+void run_faces(const rhd_t* h, const double* bvals, int k, double out[6][4]) {
+  for (int f = 0; f < 6; ++f)
+    for (int q = 0; q < 4; ++q)
+      out[f][q] = (bvals && (h->fixed_mask & (1 << f))) ? bvals[size_t(k) * 24 + 4 * f + q]
+                                                        : h->bval[f][q];
+}
+
+template <typename T>
+int run_impl(rhd_t* h, int nsteps, const double* dt, const int* nsub, double chat,
+             const double* bvals) {
+  if (!run_fused(h)) {
+    for (int k = 0; k < nsteps; ++k) {
+      run_faces(h, bvals, k, h->bval);
+      if (int rc = enqueue_step<T>(h, dt[k], chat, nsub[k])) return rc;
+      h->steps += 1;
+      h->subcycles += nsub[k];
+    }
+    return RHD_OK;
+  }
+  using Step = rhdk::RunStep<T>;
+  if (!h->b.run_dev) {
+    const size_t bytes = 2 * size_t(RUN_CHUNK) * sizeof(Step);
+    HIP_TRY(h, hipMalloc(&h->b.run_dev, bytes));
+    HIP_TRY(h, hipHostMalloc(&h->b.run_host, bytes, hipHostMallocDefault));
+    for (auto& e : h->b.run_ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->bytes += (long long)bytes;
+  }
+  const rhd_params& p = h->p;
+  const unsigned mode = p.flags & RHD_EXCHANGE_MASK;
+  const int do_exch = mode == RHD_EXCHANGE_FULL && !(p.flags & RHD_ISOTHERMAL);
+  const rhdk::RadConst<T> RK = rad_const<T>(h, chat);
+  const rhdk::ExchConst X = exch_const(h, chat, 0.0);
+  const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
+  for (int c0 = 0; c0 < nsteps; c0 += RUN_CHUNK) {
+    const int cnt = std::min(RUN_CHUNK, nsteps - c0);
+    const int half = (c0 / RUN_CHUNK) & 1;
+    Step* hs = static_cast<Step*>(h->b.run_host) + size_t(half) * RUN_CHUNK;
+    Step* ds = static_cast<Step*>(h->b.run_dev) + size_t(half) * RUN_CHUNK;
+    // the copy that last read this half of the host table must have finished
+    if (h->b.run_ev_used[half]) HIP_TRY(h, hipEventSynchronize(h->b.run_ev[half]));
+    for (int k = 0; k < cnt; ++k) {
+      double bv[6][4];
+      run_faces(h, bvals, c0 + k, bv);
+      hs[k].dt = dt[c0 + k];
+      hs[k].nsub = nsub[c0 + k];
+      hs[k].pad = 0;
+      for (int f = 0; f < 6; ++f)
+        for (int q = 0; q < 4; ++q) hs[k].bv[f][q] = T(bv[f][q]);
+    }
+    HIP_TRY(h, hipMemcpyAsync(ds, hs, size_t(cnt) * sizeof(Step), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipEventRecord(h->b.run_ev[half], h->stream));
+    h->b.run_ev_used[half] = true;
+    long long sub = 0;
+    for (int k = 0; k < cnt; ++k) sub += nsub[c0 + k];
+    const int ti = tbegin(h, KC_RUN_1D, h->N * sub);
+    hipLaunchKernelGGL(rhdk::k_run_1d<T>, dim3(1), dim3(rhdk::RUN1D_THREADS), 0, h->stream,
+                       gas_ptrs<T>(h->b.gas), rad_ptrs<T>(h->b.rad), rad_ptrs<T>(h->b.rh),
+                       gas_view<T>(h), h->G, RK, X, kPp, h->kP_s, do_exch, h->fixed_mask, ds, cnt,
+                       h->b.exch_partials, h->b.ctr);
+    tend(h, ti);
+    hipLaunchKernelGGL(rhdk::k_exchange_final, dim3(1), dim3(rhdk::EXCH_THREADS), 0, h->stream,
+                       h->b.exch_partials, 1, h->b.ctr);
+    HIP_TRY(h, hipGetLastError());
+    h->steps += cnt;
+    h->subcycles += sub;
+  }
+  if (nsteps > 0) run_faces(h, bvals, nsteps - 1, h->bval);
+  return enqueue_ledger<T>(h, chat);
 }
 
 template <typename T>
@@ -742,6 +832,10 @@ void free_buffers(rhd_t* h) {
   fr(h->b.vmax);
   fr(h->b.exch_partials);
   fr(h->b.ctr);
+  fr(h->b.run_dev);
+  if (h->b.run_host) (void)hipHostFree(h->b.run_host);
+  for (auto& e : h->b.run_ev)
+    if (e) (void)hipEventDestroy(e);
   h->b = Buffers();
 }
 
@@ -1024,6 +1118,34 @@ int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub) {
     h->subcycles += nsub;
   }
   return rc;
+}
+
+int rhd_run(rhd_t* h, int nsteps, const double* dt_gas, const int* nsub, double chat,
+            const double* bvals) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (!h->have_state) return fail(h, RHD_ESTATE, "rhd_run before rhd_set_state");
+  if (nsteps < 0) return fail(h, RHD_EINVAL, "nsteps must be >= 0");
+  if (nsteps > 0 && (!dt_gas || !nsub)) return fail(h, RHD_EINVAL, "dt_gas and nsub must be non-NULL");
+  if (!(chat > 0.0) || !std::isfinite(chat))
+    return fail(h, RHD_EINVAL, "chat must be finite and > 0 (got %g)", chat);
+  // every step is checked before anything is enqueued
+  for (int k = 0; k < nsteps; ++k) {
+    if (!(dt_gas[k] > 0.0) || !std::isfinite(dt_gas[k]))
+      return fail(h, RHD_EINVAL, "step %d: dt_gas must be finite and > 0", k);
+    if (nsub[k] < 0 || nsub[k] > (1 << 20)) return fail(h, RHD_EINVAL, "step %d: nsub out of range", k);
+    if (nsub[k] > 0 && chat * dt_gas[k] / nsub[k] > h->p.cfl * h->dxmin * (1.0 + 1e-12))
+      return fail(h, RHD_ECFL, "step %d: chat dt_gas / nsub exceeds K0 dx", k);
+    if (!bvals) continue;
+    for (int f = 0; f < 6; ++f) {
+      if (!(h->fixed_mask & (1 << f))) continue;
+      const double* U = bvals + size_t(k) * 24 + 4 * f;
+      if (!(U[0] > 0.0) || !std::isfinite(U[0]) || !std::isfinite(U[1]) || !std::isfinite(U[2]) ||
+          !std::isfinite(U[3]))
+        return fail(h, RHD_EINVAL, "step %d: state of fixed face %d must be finite with E_r > 0", k, f);
+    }
+  }
+  return h->mixed ? run_impl<float>(h, nsteps, dt_gas, nsub, chat, bvals)
+                  : run_impl<double>(h, nsteps, dt_gas, nsub, chat, bvals);
 }
 
 int rhd_suggest_dt(rhd_t* h, double chat, double* dt_gas, int* nsub) {

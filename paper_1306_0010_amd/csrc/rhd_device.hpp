@@ -584,9 +584,58 @@ __device__ __forceinline__ void load_padded4(const RadPtrs<T>& R, int p, T U[4])
   U[3] = R.F[2][p];
 }
 
-// Radiation corrector: MC-limited linear reconstruction of U^{m+1/2}, HLL fluxes,
-// full step from U^m with sources at U^{m+1/2}; writes U^{m+1} over U^m (each thread
-// reads U^m only in its own cell).
+// Radiation corrector at interior cell (i, j, k): MC-limited linear reconstruction of
+// U^{m+1/2}, HLL fluxes, full step from U^m with sources at U^{m+1/2}; writes U^{m+1}
+// over U^m (U^m is read only in the cell itself). ef / fc report the E_r floor and the
+// flux clamp.
+template <typename T>
+__device__ __forceinline__ void rad_correct_cell(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
+                                                 const GasView<T>& gas, const Geom& G,
+                                                 const RadConst<T>& K, T h, int i, int j, int k,
+                                                 bool& ef, bool& fc) {
+  const int pc = padded_cell(G, i, j, k);
+  T Uc[4];
+  load_padded4(Uh, pc, Uc);
+  T div[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    const int stride = d == 0 ? 1 : (d == 1 ? G.ps[0] : G.ps[0] * G.ps[1]);
+    T Um2[4], Um1[4], Up1[4], Up2[4];
+    load_padded4(Uh, pc - 2 * stride, Um2);
+    load_padded4(Uh, pc - stride, Um1);
+    load_padded4(Uh, pc + stride, Up1);
+    load_padded4(Uh, pc + 2 * stride, Up2);
+    T Lm[4], Rm[4], Lp[4], Rp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T sm = mc_half_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
+      const T s0 = mc_half_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
+      const T sp = mc_half_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
+      Lm[q] = Um1[q] + sm;
+      Rm[q] = Uc[q] - s0;
+      Lp[q] = Uc[q] + s0;
+      Rp[q] = Up1[q] - sp;
+    }
+    T fl[4], fr[4];
+    rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
+    rad_hll(Lp, Rp, d, K.c, K.inv_c, K.chat, fr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
+  }
+  const int a = i + G.n[0] * (j + G.n[1] * k);
+  const int s[3] = {1, 1, 1};
+  const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+  T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+  T out[4];
+  rad_update(K, h, Uo, Uc, div, fz, out, ef, fc);
+  Um.E[a] = out[0];
+  Um.F[0][a] = out[1];
+  Um.F[1][a] = out[2];
+  Um.F[2][a] = out[3];
+}
+
+// Radiation corrector on the interior, one thread per cell.
 template <typename T>
 __global__ void __launch_bounds__(256) k_rad_correct(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas,
                                                      Geom G, RadConst<T> K, T h,
@@ -594,50 +643,8 @@ __global__ void __launch_bounds__(256) k_rad_correct(RadPtrs<T> Um, RadPtrs<T> U
   const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
   const int j = int(blockIdx.y * blockDim.y + threadIdx.y);
   const int k = int(blockIdx.z);
-  const bool valid = i < G.n[0] && j < G.n[1];
   bool ef = false, fc = false;
-  if (valid) {
-    const int pc = padded_cell(G, i, j, k);
-    T Uc[4];
-    load_padded4(Uh, pc, Uc);
-    T div[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (!G.act[d]) continue;
-      const int stride = d == 0 ? 1 : (d == 1 ? G.ps[0] : G.ps[0] * G.ps[1]);
-      T Um2[4], Um1[4], Up1[4], Up2[4];
-      load_padded4(Uh, pc - 2 * stride, Um2);
-      load_padded4(Uh, pc - stride, Um1);
-      load_padded4(Uh, pc + stride, Up1);
-      load_padded4(Uh, pc + 2 * stride, Up2);
-      T Lm[4], Rm[4], Lp[4], Rp[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T sm = mc_half_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
-        const T s0 = mc_half_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
-        const T sp = mc_half_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
-        Lm[q] = Um1[q] + sm;
-        Rm[q] = Uc[q] - s0;
-        Lp[q] = Uc[q] + s0;
-        Rp[q] = Up1[q] - sp;
-      }
-      T fl[4], fr[4];
-      rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
-      rad_hll(Lp, Rp, d, K.c, K.inv_c, K.chat, fr);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
-    }
-    const int a = i + G.n[0] * (j + G.n[1] * k);
-    const int s[3] = {1, 1, 1};
-    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
-    T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
-    T out[4];
-    rad_update(K, h, Uo, Uc, div, fz, out, ef, fc);
-    Um.E[a] = out[0];
-    Um.F[0][a] = out[1];
-    Um.F[1][a] = out[2];
-    Um.F[2][a] = out[3];
-  }
+  if (i < G.n[0] && j < G.n[1]) rad_correct_cell(Um, Uh, gas, G, K, h, i, j, k, ef, fc);
   wave_add(ctr + CTR_RAD_EFLOOR, ef ? 1ull : 0ull);
   wave_add(ctr + CTR_RAD_FCLAMP, fc ? 1ull : 0ull);
 }
@@ -1045,6 +1052,31 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
   return x;
 }
 
+// Exchange of cell a over X.dt (FP64 whatever T is): new gas energy and E_r, and the
+// solver statistics of the cell added to the running counts.
+template <typename T>
+__device__ __forceinline__ void exchange_cell(const GasPtrs<T>& Ug, const RadPtrs<T>& Ur,
+                                              const T* kP, double kP_s, const ExchConst& X, int a,
+                                              unsigned& n_th1, unsigned& n_bis, unsigned& n_it,
+                                              unsigned& it_max) {
+  const double rho = double(Ug.rho[a]);
+  const double m0 = double(Ug.m[0][a]), m1 = double(Ug.m[1][a]), m2 = double(Ug.m[2][a]);
+  const double Et = double(Ug.E[a]);
+  const double ke = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+  const double e = Et - ke;
+  double Er_new;
+  int it = 0;
+  bool th1 = false, bis = false;
+  const double x = exchange_root(X, rho, e, double(Ur.E[a]), kP ? double(kP[a]) : kP_s, Er_new,
+                                 it, th1, bis);
+  Ug.E[a] = T(Et + (x - e));
+  Ur.E[a] = T(Er_new);
+  n_th1 += th1 ? 1u : 0u;
+  n_bis += bis ? 1u : 0u;
+  n_it += unsigned(it);
+  it_max = unsigned(it) > it_max ? unsigned(it) : it_max;
+}
+
 // The exchange kernel keeps its solver statistics (theta = 1 fallbacks, bisections,
 // Newton iterations and their maximum) in registers, reduces them over the block and
 // writes one record of EXCH_STATS values per block; k_exchange_final folds the records
@@ -1060,24 +1092,8 @@ __global__ void __launch_bounds__(EXCH_THREADS) k_exchange(GasPtrs<T> Ug, RadPtr
   __shared__ unsigned long long sh[EXCH_STATS][EXCH_THREADS / 64];
   unsigned n_th1 = 0, n_bis = 0, n_it = 0, it_max = 0;
   const int stride = int(gridDim.x * blockDim.x);
-  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride) {
-    const double rho = double(Ug.rho[a]);
-    const double m0 = double(Ug.m[0][a]), m1 = double(Ug.m[1][a]), m2 = double(Ug.m[2][a]);
-    const double Et = double(Ug.E[a]);
-    const double ke = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
-    const double e = Et - ke;
-    double Er_new;
-    int it = 0;
-    bool th1 = false, bis = false;
-    const double x = exchange_root(X, rho, e, double(Ur.E[a]), kP ? double(kP[a]) : kP_s, Er_new,
-                                   it, th1, bis);
-    Ug.E[a] = T(Et + (x - e));
-    Ur.E[a] = T(Er_new);
-    n_th1 += th1 ? 1u : 0u;
-    n_bis += bis ? 1u : 0u;
-    n_it += unsigned(it);
-    it_max = unsigned(it) > it_max ? unsigned(it) : it_max;
-  }
+  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride)
+    exchange_cell(Ug, Ur, kP, kP_s, X, a, n_th1, n_bis, n_it, it_max);
   unsigned long long v[EXCH_STATS] = {n_th1, n_bis, n_it, it_max};
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -1259,6 +1275,97 @@ __global__ void __launch_bounds__(RED_THREADS) k_vmax_final(const T* partials, i
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = double(sh[0]);
+}
+
+// ---------------------------------------------------------------------------
+// many gas steps of a small 1D radiation-only grid in one launch
+// ---------------------------------------------------------------------------
+
+// One gas step of a sequence: its length, subcycle count and fixed-face states.
+template <typename T>
+struct RunStep {
+  double dt;
+  int nsub;
+  int pad;
+  T bv[6][4];
+};
+
+constexpr int RUN1D_THREADS = 1024;
+constexpr int RUN1D_MAX_CELLS = 4096;
+
+// One workgroup advances a 1D grid of at most RUN1D_MAX_CELLS cells with the gas frozen
+// by nsteps gas steps: per step the exchange over dt (if do_exch), then nsub radiation
+// Van Leer subcycles, each stage a loop of the workgroup over the cells with a barrier
+// after it. The per-cell work is the same device code as the separate launches, so the
+// result is the same bit for bit; what goes is the launch latency between the stages,
+// which dominates at these sizes. Every loop runs a bounded count, so the workgroup
+// always finishes. Exchange statistics go to part[0 .. EXCH_STATS) as one block record.
+template <typename T>
+__global__ void __launch_bounds__(RUN1D_THREADS) k_run_1d(GasPtrs<T> Ug, RadPtrs<T> Um,
+                                                          RadPtrs<T> Uh, GasView<T> view, Geom G,
+                                                          RadConst<T> K, ExchConst X, const T* kP,
+                                                          double kP_s, int do_exch, int fixed_mask,
+                                                          const RunStep<T>* __restrict__ steps,
+                                                          int nsteps, unsigned long long* part,
+                                                          unsigned long long* ctr) {
+  __shared__ unsigned long long sh[EXCH_STATS][RUN1D_THREADS / 64];
+  const int tid = int(threadIdx.x);
+  const int n0 = G.n[0], g0 = G.g[0];
+  unsigned n_th1 = 0, n_bis = 0, n_it = 0, it_max = 0;
+  unsigned long long nef = 0, nfc = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    const double dt = steps[k].dt;
+    const int ns = steps[k].nsub;
+    if (do_exch) {
+      ExchConst Xk = X;
+      Xk.dt = dt;
+      for (int a = tid; a < n0; a += RUN1D_THREADS)
+        exchange_cell(Ug, Um, kP, kP_s, Xk, a, n_th1, n_bis, n_it, it_max);
+      __syncthreads();
+    }
+    if (ns <= 0) continue;
+    FixedFaces<T> B;
+    B.mask = fixed_mask;
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) B.v[f][q] = steps[k].bv[f][q];
+    const double hr = dt / ns;
+    const T hp = T(0.5 * hr), hc = T(hr);
+    for (int m = 0; m < ns; ++m) {
+      for (int p = tid; p < n0 + 2 * g0; p += RUN1D_THREADS)
+        rad_predict_cell(Um, Uh, view, G, K, B, hp, p - g0, 0, 0);
+      __syncthreads();
+      for (int a = tid; a < n0; a += RUN1D_THREADS) {
+        bool ef = false, fc = false;
+        rad_correct_cell(Um, Uh, view, G, K, hc, a, 0, 0, ef, fc);
+        nef += ef ? 1ull : 0ull;
+        nfc += fc ? 1ull : 0ull;
+      }
+      __syncthreads();
+    }
+  }
+  wave_add(ctr + CTR_RAD_EFLOOR, nef);
+  wave_add(ctr + CTR_RAD_FCLAMP, nfc);
+  unsigned long long v[EXCH_STATS] = {n_th1, n_bis, n_it, it_max};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] += __shfl_xor(v[q], off, 64);
+    const unsigned long long o = __shfl_xor(v[3], off, 64);
+    v[3] = o > v[3] ? o : v[3];
+  }
+  if (__lane_id() == 0) {
+#pragma unroll
+    for (int q = 0; q < EXCH_STATS; ++q) sh[q][tid >> 6] = v[q];
+  }
+  __syncthreads();
+  if (tid < EXCH_STATS) {
+    unsigned long long r = sh[tid][0];
+    for (int w = 1; w < RUN1D_THREADS / 64; ++w)
+      r = tid == 3 ? (sh[tid][w] > r ? sh[tid][w] : r) : r + sh[tid][w];
+    part[tid] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------

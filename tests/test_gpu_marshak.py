@@ -101,3 +101,104 @@ def test_boundary_calls_are_checked():
     with P.Solver(spec) as s:
         with pytest.raises(P.RhdError):
             P.rhd_set_boundary(s.h, 0, (1.0, 0.0, 0.0, 0.0))
+
+
+def stepped(spec, st, dts, nsubs, chat, bvals=None):
+    """Reference: one rhd_set_boundary + rhd_step per step."""
+    with P.Solver(spec) as s:
+        s.set_state(st)
+        for k, (dt, ns) in enumerate(zip(dts, nsubs)):
+            if bvals is not None:
+                s.set_boundary(bvals[k])
+            s.step(dt, chat, ns)
+        s.sync()
+        return s.get_state(), s.diagnostics()
+
+
+def run_once(spec, st, dts, nsubs, chat, bvals=None):
+    with P.Solver(spec) as s:
+        s.set_state(st)
+        s.run(dts, nsubs, chat, bvals)
+        s.sync()
+        return s.get_state(), s.diagnostics()
+
+
+def assert_same(a, b, da, db):
+    for k in ri.FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("steps", "subcycles", "exch_theta1", "exch_bisect", "newton_iters", "newton_max",
+              "rad_fclamp", "rad_efloor", "nonfinite"):
+        assert da[k] == db[k], k
+    assert da["ledger"] == db["ledger"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_run_equals_stepping_on_the_marshak_wave(precision):
+    """rhd_run on a small 1D radiation-only grid takes 1024 steps per launch of one
+    workgroup; across three launches its result and counters equal step-by-step
+    stepping bit for bit."""
+    announce(f"rhd_run marshak {precision}")
+    pb = ri.marshak_problem(96, precision=precision)
+    spec, dt = pb["spec"], pb["dt"]
+    n = 2300
+    dts = np.full(n, dt)
+    nsubs = np.ones(n, dtype=np.int32)
+    bvals = np.array([ri.marshak_boundary((k + 0.5) * dt, nq=400) for k in range(n)])
+    a, da = run_once(spec, pb["state"], dts, nsubs, 1.0, bvals)
+    b, db = stepped(spec, pb["state"], dts, nsubs, 1.0, bvals)
+    assert_same(a, b, da, db)
+    assert a["Er"][0, 0, 0] > 0.5
+
+
+def test_run_equals_stepping_with_exchange_opacity_and_emission_fields():
+    """A 1D periodic radiation-only grid of 1500 cells (more cells than threads) with
+    the ideal-gas exchange (Newton iterations), per-cell opacities, emission and a
+    subcycle count that changes from step to step."""
+    announce("rhd_run 1d ideal gas")
+    n = 1500
+    spec = ri.default_spec(nx=n, dx=1.0 / n, c_light=20.0, rad_only=True, exchange="full",
+                           theta_E=0.7, theta_F=0.51, bc="periodic", precision="fp64")
+    st = ri.smooth_random_state(spec, seed=77, amp=0.2, f_amp=0.3, kappa=(3.0, 2.0), v_amp=0.0,
+                                with_j=True)
+    assert np.ndim(st["kP"]) > 0 and np.ptp(st["kP"]) > 0 and st.get("j") is not None
+    nsubs = np.array([1, 2, 3, 4, 2, 1] * 20, dtype=np.int32)
+    dts = 0.35 * spec["dx"] / spec["c_light"] * nsubs
+    a, da = run_once(spec, st, dts, nsubs, spec["c_light"])
+    b, db = stepped(spec, st, dts, nsubs, spec["c_light"])
+    assert da["newton_iters"] > 0
+    assert_same(a, b, da, db)
+
+
+def test_run_on_other_grids_enqueues_the_steps():
+    announce("rhd_run 3d")
+    spec = ri.default_spec(nx=20, ny=12, nz=10, dx=0.05, dy=1 / 12, dz=0.1, c_light=30.0,
+                           exchange="full", bc="periodic", precision="mixed")
+    st = ri.smooth_random_state(spec, seed=5, amp=0.1, f_amp=0.3, kappa=(3.0, 2.0), v_amp=0.1)
+    dt, ns, _ = oracle.suggest_dt(spec, st, 30.0)
+    dts, nsubs = np.full(3, dt), np.full(3, ns, dtype=np.int32)
+    a, da = run_once(spec, st, dts, nsubs, 30.0)
+    b, db = stepped(spec, st, dts, nsubs, 30.0)
+    assert_same(a, b, da, db)
+
+
+def test_run_checks_every_step_before_enqueueing():
+    announce("rhd_run errors")
+    pb = ri.marshak_problem(32)
+    spec, dt = pb["spec"], pb["dt"]
+    with P.Solver(spec) as s:
+        s.set_state(pb["state"])
+        before = s.get_state()
+        dts = np.full(8, dt)
+        dts[5] = 10 * dt  # breaks the CFL condition in step 5
+        with pytest.raises(P.RhdError) as e:
+            s.run(dts, np.ones(8, dtype=np.int32), 1.0)
+        assert e.value.code == P.RHD_ECFL
+        bv = np.array([ri.marshak_boundary(0.1)] * 8)
+        bv[3, 0, 0] = -1.0
+        with pytest.raises(P.RhdError) as e:
+            s.run(np.full(8, dt), np.ones(8, dtype=np.int32), 1.0, bv)
+        assert e.value.code == P.RHD_EINVAL
+        after = s.get_state()
+        assert s.diagnostics()["steps"] == 0
+        for k in ri.FIELDS:
+            assert np.array_equal(before[k], after[k]), k
