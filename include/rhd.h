@@ -183,10 +183,11 @@ int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub);
    face f during step k (entries of other faces are ignored; with bvals NULL the states
    of rhd_set_boundary stay). The result equals nsteps calls of rhd_set_boundary and
    rhd_step, bit for bit, with the ledger taken once at the end; afterwards the fixed
-   faces keep the last step's states. A 1D RHD_RAD_ONLY grid of at most 4096 cells runs
-   1024 steps per launch of one workgroup (at such sizes separate launches cost more than
-   the arithmetic); on its first such call the handle allocates its step tables (device
-   and pinned host memory, 2 x 1024 steps). Other grids enqueue the steps one by one.
+   faces keep the last step's states. A 1D RHD_RAD_ONLY grid of at most 1024 cells (2048
+   in mixed precision) runs 1024 steps per launch of one workgroup (at such sizes
+   separate launches cost more than the arithmetic); on its first such call the handle
+   allocates its step tables (device and pinned host memory, 2 x 1024 steps). Other
+   grids enqueue the steps one by one.
    Every step is checked before anything is enqueued: RHD_EINVAL for nsteps < 0, NULL
    arrays, dt_gas <= 0, nsub < 0, chat <= 0 or a fixed-face state with E_r <= 0 or a
    non-finite value; RHD_ECFL as rhd_step. Asynchronous like rhd_step. */

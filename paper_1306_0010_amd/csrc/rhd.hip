@@ -612,8 +612,9 @@ int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
 
 constexpr int RUN_CHUNK = 1024;  // steps per launch of the fused 1D path
 
+template <typename T>
 bool run_fused(const rhd_t* h) {
-  return h->G.act[0] && !h->G.act[1] && !h->G.act[2] && h->N <= rhdk::RUN1D_MAX_CELLS &&
+  return h->G.act[0] && !h->G.act[1] && !h->G.act[2] && h->N <= rhdk::run1d_max_cells<T>() &&
          (h->p.flags & RHD_RAD_ONLY);
 }
 
@@ -628,7 +629,7 @@ void run_faces(const rhd_t* h, const double* bvals, int k, double out[6][4]) {
 template <typename T>
 int run_impl(rhd_t* h, int nsteps, const double* dt, const int* nsub, double chat,
              const double* bvals) {
-  if (!run_fused(h)) {
+  if (!run_fused<T>(h)) {
     for (int k = 0; k < nsteps; ++k) {
       run_faces(h, bvals, k, h->bval);
       if (int rc = enqueue_step<T>(h, dt[k], chat, nsub[k])) return rc;

@@ -1291,9 +1291,14 @@ struct RunStep {
 };
 
 constexpr int RUN1D_THREADS = 1024;
-constexpr int RUN1D_MAX_CELLS = 4096;
+// Largest grid the fused path takes: one workgroup does all the arithmetic, so beyond one
+// cell per thread in FP64 (two in FP32) separate launches over the whole GPU are faster.
+template <typename T>
+constexpr int run1d_max_cells() {
+  return sizeof(T) == 4 ? 2 * RUN1D_THREADS : RUN1D_THREADS;
+}
 
-// One workgroup advances a 1D grid of at most RUN1D_MAX_CELLS cells with the gas frozen
+// One workgroup advances a 1D grid of at most run1d_max_cells<T>() cells with the gas frozen
 // by nsteps gas steps: per step the exchange over dt (if do_exch), then nsub radiation
 // Van Leer subcycles, each stage a loop of the workgroup over the cells with a barrier
 // after it. The per-cell work is the same device code as the separate launches, so the

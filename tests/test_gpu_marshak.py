@@ -134,9 +134,18 @@ def assert_same(a, b, da, db):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_run_equals_stepping_on_the_marshak_wave(precision):
+    announce(f"rhd_run marshak 1200 fp64")
+    pb = ri.marshak_problem(1200)
+    dts = np.full(40, pb["dt"])
+    nsubs = np.ones(40, dtype=np.int32)
+    bvals = np.array([ri.marshak_boundary((k + 0.5) * pb["dt"], nq=400) for k in range(40)])
+    a, da = run_once(pb["spec"], pb["state"], dts, nsubs, 1.0, bvals)
+    b, db = stepped(pb["spec"], pb["state"], dts, nsubs, 1.0, bvals)
+    assert_same(a, b, da, db)
     """rhd_run on a small 1D radiation-only grid takes 1024 steps per launch of one
     workgroup; across three launches its result and counters equal step-by-step
-    stepping bit for bit."""
+    stepping bit for bit. The 1200-cell FP64 grid takes the step-by-step path inside
+    rhd_run and must give the same."""
     announce(f"rhd_run marshak {precision}")
     pb = ri.marshak_problem(96, precision=precision)
     spec, dt = pb["spec"], pb["dt"]
@@ -151,13 +160,13 @@ def test_run_equals_stepping_on_the_marshak_wave(precision):
 
 
 def test_run_equals_stepping_with_exchange_opacity_and_emission_fields():
-    """A 1D periodic radiation-only grid of 1500 cells (more cells than threads) with
-    the ideal-gas exchange (Newton iterations), per-cell opacities, emission and a
-    subcycle count that changes from step to step."""
+    """A 1D periodic radiation-only grid of 1500 cells (more cells than threads, mixed
+    precision, so still one workgroup) with the ideal-gas exchange (Newton iterations),
+    per-cell opacities, emission and a subcycle count that changes from step to step."""
     announce("rhd_run 1d ideal gas")
     n = 1500
     spec = ri.default_spec(nx=n, dx=1.0 / n, c_light=20.0, rad_only=True, exchange="full",
-                           theta_E=0.7, theta_F=0.51, bc="periodic", precision="fp64")
+                           theta_E=0.7, theta_F=0.51, bc="periodic", precision="mixed")
     st = ri.smooth_random_state(spec, seed=77, amp=0.2, f_amp=0.3, kappa=(3.0, 2.0), v_amp=0.0,
                                 with_j=True)
     assert np.ndim(st["kP"]) > 0 and np.ptp(st["kP"]) > 0 and st.get("j") is not None
