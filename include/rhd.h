@@ -70,6 +70,11 @@ extern "C" {
 #define RHD_RAD_ONLY            (1u << 4)  /* gas frozen: no gas transport, no correction  */
 #define RHD_PRECISION_MIXED     (1u << 5)  /* FP32 storage and stencils, FP64 exchange and
                                               ledger; without it everything is FP64        */
+#define RHD_OPACITY_LAW         (1u << 7)  /* kappa_P = kappa_F = k0 (T_gas/T0)^a (rho/rho0)^b
+                                              (Sec. 4.2.1), kappa_law = {k0, T0, rho0, a, b},
+                                              from the gas state at the start of each gas
+                                              step (and for rhd_suggest_dt); the kappa
+                                              arrays of rhd_set_state are then not read   */
 #define RHD_GAS_CV_T3           (1u << 6)  /* heat capacity c_v = cv_alpha T^3 (Sec. 4.2.3):
                                               a_R T^4 = (4 a_R / cv_alpha) e, so the exchange
                                               (theta-scheme of Eq. source:energyupdate) is
@@ -94,6 +99,7 @@ typedef struct {
                                    come in pairs; reflecting faces need n >= 3             */
   unsigned flags;               /* RHD_* flags above                                        */
   double cv_alpha;              /* alpha of c_v = alpha T^3 with RHD_GAS_CV_T3, else unused */
+  double kappa_law[5];          /* k0 >= 0, T0 > 0, rho0 > 0, a, b of RHD_OPACITY_LAW      */
 } rhd_params;
 
 typedef struct {

@@ -30,6 +30,7 @@ BETA_TAU = 1 << 3
 RAD_ONLY = 1 << 4
 PRECISION_MIXED = 1 << 5
 GAS_CV_T3 = 1 << 6
+OPACITY_LAW = 1 << 7
 
 STATE_FIELDS = ("rho", "mx", "my", "mz", "E", "Er", "Fx", "Fy", "Fz")
 
@@ -62,6 +63,7 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_uint),
         ("cv_alpha", ctypes.c_double),
         ("bval", (ctypes.c_double * 4) * 6),
+        ("kappa_law", ctypes.c_double * 5),
     ]
 
 
@@ -136,6 +138,10 @@ def make_params(spec):
         flags |= PRECISION_MIXED
     if spec["cv_t3"]:
         flags |= GAS_CV_T3
+    if spec["kappa_law"] is not None:
+        flags |= OPACITY_LAW
+        for q in range(5):
+            p.kappa_law[q] = float(spec["kappa_law"][q])
     p.flags = flags
     p.cv_alpha = float(spec["cv_alpha"])
     for f in range(6):

@@ -36,7 +36,8 @@
  *    with three ghost layers filled; the corrector uses those predicted ghosts
  *    directly (no boundary refill between the stages);
  *  - after every radiation stage E_r is raised to er_floor and then F is scaled
- *    back to |F| = c E_r if it exceeds it; after every gas stage rho and P are
+ *    back to |F| = c E_r if it exceeds it, and E_r of every reconstructed face state
+ *    is raised to er_floor before its closure; after every gas stage rho and P are
  *    raised to their floors;
  *  - emission j adds (chat/c) j to dE_r/dt, so that div F = j in a steady state;
  *  - in ABSORB_ONLY mode E_r is damped with kappa_P by the same theta-form as F,
@@ -47,7 +48,11 @@
  *    continue zero-gradient there;
  *  - with c_v = alpha T^3 (Sec. 4.2.3) the exchange keeps the theta-scheme form of
  *    Eq. source:energyupdate with a_R T^4 = (4 a_R/alpha) e, which makes the update
- *    linear in e; with chat = c it is the update printed with that problem.
+ *    linear in e; with chat = c it is the update printed with that problem;
+ *  - an opacity law kappa(T_gas, rho) (the shadow test of Sec. 4.2.1) gives the one
+ *    absorption opacity for kappa_P and kappa_F, evaluated from the gas state at the
+ *    start of each gas step and held through the step (exchange, gas step and
+ *    subcycles), and from the current state for the CFL step.
  */
 #include "rhd_oracle.h"
 
@@ -380,6 +385,13 @@ static void rad_stage(const orc_params *p, const pgrid *G, double chat, double h
               Lp[q] = U0[q] + 0.5 * s0[q]; /* left state of face i+1/2  */
               Rp[q] = Up[q] - 0.5 * sp[q]; /* right state of face i+1/2 */
             }
+            /* E_r of a face state is raised to the floor: a face state may reach a
+               neighbour's value, and next to a cell at the floor rounding can take it to
+               zero, where the closure has no direction */
+            Lm[0] = Lm[0] > p->er_floor ? Lm[0] : p->er_floor;
+            Rm[0] = Rm[0] > p->er_floor ? Rm[0] : p->er_floor;
+            Lp[0] = Lp[0] > p->er_floor ? Lp[0] : p->er_floor;
+            Rp[0] = Rp[0] > p->er_floor ? Rp[0] : p->er_floor;
             orc_rad_hll_flux(Lm, Rm, d, c, chat, fl);
             orc_rad_hll_flux(Lp, Rp, d, c, chat, fr);
           }
@@ -750,6 +762,30 @@ double orc_exchange_cell(double rho, double e, double Er, double kP, double dt,
 }
 
 /* ------------------------------------------------------------------------- */
+/* opacity law (Sec. 4.2.1): kappa = k0 (T_gas/T0)^a (rho/rho0)^b             */
+/* ------------------------------------------------------------------------- */
+
+/* Gas temperature of cell a: P/(rho r_gas) for the ideal gas, c_s^2/r_gas when
+   isothermal, and from a_R T^4 = (4 a_R/alpha) e when c_v = alpha T^3. */
+static double gas_temperature(const orc_params *p, const orc_fields *s, long a) {
+  double rho = s->rho[a];
+  if (isothermal(p)) return p->iso_cs * p->iso_cs / p->r_gas;
+  double e = s->E[a] - 0.5 * (s->mx[a] * s->mx[a] + s->my[a] * s->my[a] + s->mz[a] * s->mz[a]) / rho;
+  if (p->flags & ORC_GAS_CV_T3) return pow(4.0 * e / p->cv_alpha, 0.25);
+  return (p->gamma - 1.0) * e / (rho * p->r_gas);
+}
+
+/* The law's opacity of every cell into kap (N values). */
+static void opacity_law(const orc_params *p, const orc_fields *s, double *kap) {
+  const long N = (long)p->nx * p->ny * p->nz;
+  const double *L = p->kappa_law;
+  for (long a = 0; a < N; ++a) {
+    double T = gas_temperature(p, s, a);
+    kap[a] = L[0] * pow(T / L[1], L[3]) * pow(s->rho[a] / L[2], L[4]);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
 /* time step (Sec. 3.1, Eqs. algorithm:ceff to algorithm:radtimestep)         */
 /* ------------------------------------------------------------------------- */
 
@@ -758,6 +794,15 @@ int orc_suggest_dt(const orc_params *p, const orc_fields *s, double chat, double
   const double dxm = min_width(p);
   double vmax = 0.0;
   long N = (long)p->nx * p->ny * p->nz;
+  orc_fields local;
+  double *law = NULL;
+  if (p->flags & ORC_OPACITY_LAW) {
+    law = (double *)malloc((size_t)N * sizeof(double));
+    opacity_law(p, s, law);
+    local = *s;
+    local.kP = local.kF = law;
+    s = &local;
+  }
   for (long a = 0; a < N; ++a) {
     double rho = s->rho[a];
     double v[3] = {s->mx[a] / rho, s->my[a] / rho, s->mz[a] / rho};
@@ -772,6 +817,7 @@ int orc_suggest_dt(const orc_params *p, const orc_fields *s, double chat, double
     double ceff = sqrt((gP + (4.0 / 9.0) * s->Er[a] * (1.0 - exp(-rho * s->kF[a] * dxm))) / rho);
     if (vn + ceff > vmax) vmax = vn + ceff;
   }
+  free(law);
   *vmax_out = vmax;
   if (!(vmax > 0.0)) return -1;
   *dt_gas = p->cfl * dxm / vmax;
@@ -820,6 +866,16 @@ int orc_step(const orc_params *p, orc_fields *s, double dt_gas, double chat, int
   const long N = (long)p->nx * p->ny * p->nz;
   const unsigned mode = p->flags & ORC_EXCH_MASK;
   const int rad_only = (p->flags & ORC_RAD_ONLY) != 0;
+
+  /* opacity law: evaluated once from the state at the start of the step */
+  orc_fields local = *s;
+  double *law = NULL;
+  if (p->flags & ORC_OPACITY_LAW) {
+    law = (double *)malloc((size_t)N * sizeof(double));
+    opacity_law(p, s, law);
+    local.kP = local.kF = law;
+  }
+  s = &local;
 
   /* step 2: implicit energy exchange S_i over dt_gas */
   if (mode == ORC_EXCH_FULL && !isothermal(p)) {
@@ -953,5 +1009,6 @@ int orc_step(const orc_params *p, orc_fields *s, double dt_gas, double chat, int
     free_fields(s_n, 4);
     free_fields(w_h, 4);
   }
+  free(law);
   return 0;
 }

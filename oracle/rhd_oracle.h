@@ -37,6 +37,9 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2, ORC_BC_FIXED
 #define ORC_PRECISION_MIXED   (1u << 5)   /* ignored by the oracle (always FP64)      */
 #define ORC_GAS_CV_T3         (1u << 6)   /* heat capacity c_v = cv_alpha T^3, so that
                                              a_R T^4 = (4 a_R / cv_alpha) e            */
+#define ORC_OPACITY_LAW       (1u << 7)   /* kappa_P = kappa_F = k0 (T/T0)^a (rho/rho0)^b
+                                             from the gas state at the start of each
+                                             step; kappa_law = {k0, T0, rho0, a, b}     */
 
 typedef struct {
   int nx, ny, nz;                 /* interior cells; ny = nz = 1 for 1D           */
@@ -53,6 +56,7 @@ typedef struct {
   unsigned flags;
   double cv_alpha;                /* alpha of c_v = alpha T^3 (ORC_GAS_CV_T3)     */
   double bval[6][4];              /* radiation state of each ORC_BC_FIXED face    */
+  double kappa_law[5];            /* k0, T0, rho0, a, b of ORC_OPACITY_LAW        */
 } orc_params;
 
 typedef struct {

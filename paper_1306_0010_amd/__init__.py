@@ -40,6 +40,7 @@ RHD_BETA_TAU = 1 << 3
 RHD_RAD_ONLY = 1 << 4
 RHD_PRECISION_MIXED = 1 << 5
 RHD_GAS_CV_T3 = 1 << 6
+RHD_OPACITY_LAW = 1 << 7
 RHD_KERNELS_PER_CELL = 0
 RHD_KERNELS_TILED = 1
 
@@ -77,6 +78,7 @@ class rhd_params(ctypes.Structure):
         ("bc", ctypes.c_int * 6),
         ("flags", ctypes.c_uint),
         ("cv_alpha", ctypes.c_double),
+        ("kappa_law", ctypes.c_double * 5),
     ]
 
 
@@ -522,6 +524,10 @@ def params_from_spec(spec):
         flags |= RHD_PRECISION_MIXED
     if spec.get("cv_t3"):
         flags |= RHD_GAS_CV_T3
+    if spec.get("kappa_law") is not None:
+        flags |= RHD_OPACITY_LAW
+        for q in range(5):
+            p.kappa_law[q] = float(spec["kappa_law"][q])
     p.flags = flags
     p.cv_alpha = float(spec.get("cv_alpha", 0.0))
     return p

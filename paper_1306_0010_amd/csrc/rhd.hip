@@ -213,7 +213,13 @@ int validate(const rhd_params* p) {
     return fail(nullptr, RHD_EINVAL, "floors must be >= 0");
   if ((p->flags & RHD_EXCHANGE_MASK) == (3u << 1))
     return fail(nullptr, RHD_EINVAL, "unknown exchange mode");
-  if (p->flags & ~((1u << 7) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  if (p->flags & ~((1u << 8) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  if (p->flags & RHD_OPACITY_LAW) {
+    const double* L = p->kappa_law;
+    if (!(L[0] >= 0.0) || !(L[1] > 0.0) || !(L[2] > 0.0) || !std::isfinite(L[0]) ||
+        !std::isfinite(L[1]) || !std::isfinite(L[2]) || !std::isfinite(L[3]) || !std::isfinite(L[4]))
+      return fail(nullptr, RHD_EINVAL, "kappa_law needs k0 >= 0, T0 > 0, rho0 > 0, finite exponents");
+  }
   if (p->flags & RHD_GAS_CV_T3) {
     if (!(p->flags & RHD_RAD_ONLY) || (p->flags & RHD_ISOTHERMAL))
       return fail(nullptr, RHD_EINVAL, "RHD_GAS_CV_T3 needs RHD_RAD_ONLY and an ideal gas");
@@ -519,6 +525,27 @@ rhdk::ExchConst exch_const(const rhd_t* h, double chat, double dt) {
   return X;
 }
 
+// Refill the per-cell opacities from the law (RHD_OPACITY_LAW) for the current state.
+template <typename T>
+int enqueue_opacity_law(rhd_t* h) {
+  if (!(h->p.flags & RHD_OPACITY_LAW)) return RHD_OK;
+  const rhd_params& p = h->p;
+  rhdk::OpacityLaw L;
+  L.k0 = p.kappa_law[0];
+  L.T0 = p.kappa_law[1];
+  L.rho0 = p.kappa_law[2];
+  L.a = p.kappa_law[3];
+  L.b = p.kappa_law[4];
+  L.gm1_over_r = (p.gamma - 1.0) / p.r_gas;
+  L.T_iso = p.iso_cs * p.iso_cs / p.r_gas;
+  L.cv_4 = (p.flags & RHD_GAS_CV_T3) ? 4.0 / p.cv_alpha : 0.0;
+  L.mode = (p.flags & RHD_ISOTHERMAL) ? 1 : ((p.flags & RHD_GAS_CV_T3) ? 2 : 0);
+  hipLaunchKernelGGL(rhdk::k_opacity_law<T>, dim3(blocks_for(h->N, 256)), dim3(256), 0, h->stream,
+                     gas_ptrs<T>(h->b.gas), as<T>(h->b.kP), as<T>(h->b.kF), L, h->N);
+  HIP_TRY(h, hipGetLastError());
+  return RHD_OK;
+}
+
 template <typename T>
 int enqueue_pre(rhd_t* h, double dt, double chat) {
   const rhd_params& p = h->p;
@@ -530,6 +557,8 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
   auto rad = rad_ptrs<T>(h->b.rad);
   const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
   const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
+  // an opacity law is evaluated once per gas step, from the state at its start
+  if (int rc = enqueue_opacity_law<T>(h)) return rc;
 
   // implicit energy exchange over dt_gas (FP64)
   if (mode == RHD_EXCHANGE_FULL && !iso) {
@@ -614,8 +643,9 @@ constexpr int RUN_CHUNK = 1024;  // steps per launch of the fused 1D path
 
 template <typename T>
 bool run_fused(const rhd_t* h) {
+  // an opacity law is refreshed per step by its own kernel, which the fused path does not run
   return h->G.act[0] && !h->G.act[1] && !h->G.act[2] && h->N <= rhdk::run1d_max_cells<T>() &&
-         (h->p.flags & RHD_RAD_ONLY);
+         (h->p.flags & RHD_RAD_ONLY) && !(h->p.flags & RHD_OPACITY_LAW);
 }
 
 // Fixed-face states of step k of rhd_run: from the table when given, else the handle's.
@@ -722,7 +752,8 @@ template <typename T>
 int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double* E,
                    const double* Er, const double* Fr, const double* kappaP, const double* kappaF,
                    int kappa_scalar, bool host) {
-  if (!rho || !mom || !Er || !Fr || !kappaP || !kappaF)
+  const bool law = (h->p.flags & RHD_OPACITY_LAW) != 0;
+  if (!rho || !mom || !Er || !Fr || ((!kappaP || !kappaF) && !law))
     return fail(h, RHD_EINVAL, "rho, mom, Er, Fr, kappaP and kappaF must be non-NULL");
   const bool iso = (h->p.flags & RHD_ISOTHERMAL) != 0;
   if (!E && !iso) return fail(h, RHD_EINVAL, "E must be non-NULL for an ideal gas");
@@ -740,7 +771,17 @@ int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double*
   if ((rc = upload_field<T>(h, Er, h->b.rad[0], N, host))) return rc;
   for (int q = 0; q < 3; ++q)
     if ((rc = upload_field<T>(h, Fr + size_t(q) * N, h->b.rad[1 + q], N, host))) return rc;
-  if (kappa_scalar) {
+  if (law) {
+    // the opacities come from the law; the arrays given (if any) are not read
+    if (!h->b.kP) {
+      HIP_TRY(h, hipMalloc(&h->b.kP, size_t(N) * h->esize));
+      HIP_TRY(h, hipMalloc(&h->b.kF, size_t(N) * h->esize));
+      h->bytes += 2ll * N * (long long)h->esize;
+    }
+    h->kappa_scalar = false;
+    if ((rc = enqueue_opacity_law<T>(h))) return rc;
+    if (host) HIP_TRY(h, hipStreamSynchronize(h->stream));
+  } else if (kappa_scalar) {
     double kp = 0.0, kf = 0.0;
     if (host) {
       kp = kappaP[0];
@@ -786,6 +827,7 @@ int get_state_impl(rhd_t* h, double* rho, double* mom, double* E, double* Er, do
 
 template <typename T>
 int suggest_impl(rhd_t* h, double chat, double* dt_gas, int* nsub) {
+  if (int rc = enqueue_opacity_law<T>(h)) return rc;
   rhdk::CflConst C;
   C.gamma = h->p.gamma;
   C.gm1 = h->p.gamma - 1.0;
@@ -962,6 +1004,7 @@ void rhd_default_params(rhd_params* p, int nx, int ny, int nz) {
   for (int f = 0; f < 6; ++f) p->bc[f] = RHD_BC_PERIODIC;
   p->flags = RHD_EXCHANGE_FULL;
   p->cv_alpha = 0.0;
+  for (int q = 0; q < 5; ++q) p->kappa_law[q] = 0.0;
 }
 
 long long rhd_footprint_bytes(const rhd_params* p) {
@@ -1406,6 +1449,7 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
   // 1. v_max of every member, one synchronisation
   for (int i = 0; i < S; ++i) {
     rhd_t* h = b->members[i];
+    if (int rc = enqueue_opacity_law<T>(h)) return bfail(b, rc, "member %d: %s", i, h->err);
     rhdk::CflConst C;
     C.gamma = h->p.gamma;
     C.gm1 = h->p.gamma - 1.0;

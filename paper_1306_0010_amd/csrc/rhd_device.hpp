@@ -438,7 +438,12 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
   const T cE = K.c * En;
   const T Fm2 = Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2];
   if (Fm2 > cE * cE) {
-    const T scale = cE * rsqrt_(Fm2);
+    // FP32: near the E_r floor both squares can be subnormal, which the hardware
+    // reciprocal square root reads as zero (an infinite scale); from the smallest normal
+    // up the scale is finite and still brings |F| to at most c E_r
+    T m2 = Fm2;
+    if constexpr (sizeof(T) == 4) m2 = vmax(Fm2, 1.17549435e-38f);
+    const T scale = cE * rsqrt_(m2);
     Fn[0] *= scale;
     Fn[1] *= scale;
     Fn[2] *= scale;
@@ -617,6 +622,12 @@ __device__ __forceinline__ void rad_correct_cell(const RadPtrs<T>& Um, const Rad
       Lp[q] = Uc[q] + s0;
       Rp[q] = Up1[q] - sp;
     }
+    // E_r of a face state is raised to the floor (rounding next to a cell at the floor
+    // can take it to zero)
+    Lm[0] = vmax(Lm[0], K.er_floor);
+    Rm[0] = vmax(Rm[0], K.er_floor);
+    Lp[0] = vmax(Lp[0], K.er_floor);
+    Rp[0] = vmax(Rp[0], K.er_floor);
     T fl[4], fr[4];
     rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
     rad_hll(Lp, Rp, d, K.c, K.inv_c, K.chat, fr);
@@ -1275,6 +1286,37 @@ __global__ void __launch_bounds__(RED_THREADS) k_vmax_final(const T* partials, i
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = double(sh[0]);
+}
+
+// ---------------------------------------------------------------------------
+// opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.2.1)
+// ---------------------------------------------------------------------------
+
+struct OpacityLaw {
+  double k0, T0, rho0, a, b;
+  double gm1_over_r;  // (gamma - 1) / r_gas: T = gm1_over_r e / rho for the ideal gas
+  double T_iso;       // c_s^2 / r_gas for the isothermal gas
+  double cv_4;        // 4 / cv_alpha when c_v = cv_alpha T^3: T^4 = cv_4 e
+  int mode;           // 0 ideal gas, 1 isothermal, 2 c_v = alpha T^3
+};
+
+// The one absorption opacity of every cell (kappa_P = kappa_F) from its gas temperature
+// and density, in FP64, stored as T.
+template <typename T>
+__global__ void __launch_bounds__(256) k_opacity_law(GasPtrs<T> g, T* kP, T* kF, OpacityLaw L,
+                                                     int N) {
+  const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a >= N) return;
+  const double rho = double(g.rho[a]);
+  double Tg = L.T_iso;
+  if (L.mode != 1) {
+    const double m0 = double(g.m[0][a]), m1 = double(g.m[1][a]), m2 = double(g.m[2][a]);
+    const double e = double(g.E[a]) - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+    Tg = L.mode == 2 ? sqrt(sqrt(L.cv_4 * e)) : L.gm1_over_r * e / rho;
+  }
+  const double k = L.k0 * pow(Tg / L.T0, L.a) * pow(rho / L.rho0, L.b);
+  kP[a] = T(k);
+  kF[a] = T(k);
 }
 
 // ---------------------------------------------------------------------------

@@ -379,26 +379,30 @@ struct CorrectRing {
 };
 
 // MC-limited face states of a cell with neighbours um (below) and up (above) along one
-// direction: lo on its low face, hi on its high face.
+// direction: lo on its low face, hi on its high face. E_r of a face state is raised to
+// ef: a face state may reach a neighbour's value, and next to a cell at the floor
+// rounding can take it to zero, where the closure has no direction.
 template <typename T>
 __device__ __forceinline__ void mc_states(const T um[4], const T u[4], const T up[4], T lo[4],
-                                          T hi[4]) {
+                                          T hi[4], T ef) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const T hs = mc_half_slope(u[q] - um[q], up[q] - u[q]);
     lo[q] = u[q] - hs;
     hi[q] = u[q] + hs;
   }
+  lo[0] = vmax(lo[0], ef);
+  hi[0] = vmax(hi[0], ef);
 }
 
 // HLL flux through the face between cells b and c of the row a, b, c, d along direction
 // dir, from the MC-limited states of b (high side) and c (low side).
 template <typename T>
 __device__ __forceinline__ void face_flux4(const T a[4], const T b[4], const T cc[4], const T d[4],
-                                           int dir, T c, T ic, T chat, T f[4]) {
+                                           int dir, T c, T ic, T chat, T ef, T f[4]) {
   T lo[4], hi[4], bh[4], cl[4];
-  mc_states(a, b, cc, lo, bh);
-  mc_states(b, cc, d, cl, hi);
+  mc_states(a, b, cc, lo, bh, ef);
+  mc_states(b, cc, d, cl, hi, ef);
   hll(face_side(bh, dir, c, ic, chat), face_side(cl, dir, c, ic, chat), f);
 }
 
@@ -417,7 +421,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   const int z0 = bz * zc;
   const int z1 = min(z0 + zc, n2);
   const int zs = G.ps[0] * G.ps[1];
-  const T c = K.c, ic = K.inv_c, chat = K.chat;
+  const T c = K.c, ic = K.inv_c, chat = K.chat, ef = K.er_floor;
   // the ring of the LDS plane, loaded one plane ahead; the half-step arrays hold valid
   // values on [-2, n + 2) in every dimension
   int rpos[RP], rcol[RP];
@@ -472,7 +476,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
     // z: limited states of the own cell; the low z face pairs them with plane t-1
     {
       T mz[4], pz[4];
-      mc_states(Uzm, Uz0, Uzp, mz, pz);
+      mc_states(Uzm, Uz0, Uzp, mz, pz, ef);
       T fz[4] = {T(0), T(0), T(0), T(0)};
       if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, chat), fz);
       if (t > z0 && out_xy) {
@@ -512,7 +516,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         T b[4], d[4], lo[4], hi[4], bh[4];
         get4(sh.U[ty + 2][tx + 1], b);
         get4(sh.U[ty + 2][tx + 3], d);
-        mc_states(b, Uz0, d, lo, hi);
+        mc_states(b, Uz0, d, lo, hi, ef);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bh[q] = lane_from_left(hi[q], hi[q]);
         hll(face_side(bh, 0, c, ic, chat), face_side(lo, 0, c, ic, chat), fl);
@@ -522,7 +526,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[ty][tx + 2], a);
         get4(sh.U[ty + 1][tx + 2], b);
         get4(sh.U[ty + 3][tx + 2], d);
-        face_flux4(a, b, Uz0, d, 1, c, ic, chat, fb);
+        face_flux4(a, b, Uz0, d, 1, c, ic, chat, ef, fb);
       }
       put4(sh.fy[ty][tx], fb);
       // extra items on waves of different SIMDs (wave w runs on SIMD w mod 4)
@@ -535,7 +539,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[r + 2][c0 + 1], b);
         get4(sh.U[r + 2][c0 + 2], cc);
         get4(sh.U[r + 2][c0 + 3], d);
-        face_flux4(a, b, cc, d, 0, c, ic, chat, f);
+        face_flux4(a, b, cc, d, 0, c, ic, chat, ef, f);
         put4(sh.fxe[r][k], f);
       }
       if (ty == BY - 1) {
@@ -544,7 +548,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[BY][tx + 2], a);
         get4(sh.U[BY + 2][tx + 2], cc);
         get4(sh.U[BY + 3][tx + 2], d);
-        face_flux4(a, Uz0, cc, d, 1, c, ic, chat, f);
+        face_flux4(a, Uz0, cc, d, 1, c, ic, chat, ef, f);
         put4(sh.fy[BY][tx], f);
       }
       __syncthreads();

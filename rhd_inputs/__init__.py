@@ -46,6 +46,7 @@ def default_spec(**over):
         cv_t3=False,              # gas heat capacity c_v = cv_alpha T^3 (Marshak problem)
         cv_alpha=0.0,
         bvals=((0.0,) * 4,) * 6,  # (E_r, F_x, F_y, F_z) of each "fixed" face
+        kappa_law=None,           # (k0, T0, rho0, a, b): kappa = k0 (T/T0)^a (rho/rho0)^b
     )
     for k, v in over.items():
         if k not in spec:
@@ -409,3 +410,56 @@ def marshak_boundary(t, eps=1.0, nq=4000):
     right = (MARSHAK_EBG, 0.0, 0.0, 0.0)
     zero = (0.0, 0.0, 0.0, 0.0)
     return (left, right, zero, zero, zero, zero)
+
+
+# --------------------------------------------------------------------------
+# shadowing by a dense cloud (Sec. 4.2.1), cgs units
+# --------------------------------------------------------------------------
+
+C_CGS = 2.99792458e10          # cm / s
+A_RAD_CGS = 7.5657e-15         # erg cm^-3 K^-4
+R_GAS_CGS = 1.380649e-16 / 1.6735575e-24  # k_B / m_H (mean molecular weight 1)
+
+
+def shadow_problem(nx=280, ny=80, emission=False, precision="fp64", heat_capacity=1.0):
+    """The shadow test of Sec. 4.2.1: a 1 cm x 0.12 cm box of gas at rho0 = 1e-3 g/cm^3
+    holding an ellipsoidal cloud of rho1 = 1 (Eqs. radshadow:rho, radshadow:delta;
+    centre (0.5, 0), semi-axes 0.10 and 0.06), static, in radiative equilibrium at
+    T0 = 290 K; from t = 0 the left face holds a beam of temperature T1 = 6 T0 moving
+    right (E_r = a_R T1^4, F = c E_r x-hat); outflow on the right and top, reflection on
+    the bottom; opacity kappa = 100 (T_gas/T0)^-3.5 (rho/rho0) cm^2/g for absorption
+    and flux alike; chat = c. Without emission the source step is absorption only;
+    with it, the full exchange. Gas: gamma = 5/3, mean molecular weight 1 (heat
+    capacity scaled by heat_capacity: r_gas = heat_capacity k_B / m_H). theta = 1
+    (the paper's default): the cloud's absorption per step is ~10^2-10^5, where a
+    theta near 1/2 makes the damping factor negative."""
+    Lx, Ly = 1.0, 0.12
+    rho0, rho1, T0 = 1e-3, 1.0, 290.0
+    T1 = 6.0 * T0
+    spec = default_spec(nx=nx, ny=ny, dx=Lx / nx, dy=Ly / ny, gamma=5.0 / 3.0,
+                        c_light=C_CGS, a_rad=A_RAD_CGS, r_gas=R_GAS_CGS * heat_capacity, cfl=0.4,
+                        theta_E=1.0, theta_F=1.0, rad_only=True,
+                        exchange="full" if emission else "absorb_only",
+                        bc=("fixed", "outflow", "reflect", "outflow", "periodic", "periodic"),
+                        kappa_law=(100.0, T0, rho0, -3.5, 1.0), precision=precision,
+                        er_floor=1e-30, rho_floor=1e-12, p_floor=1e-30)
+    X, Y, _ = cell_centres(spec)
+    delta = 10.0 * (((X - 0.5) / 0.10) ** 2 + (Y / 0.06) ** 2 - 1.0)
+    rho = rho0 + (rho1 - rho0) / (1.0 + np.exp(np.minimum(delta, 700.0)))
+    Er0 = A_RAD_CGS * T0 ** 4
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=Er0, kP=1.0, kF=1.0)
+    st["rho"] = rho
+    st["E"] = rho * spec["r_gas"] * T0 / (spec["gamma"] - 1.0)
+    E1 = A_RAD_CGS * T1 ** 4
+    beam = (E1, C_CGS * E1, 0.0, 0.0)
+    zero = (0.0, 0.0, 0.0, 0.0)
+    spec["bvals"] = (beam, zero, zero, zero, zero, zero)
+    dt = spec["cfl"] * min(spec["dx"], spec["dy"]) / C_CGS
+    return dict(name=f"shadow_{nx}x{ny}_{'emission' if emission else 'absorption'}",
+                spec=spec, state=st, chat=C_CGS, dt=dt, nsub=1, T0=T0, T1=T1,
+                crossing=Lx / C_CGS)
+
+
+def radiation_temperature(Er):
+    """T_rad = (E_r / a_R)^(1/4) in cgs."""
+    return (np.asarray(Er) / A_RAD_CGS) ** 0.25
