@@ -37,7 +37,9 @@
  *    directly (no boundary refill between the stages);
  *  - after every radiation stage E_r is raised to er_floor and then F is scaled
  *    back to |F| = c E_r if it exceeds it, and E_r of every reconstructed face state
- *    is raised to er_floor before its closure; after every gas stage rho and P are
+ *    is raised to er_floor before its closure; E_r after the exchange is raised to
+ *    er_floor too (Eq. source:eradupdate can round to zero or below when K of
+ *    Eq. source:kappacond is large); after every gas stage rho and P are
  *    raised to their floors;
  *  - emission j adds (chat/c) j to dE_r/dt, so that div F = j in a steady state;
  *  - in ABSORB_ONLY mode E_r is damped with kappa_P by the same theta-form as F,
@@ -888,7 +890,10 @@ int orc_step(const orc_params *p, orc_fields *s, double dt_gas, double chat, int
       double x = orc_exchange_cell(rho, e, s->Er[a], s->kP[a], dt_gas, chat, p, &Er_new, &it,
                                    &th1, &bis);
       s->E[a] += x - e;
-      s->Er[a] = Er_new;
+      /* E_r from Eq. source:eradupdate is a difference of nearly equal energies when
+         the condition number K of Eq. source:kappacond is large, and can round to
+         zero or below; it is raised to the floor as after a radiation stage */
+      s->Er[a] = Er_new < p->er_floor ? p->er_floor : Er_new;
       if (cnt) {
         cnt->newton_iters += it;
         if (it > cnt->newton_max) cnt->newton_max = it;

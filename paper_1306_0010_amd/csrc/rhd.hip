@@ -521,6 +521,7 @@ rhdk::ExchConst exch_const(const rhd_t* h, double chat, double dt) {
   X.theta = p.theta_E;
   X.rtol = p.newton_rtol;
   X.eps_cv = (p.flags & RHD_GAS_CV_T3) ? 4.0 * p.a_rad / p.cv_alpha : 0.0;
+  X.er_floor = p.er_floor;
   X.maxit = p.newton_maxit;
   return X;
 }

@@ -212,6 +212,15 @@ __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float vdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double vdiv(double a, double b) { return a / b; }
 
+// Smallest normal number of each precision.
+template <typename T>
+__device__ __forceinline__ constexpr T min_normal() {
+  if constexpr (sizeof(T) == 4)
+    return T(1.17549435e-38f);
+  else
+    return T(2.2250738585072014e-308);
+}
+
 // Direction-independent part of the M1 closure of one state (E_r, F).
 //
 // With the reduced flux f = F/(c E) (norm clamped to 1) and s = sqrt(4 - 3 f^2), the
@@ -241,12 +250,24 @@ __device__ __forceinline__ M1State<T> m1_state(const T U[4], T inv_c, T chat) {
   m.f[1] = U[2] * icE;
   m.f[2] = U[3] * icE;
   T ff = m.f[0] * m.f[0] + m.f[1] * m.f[1] + m.f[2] * m.f[2];
-  if (ff > T(1)) {
-    const T r = rsqrt_(ff);
-    m.f[0] *= r;
-    m.f[1] *= r;
-    m.f[2] *= r;
+  if (!(ff <= T(1))) {
+    // f = F/|F|, taken from F itself: near E_r = 0 the product F/(c E_r) overflows,
+    // and a zero component of F times an infinite 1/(c E_r) is NaN (so is ff then).
+    // ff is then exactly 1, as the branch point of the closure at f = 1 needs. In FP32
+    // |F|^2 is kept normal for the hardware reciprocal square root; below that f falls
+    // short of unit length, and ff is taken from f.
+    const T n2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    T r;
+    if constexpr (sizeof(T) == 4)
+      r = rsqrt_(vmax(n2, min_normal<T>()));
+    else
+      r = rsqrt_(n2);
+    m.f[0] = U[1] * r;
+    m.f[1] = U[2] * r;
+    m.f[2] = U[3] * r;
     ff = T(1);
+    if constexpr (sizeof(T) == 4)
+      if (n2 < min_normal<T>()) ff = m.f[0] * m.f[0] + m.f[1] * m.f[1] + m.f[2] * m.f[2];
   }
   const T q = T(4) - T(3) * ff;  // s^2, in [1, 4]
   if constexpr (sizeof(T) == 4) {
@@ -309,12 +330,17 @@ __device__ __forceinline__ FaceSide<T> face_side(const T U[4], int d, T c, T inv
 
 // HLL flux of Eq. hyperbolic:hllflux2 with S_L = min(lambda_1(U_L), lambda_1(U_R)) and
 // S_R = max(lambda_3(U_L), lambda_3(U_R)); the central flux when both bounds vanish.
+// A bound difference below the smallest normal number counts as vanishing: its
+// reciprocal overflows to infinity while the products it multiplies underflow to zero
+// (0 * inf). Such bounds come only from beams with f = 1 parallel to the face (s = 1, a
+// zero radicand, a subnormal f_d), whose fluxes through the face are as small, so the
+// two fluxes differ by a negligible amount.
 template <typename T>
 __device__ __forceinline__ void hll(const FaceSide<T>& L, const FaceSide<T>& R, T flux[4]) {
   const T SLm = vmin(vmin(L.lmin, R.lmin), T(0));
   const T SRp = vmax(vmax(L.lmax, R.lmax), T(0));
   const T den = SRp - SLm;
-  if (den > T(0)) {
+  if (den >= min_normal<T>()) {
     const T id = rcp(den);
     const T pr = SRp * SLm;
 #pragma unroll
@@ -442,7 +468,7 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
     // reciprocal square root reads as zero (an infinite scale); from the smallest normal
     // up the scale is finite and still brings |F| to at most c E_r
     T m2 = Fm2;
-    if constexpr (sizeof(T) == 4) m2 = vmax(Fm2, 1.17549435e-38f);
+    if constexpr (sizeof(T) == 4) m2 = vmax(Fm2, min_normal<T>());
     const T scale = cE * rsqrt_(m2);
     Fn[0] *= scale;
     Fn[1] *= scale;
@@ -977,6 +1003,7 @@ struct ExchConst {
   double gm1, a_rad, r_gas;
   double theta, rtol;
   double eps_cv;  // 4 a_R / alpha when c_v = alpha T^3 (a_R T^4 = eps_cv e), else 0
+  double er_floor;
   int maxit;
 };
 
@@ -1081,7 +1108,10 @@ __device__ __forceinline__ void exchange_cell(const GasPtrs<T>& Ug, const RadPtr
   const double x = exchange_root(X, rho, e, double(Ur.E[a]), kP ? double(kP[a]) : kP_s, Er_new,
                                  it, th1, bis);
   Ug.E[a] = T(Et + (x - e));
-  Ur.E[a] = T(Er_new);
+  // E_r = (chat/c)(Ebar - x) loses K eps of its precision (Eq. source:kappacond) and can
+  // round to zero or below in a cell whose radiation is negligible beside its gas
+  // energy; it is raised to the floor as after a radiation stage
+  Ur.E[a] = T(Er_new < X.er_floor ? X.er_floor : Er_new);
   n_th1 += th1 ? 1u : 0u;
   n_bis += bis ? 1u : 0u;
   n_it += unsigned(it);

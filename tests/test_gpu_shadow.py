@@ -115,3 +115,86 @@ def test_opacity_law_on_tiled_kernels_matches_oracle(precision):
         s.sync()
         gpu = s.get_state()
     assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"law 3d {precision}")
+
+
+# Transverse flux of a beam below the smallest normal number of each precision.
+SUBNORMAL = {"fp64": 1e-315, "mixed": 1e-42}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["1d fused", "2d per-cell", "3d tiled"])
+def test_beam_with_subnormal_transverse_flux_stays_finite(case, precision):
+    """A beam at f = 1 whose flux across the faces of one direction is subnormal, with
+    random signs; in the shadow test's lit region FP64 develops such values after ~1900
+    steps at 280 x 80. The HLL bounds across those faces then differ by a subnormal
+    amount, whose reciprocal overflows; the flux is the central one there, as when the
+    bounds vanish (negligible against the oracle's, which divides). The 1D grid carries
+    the beam along y (a passive component) and the subnormal part along x, the only
+    active direction, on the one-workgroup path; 2D runs the per-cell kernels, 3D the
+    tiled ones."""
+    announce(f"subnormal transverse flux {case} {precision}")
+    n = {"1d fused": (64, 1, 1), "2d per-cell": (40, 24, 1), "3d tiled": (48, 16, 12)}[case]
+    spec = ri.default_spec(nx=n[0], ny=n[1], nz=n[2], dx=1.0 / n[0], dy=1.0 / n[1],
+                           dz=1.0 / n[2], c_light=1.0, rad_only=True, exchange="none",
+                           theta_F=1.0, bc="periodic", precision=precision)
+    st = ri.uniform_state(spec, Er=1.0, kP=0.0, kF=0.0)  # transparent: f stays 1
+    rng = np.random.default_rng(12)
+    tiny = SUBNORMAL[precision] * rng.choice([-1.0, 1.0], size=st["Er"].shape)
+    tiny *= rng.integers(1, 50, size=st["Er"].shape)
+    if case == "1d fused":
+        st["Fy"][:], st["Fx"][:] = 1.0, tiny
+    else:
+        st["Fx"][:], st["Fy"][:] = 1.0, tiny
+    dt = 0.3 * min(spec["dx"], spec["dy"] if n[1] > 1 else 1.0, spec["dz"] if n[2] > 1 else 1.0)
+    steps = 4
+    ref, _ = oracle.step(spec, st, dt, 1.0, 1, steps=steps)
+    with P.Solver(spec) as s:
+        if case == "3d tiled":
+            s.set_kernel_variant(P.RHD_KERNELS_TILED, 8 if precision == "fp64" else 16)
+        s.set_state(st)
+        s.run(np.full(steps, dt), np.ones(steps, dtype=np.int32), 1.0)
+        s.sync()
+        gpu, diag = s.get_state(), s.diagnostics()
+    assert diag["nonfinite"] == 0 and diag["steps"] == steps
+    for k in ri.FIELDS:
+        if gpu.get(k) is not None:
+            assert np.isfinite(gpu[k]).all(), k
+    assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"subnormal {case}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["1d fused", "2d per-cell", "3d tiled"])
+@pytest.mark.parametrize("Er", [1e-12, 1e-8])
+def test_exchange_that_rounds_the_radiation_away_is_floored(Er, case, precision):
+    """Gas at 1 K holding e ~ 1.2e8 erg/cm^3 beside a beam of E_r far below the spacing
+    of e (condition number K ~ 1e20, Eq. source:kappacond): the exchange's E_r rounds to
+    zero or below and is raised to the floor, as in the oracle; a zero E_r left in place
+    made the closure of the beam 0 * inf. Every path (the one-workgroup 1D path, the
+    per-cell and the tiled kernels) ends at E_r = er_floor in every cell."""
+    announce(f"exchange floor {case} {precision} Er={Er}")
+    n = {"1d fused": (64, 1, 1), "2d per-cell": (40, 24, 1), "3d tiled": (48, 16, 12)}[case]
+    spec = ri.default_spec(nx=n[0], ny=n[1], nz=n[2], dx=0.1, dy=0.1, dz=0.1, c_light=ri.C_CGS,
+                           a_rad=ri.A_RAD_CGS, r_gas=ri.R_GAS_CGS, gamma=5.0 / 3.0, rad_only=True,
+                           exchange="full", theta_E=1.0, bc="periodic", er_floor=1e-30,
+                           precision=precision)
+    c = spec["c_light"]
+    st = ri.uniform_state(spec, rho=1.0, P=ri.R_GAS_CGS, Er=Er, F=(c * Er, 0.0, 0.0),
+                          kP=1.0, kF=1.0)
+    floor = float(np.float32(spec["er_floor"])) if precision == "mixed" else spec["er_floor"]
+    dt = 1e-12
+    nsubs = np.array([0, 1, 1], dtype=np.int32)  # the exchange alone, then whole steps
+    ref, _ = oracle.step(spec, st, dt, c, 0)
+    ref, _ = oracle.step(spec, ref, dt, c, 1, steps=2)
+    with P.Solver(spec) as s:
+        if case == "3d tiled":
+            s.set_kernel_variant(P.RHD_KERNELS_TILED, 8 if precision == "fp64" else 16)
+        s.set_state(st)
+        s.run(np.full(1, dt), nsubs[:1], c)
+        s.sync()
+        assert np.all(s.get_state()["Er"] == floor)
+        s.run(np.full(2, dt), nsubs[1:], c)
+        s.sync()
+        gpu, diag = s.get_state(), s.diagnostics()
+    assert diag["nonfinite"] == 0
+    assert np.all(ref["Er"] == spec["er_floor"]) and np.all(gpu["Er"] == floor)
+    assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"exchange floor {case}")

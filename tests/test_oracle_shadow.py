@@ -1,7 +1,8 @@
 """Oracle pins for the opacity law kappa(T_gas, rho) and the shadow test of Sec. 4.2.1:
 the law against the relaxation ODE it defines, the M1 shadow behind a dense cloud
-(sharp without emission, softer with it, as the paper finds), and the floor on
-reconstructed face states that keeps cells next to the floor finite."""
+(sharp without emission, softer with it, as the paper finds), the floor on
+reconstructed face states that keeps cells next to the floor finite, and the floor on
+E_r after an ill-conditioned exchange."""
 import math
 
 import numpy as np
@@ -112,3 +113,41 @@ def test_face_states_next_to_the_floor_stay_finite():
     assert cnt["rad_efloor"] > 0
     for k in ("Er", "Fx", "Fy"):
         assert np.all(np.isfinite(st[k])), k
+
+
+def cold_gas_spec(nx=8, ny=6):
+    return ri.default_spec(nx=nx, ny=ny, dx=0.1, dy=0.1, c_light=ri.C_CGS, a_rad=ri.A_RAD_CGS,
+                           r_gas=ri.R_GAS_CGS, gamma=5.0 / 3.0, rad_only=True, exchange="full",
+                           theta_E=1.0, bc="periodic", er_floor=1e-30)
+
+
+# gas at T = 1 K, rho = 1 in cgs: e = 1.24e8 erg/cm^3, whose spacing is 1.5e-8
+COLD_E = ri.R_GAS_CGS * 1.0 / (2.0 / 3.0)
+
+
+@pytest.mark.parametrize("Er", [1e-12, 1e-8])
+def test_exchange_that_rounds_the_radiation_away_is_floored(Er):
+    """Eq. source:kappacond: E_r from Eq. source:eradupdate carries a relative error of
+    about K eps, with K = e / ((c/chat) E_r) ~ 1e20 here, so it rounds to one spacing of
+    e below zero (E_r = 1e-12) or to exactly zero (1e-8). After the exchange E_r is
+    raised to the floor (a step without radiation subcycles shows the exchange alone);
+    the stage that follows keeps it there, with |F| <= c E_r, and every value stays
+    finite; the combined energy e + (c/chat) E_r changes by less than one spacing of e."""
+    spec = cold_gas_spec()
+    c = spec["c_light"]
+    st = ri.uniform_state(spec, rho=1.0, P=ri.R_GAS_CGS, Er=Er, F=(c * Er, 0.0, 0.0),
+                          kP=1.0, kF=1.0)
+    e0 = float(st["E"][0, 0, 0])
+    assert e0 == pytest.approx(COLD_E, rel=1e-15)
+    x, Er_raw, *_ = oracle.exchange_cell(spec, 1.0, e0, Er, 1.0, 1e-12, c)
+    assert Er_raw <= 0.0
+    ex, _ = oracle.step(spec, st, 1e-12, c, 0)
+    assert np.all(ex["Er"] == spec["er_floor"])
+    assert np.all(ex["E"] == x)
+    out, cnt = oracle.step(spec, st, 1e-12, c, 1)
+    for k in ("Er", "Fx", "Fy", "E"):
+        assert np.all(np.isfinite(out[k])), k
+    assert np.all(out["Er"] == spec["er_floor"])
+    assert np.all(np.abs(out["Fx"]) <= c * out["Er"] * (1 + 1e-15))
+    total = lambda s: s["E"] + s["Er"]  # chat = c
+    assert np.all(np.abs(total(out) - total(st)) <= 2 * np.spacing(COLD_E))
