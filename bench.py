@@ -232,6 +232,52 @@ def cpu_baseline_marshak(ri, max_zone_updates=5e6):
     return {"kind": "oracle", "cores": 1, "rows": rows}
 
 
+def shadow_timing(P, ri, stream, crossings=10.0):
+    """The shadow test of Sec. 4.2.1 at the paper's 280 x 80 cells for 10 horizontal
+    light-crossing times, without and with emission, in mixed precision and FP64, in one
+    rhd_run call each; the radiation temperature at the right boundary, behind the
+    cloud (y < 0.045) and above it (y > 0.09), shows the shadow."""
+    import numpy as np
+    import torch
+    rows = []
+    for emission, precision in ((False, "mixed"), (True, "mixed"), (False, "fp64"),
+                                (True, "fp64")):
+        pb = ri.shadow_problem(280, 80, emission=emission, precision=precision)
+        spec, dt, chat = pb["spec"], pb["dt"], pb["chat"]
+        steps = int(math.ceil(crossings * pb["crossing"] / dt))
+        with P.Solver(spec, stream=stream.cuda_stream) as s:
+            s.set_state(pb["state"])
+            s.set_boundary(spec["bvals"])
+            s.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run(np.full(steps, dt), np.ones(steps, dtype=np.int32), chat)
+            s.sync()
+            el = time.perf_counter() - t0
+            st, diag = s.get_state(), s.diagnostics()
+        y = (np.arange(spec["ny"]) + 0.5) * spec["dy"]
+        Tr = ri.radiation_temperature(st["Er"][0, :, -1]) / pb["T1"]
+        cells = spec["nx"] * spec["ny"]
+        rows.append({"workload": pb["name"], "precision": precision, "steps": steps,
+                     "seconds": el,
+                     "us_per_step": 1e6 * el / steps, "zone_updates_per_s": cells * steps / el,
+                     "T_rad_over_T1_shadow": float(np.mean(Tr[y < 0.045])),
+                     "T_rad_over_T1_lit": float(np.mean(Tr[y > 0.09])),
+                     "nonfinite": diag["nonfinite"]})
+    return {"grid": [280, 80], "crossings": crossings, "rows": rows}
+
+
+def cpu_baseline_shadow(ri, steps=2000):
+    """The FP64 oracle on the shadow problem at 56 x 16 cells (a bounded sample)."""
+    import oracle
+    pb = ri.shadow_problem(56, 16, emission=True)
+    t0 = time.perf_counter()
+    oracle.step(pb["spec"], pb["state"], pb["dt"], pb["chat"], 1, steps=steps)
+    el = time.perf_counter() - t0
+    return {"kind": "oracle", "cores": 1, "sample": f"56x16 cells, {steps} steps, with emission",
+            "zone_updates_per_s": 56 * 16 * steps / el, "seconds": el}
+
+
 def cpu_baseline(pb, nz_slab=32):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the same
     input: the first nz_slab z-planes of the 128^3 box as a periodic slab, one full
@@ -399,7 +445,8 @@ def main():
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-marshak", action="store_true",
-                    help="skip the Marshak-wave timing (the paper's own 1D benchmark)")
+                    help="skip the Marshak-wave and shadow-test timings (the paper's own 1D "
+                         "benchmark and its 2D shadow test)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
@@ -542,12 +589,15 @@ def main():
     if not args.no_marshak:
         out["marshak"] = marshak_timing(P, ri, stream)
         progress("Marshak wave timed")
+        out["shadow"] = shadow_timing(P, ri, stream)
+        progress("shadow test timed")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
         progress("oracle timed on the host")
         if not args.no_marshak:
             out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
-            progress("oracle timed on the Marshak wave")
+            out["shadow"]["cpu_baseline"] = cpu_baseline_shadow(ri)
+            progress("oracle timed on the Marshak wave and the shadow test")
     print(json.dumps(out), flush=True)
 
 
