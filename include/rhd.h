@@ -79,6 +79,11 @@ extern "C" {
                                               a_R T^4 = (4 a_R / cv_alpha) e, so the exchange
                                               (theta-scheme of Eq. source:energyupdate) is
                                               linear in e. Needs RHD_RAD_ONLY, ideal gas   */
+#define RHD_CLOSURE_P1          (1u << 8)  /* Eddington (P1) closure instead of M1: T = I/3
+                                              and the fixed wave speeds +-chat/sqrt(3) in
+                                              every face flux (Sec. 2.3; the comparison run
+                                              of Sec. 4.4.2). The flux clamp |F| <= c E_r
+                                              after each stage still applies              */
 
 typedef struct {
   int nx, ny, nz;               /* interior cells; a dimension with n = 1 is inactive      */

@@ -31,6 +31,7 @@ RAD_ONLY = 1 << 4
 PRECISION_MIXED = 1 << 5
 GAS_CV_T3 = 1 << 6
 OPACITY_LAW = 1 << 7
+CLOSURE_P1 = 1 << 8
 
 STATE_FIELDS = ("rho", "mx", "my", "mz", "E", "Er", "Fx", "Fy", "Fz")
 
@@ -97,6 +98,8 @@ def lib():
                                    ctypes.c_int, dp, dp]
         L.orc_rad_hll_flux.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        dp]
+        L.orc_p1_hll_flux.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      dp]
         L.orc_gas_flux.argtypes = [dp, ctypes.c_int, ctypes.POINTER(Params), dp]
         L.orc_gas_riemann.argtypes = [dp, dp, ctypes.c_int, ctypes.POINTER(Params), dp]
         L.orc_exchange_cell.argtypes = [ctypes.c_double] * 6 + [
@@ -142,6 +145,10 @@ def make_params(spec):
         flags |= OPACITY_LAW
         for q in range(5):
             p.kappa_law[q] = float(spec["kappa_law"][q])
+    if spec["closure"] == "p1":
+        flags |= CLOSURE_P1
+    elif spec["closure"] != "m1":
+        raise ValueError(f"unknown closure {spec['closure']!r}")
     p.flags = flags
     p.cv_alpha = float(spec["cv_alpha"])
     for f in range(6):
@@ -264,6 +271,14 @@ def rad_hll_flux(UL, UR, d, c, chat):
     b = (ctypes.c_double * 4)(*[float(x) for x in UR])
     out = (ctypes.c_double * 4)()
     lib().orc_rad_hll_flux(a, b, int(d), float(c), float(chat), out)
+    return np.array(list(out))
+
+
+def p1_hll_flux(UL, UR, d, c, chat):
+    a = (ctypes.c_double * 4)(*[float(x) for x in UL])
+    b = (ctypes.c_double * 4)(*[float(x) for x in UR])
+    out = (ctypes.c_double * 4)()
+    lib().orc_p1_hll_flux(a, b, int(d), float(c), float(chat), out)
     return np.array(list(out))
 
 

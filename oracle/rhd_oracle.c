@@ -294,6 +294,35 @@ void orc_rad_hll_flux(const double UL[4], const double UR[4], int d, double c,
   }
 }
 
+/*
+ * HLL flux of the Eddington (P1) closure (Sec. 2.3: T proportional to I, so T = I/3
+ * and P = E_r/3 I whatever F is). The wave speeds of that system are the f -> 0 limits
+ * lambda_{1,3} = -+chat/sqrt(3) of Sec. 2.4 for every state; they enter
+ * Eq. hyperbolic:hllflux2 as S_L and S_R.
+ */
+void orc_p1_hll_flux(const double UL[4], const double UR[4], int d, double c, double chat,
+                     double flux[4]) {
+  const double SL = -chat / sqrt(3.0), SR = chat / sqrt(3.0);
+  double PhiL[4], PhiR[4];
+  PhiL[0] = chat * UL[1 + d] / c;
+  PhiR[0] = chat * UR[1 + d] / c;
+  for (int e = 0; e < 3; ++e) {
+    PhiL[1 + e] = e == d ? chat * c * UL[0] / 3.0 : 0.0;
+    PhiR[1 + e] = e == d ? chat * c * UR[0] / 3.0 : 0.0;
+  }
+  for (int q = 0; q < 4; ++q)
+    flux[q] = (SR * PhiL[q] - SL * PhiR[q] + SR * SL * (UR[q] - UL[q])) / (SR - SL);
+}
+
+/* The face flux of the closure the flags choose. */
+static void face_flux(const orc_params *p, const double UL[4], const double UR[4], int d,
+                      double chat, double flux[4]) {
+  if (p->flags & ORC_CLOSURE_P1)
+    orc_p1_hll_flux(UL, UR, d, p->c_light, chat, flux);
+  else
+    orc_rad_hll_flux(UL, UR, d, p->c_light, chat, flux);
+}
+
 /* ------------------------------------------------------------------------- */
 /* piecewise-linear reconstruction                                            */
 /* ------------------------------------------------------------------------- */
@@ -363,8 +392,8 @@ static void rad_stage(const orc_params *p, const pgrid *G, double chat, double h
             gather4(Uin, am1, Um);
             gather4(Uin, a0, U0);
             gather4(Uin, ap1, Up);
-            orc_rad_hll_flux(Um, U0, d, c, chat, fl);
-            orc_rad_hll_flux(U0, Up, d, c, chat, fr);
+            face_flux(p, Um, U0, d, chat, fl);
+            face_flux(p, U0, Up, d, chat, fr);
           } else {
             long am2 = at(G, i - 2 * off[0], j - 2 * off[1], k - 2 * off[2]);
             long ap2 = at(G, i + 2 * off[0], j + 2 * off[1], k + 2 * off[2]);
@@ -394,8 +423,8 @@ static void rad_stage(const orc_params *p, const pgrid *G, double chat, double h
             Rm[0] = Rm[0] > p->er_floor ? Rm[0] : p->er_floor;
             Lp[0] = Lp[0] > p->er_floor ? Lp[0] : p->er_floor;
             Rp[0] = Rp[0] > p->er_floor ? Rp[0] : p->er_floor;
-            orc_rad_hll_flux(Lm, Rm, d, c, chat, fl);
-            orc_rad_hll_flux(Lp, Rp, d, c, chat, fr);
+            face_flux(p, Lm, Rm, d, chat, fl);
+            face_flux(p, Lp, Rp, d, chat, fr);
           }
           double w = cell_width(p, d);
           for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) / w;

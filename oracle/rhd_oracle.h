@@ -37,6 +37,7 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2, ORC_BC_FIXED
 #define ORC_PRECISION_MIXED   (1u << 5)   /* ignored by the oracle (always FP64)      */
 #define ORC_GAS_CV_T3         (1u << 6)   /* heat capacity c_v = cv_alpha T^3, so that
                                              a_R T^4 = (4 a_R / cv_alpha) e            */
+#define ORC_CLOSURE_P1        (1u << 8)   /* Eddington closure T = I/3, speeds -+chat/sqrt 3 */
 #define ORC_OPACITY_LAW       (1u << 7)   /* kappa_P = kappa_F = k0 (T/T0)^a (rho/rho0)^b
                                              from the gas state at the start of each
                                              step; kappa_law = {k0, T0, rho0, a, b}     */
@@ -84,6 +85,8 @@ void   orc_m1_eigen(double E, const double F[3], double c, double chat, int d,
                     double *l1, double *l3);
 void   orc_rad_hll_flux(const double UL[4], const double UR[4], int d, double c,
                         double chat, double flux[4]);
+void   orc_p1_hll_flux(const double UL[4], const double UR[4], int d, double c,
+                       double chat, double flux[4]);
 void   orc_gas_flux(const double W[5], int d, const orc_params *p, double flux[5]);
 void   orc_gas_riemann(const double WL[5], const double WR[5], int d,
                        const orc_params *p, double flux[5]);

@@ -41,6 +41,7 @@ RHD_RAD_ONLY = 1 << 4
 RHD_PRECISION_MIXED = 1 << 5
 RHD_GAS_CV_T3 = 1 << 6
 RHD_OPACITY_LAW = 1 << 7
+RHD_CLOSURE_P1 = 1 << 8
 RHD_KERNELS_PER_CELL = 0
 RHD_KERNELS_TILED = 1
 
@@ -528,6 +529,10 @@ def params_from_spec(spec):
         flags |= RHD_OPACITY_LAW
         for q in range(5):
             p.kappa_law[q] = float(spec["kappa_law"][q])
+    if spec.get("closure", "m1") == "p1":
+        flags |= RHD_CLOSURE_P1
+    elif spec.get("closure", "m1") != "m1":
+        raise ValueError(f"unknown closure {spec['closure']!r}")
     p.flags = flags
     p.cv_alpha = float(spec.get("cv_alpha", 0.0))
     return p

@@ -213,7 +213,7 @@ int validate(const rhd_params* p) {
     return fail(nullptr, RHD_EINVAL, "floors must be >= 0");
   if ((p->flags & RHD_EXCHANGE_MASK) == (3u << 1))
     return fail(nullptr, RHD_EINVAL, "unknown exchange mode");
-  if (p->flags & ~((1u << 8) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
+  if (p->flags & ~((1u << 9) - 1)) return fail(nullptr, RHD_EINVAL, "unknown flag bits");
   if (p->flags & RHD_OPACITY_LAW) {
     const double* L = p->kappa_law;
     if (!(L[0] >= 0.0) || !(L[1] > 0.0) || !(L[2] > 0.0) || !std::isfinite(L[0]) ||
@@ -410,6 +410,7 @@ rhdk::RadConst<T> rad_const(const rhd_t* h, double chat) {
   rhdk::RadConst<T> RK;
   RK.c = T(p.c_light);
   RK.inv_c = T(1.0 / p.c_light);
+  RK.fclo = (p.flags & RHD_CLOSURE_P1) ? T(0) : T(1.0 / p.c_light);
   RK.chat = T(chat);
   RK.inv_w[0] = G.act[0] ? T(1.0 / p.dx) : T(0);
   RK.inv_w[1] = G.act[1] ? T(1.0 / p.dy) : T(0);

@@ -74,6 +74,7 @@ struct GasView {
 template <typename T>
 struct RadConst {
   T c, inv_c, chat;
+  T fclo;      // 1/c, or 0 for the P1 closure (f is taken as 0 in the closure: T = I/3)
   T inv_w[3];
   T theta;
   T er_floor;
@@ -239,13 +240,13 @@ struct M1State {
 };
 
 template <typename T>
-__device__ __forceinline__ M1State<T> m1_state(const T U[4], T inv_c, T chat) {
+__device__ __forceinline__ M1State<T> m1_state(const T U[4], T fclo, T chat) {
   M1State<T> m;
   m.E = U[0];
   m.F[0] = U[1];
   m.F[1] = U[2];
   m.F[2] = U[3];
-  const T icE = inv_c * rcp(U[0]);
+  const T icE = fclo * rcp(U[0]);
   m.f[0] = U[1] * icE;
   m.f[1] = U[2] * icE;
   m.f[2] = U[3] * icE;
@@ -319,9 +320,10 @@ struct FaceSide {
 };
 
 template <typename T>
-__device__ __forceinline__ FaceSide<T> face_side(const T U[4], int d, T c, T inv_c, T chat) {
+__device__ __forceinline__ FaceSide<T> face_side(const T U[4], int d, T c, T inv_c, T fclo,
+                                                 T chat) {
   FaceSide<T> q;
-  const M1State<T> m = m1_state(U, inv_c, chat);
+  const M1State<T> m = m1_state(U, fclo, chat);
 #pragma unroll
   for (int k = 0; k < 4; ++k) q.U[k] = U[k];
   m1_dir(m, d, c, inv_c, chat, q.Phi, q.lmin, q.lmax);
@@ -353,8 +355,8 @@ __device__ __forceinline__ void hll(const FaceSide<T>& L, const FaceSide<T>& R, 
 
 template <typename T>
 __device__ __forceinline__ void rad_hll(const T UL[4], const T UR[4], int d, T c, T inv_c,
-                                        T chat, T flux[4]) {
-  hll(face_side(UL, d, c, inv_c, chat), face_side(UR, d, c, inv_c, chat), flux);
+                                        T fclo, T chat, T flux[4]) {
+  hll(face_side(UL, d, c, inv_c, fclo, chat), face_side(UR, d, c, inv_c, fclo, chat), flux);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,7 +567,7 @@ __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const Rad
   }
   T U0[4];
   load_rad_bc(Um, G, B, i, j, k, U0);
-  const M1State<T> m0 = m1_state(U0, K.inv_c, K.chat);
+  const M1State<T> m0 = m1_state(U0, K.fclo, K.chat);
   T div[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -578,8 +580,8 @@ __device__ __forceinline__ void rad_predict_cell(const RadPtrs<T>& Um, const Rad
     T Ul[4], Ur[4], fl[4], fr[4];
     load_rad_bc(Um, G, B, i - di, j - dj, k - dk, Ul);
     load_rad_bc(Um, G, B, i + di, j + dj, k + dk, Ur);
-    hll(face_side(Ul, d, K.c, K.inv_c, K.chat), own, fl);
-    hll(own, face_side(Ur, d, K.c, K.inv_c, K.chat), fr);
+    hll(face_side(Ul, d, K.c, K.inv_c, K.fclo, K.chat), own, fl);
+    hll(own, face_side(Ur, d, K.c, K.inv_c, K.fclo, K.chat), fr);
 #pragma unroll
     for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
   }
@@ -655,8 +657,8 @@ __device__ __forceinline__ void rad_correct_cell(const RadPtrs<T>& Um, const Rad
     Lp[0] = vmax(Lp[0], K.er_floor);
     Rp[0] = vmax(Rp[0], K.er_floor);
     T fl[4], fr[4];
-    rad_hll(Lm, Rm, d, K.c, K.inv_c, K.chat, fl);
-    rad_hll(Lp, Rp, d, K.c, K.inv_c, K.chat, fr);
+    rad_hll(Lm, Rm, d, K.c, K.inv_c, K.fclo, K.chat, fl);
+    rad_hll(Lp, Rp, d, K.c, K.inv_c, K.fclo, K.chat, fr);
 #pragma unroll
     for (int q = 0; q < 4; ++q) div[q] += (fr[q] - fl[q]) * K.inv_w[d];
   }

@@ -115,15 +115,6 @@ __device__ __forceinline__ FaceSide<T> side_dir(const M1State<T>& m, const T U[4
   return q;
 }
 
-// Closure data of the boundary-mapped cell (x, y, z) of U^m for faces normal to d.
-template <typename T>
-__device__ __forceinline__ FaceSide<T> side_at(const RadPtrs<T>& Um, const Geom& G, int x, int y,
-                                               int z, int d, T c, T inv_c, T chat) {
-  T U[4];
-  load_rad_mapped(Um, G, x, y, z, U);
-  return face_side(U, d, c, inv_c, chat);
-}
-
 // ---------------------------------------------------------------------------
 // predictor: first-order HLL fluxes of U^m, half step, on the interior plus two ghost
 // layers of a 3D grid
@@ -229,7 +220,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   const int hx = hrole == 3 ? (tx < BY ? x0 - 1 : min(x0 + TILE_BX, n0 + 2)) : xl;
   const int hy = hrole == 1 ? y0 - 1 : (hrole == 2 ? min(y0 + BY, n1 + 2) : min(y0 + hrow, n1 + 2));
   const bool need_v = K.beta != 0;
-  const T c = K.c, ic = K.inv_c, chat = K.chat;
+  const T c = K.c, ic = K.inv_c, fc = K.fclo, chat = K.chat;
 
   // loads run one plane ahead of their use: U^m of the own cell, the extra item's cell
   // and the gas data of the cell being updated
@@ -246,7 +237,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
     T U[4] = {Un[0], Un[1], Un[2], Un[3]};
     unflip_rad(U, nU);
     if (t < z1) load_rad_raw(Um, G, xl, yl, t + 1, Un, nU);
-    const M1State<T> m = m1_state(U, ic, chat);
+    const M1State<T> m = m1_state(U, fc, chat);
     // z face t-1/2, then plane t-1 is complete: its z faces are t-3/2 and t-1/2
     const FaceSide<T> fzs = side_dir(m, U, 2, c, ic, chat);
     T fz[4] = {T(0), T(0), T(0), T(0)};
@@ -284,7 +275,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       if (hrole) {
         T H[4] = {Hn[0], Hn[1], Hn[2], Hn[3]};
         unflip_rad(H, nH);
-        const FaceSide<T> hs = face_side(H, hrole == 3 ? 0 : 1, c, ic, chat);
+        const FaceSide<T> hs = face_side(H, hrole == 3 ? 0 : 1, c, ic, fc, chat);
         if (hrole == 1)
           sh.sy.put(0, tx, hs);
         else if (hrole == 2)
@@ -399,11 +390,11 @@ __device__ __forceinline__ void mc_states(const T um[4], const T u[4], const T u
 // dir, from the MC-limited states of b (high side) and c (low side).
 template <typename T>
 __device__ __forceinline__ void face_flux4(const T a[4], const T b[4], const T cc[4], const T d[4],
-                                           int dir, T c, T ic, T chat, T ef, T f[4]) {
+                                           int dir, T c, T ic, T fc, T chat, T ef, T f[4]) {
   T lo[4], hi[4], bh[4], cl[4];
   mc_states(a, b, cc, lo, bh, ef);
   mc_states(b, cc, d, cl, hi, ef);
-  hll(face_side(bh, dir, c, ic, chat), face_side(cl, dir, c, ic, chat), f);
+  hll(face_side(bh, dir, c, ic, fc, chat), face_side(cl, dir, c, ic, fc, chat), f);
 }
 
 template <typename T, int BY>
@@ -421,7 +412,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   const int z0 = bz * zc;
   const int z1 = min(z0 + zc, n2);
   const int zs = G.ps[0] * G.ps[1];
-  const T c = K.c, ic = K.inv_c, chat = K.chat, ef = K.er_floor;
+  const T c = K.c, ic = K.inv_c, fc = K.fclo, chat = K.chat, ef = K.er_floor;
   // the ring of the LDS plane, loaded one plane ahead; the half-step arrays hold valid
   // values on [-2, n + 2) in every dimension
   int rpos[RP], rcol[RP];
@@ -478,7 +469,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
       T mz[4], pz[4];
       mc_states(Uzm, Uz0, Uzp, mz, pz, ef);
       T fz[4] = {T(0), T(0), T(0), T(0)};
-      if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, chat), fz);
+      if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, fc, chat), fz);
       if (t > z0 && out_xy) {
         // plane t-1 is complete: its z faces are t-3/2 (fzprev) and t-1/2 (fz)
         T d[4];
@@ -504,7 +495,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         Uon[2] = Um.F[1][a];
         Uon[3] = Um.F[2][a];
       }
-      if (t < z1) zplus = face_side(pz, 2, c, ic, chat);
+      if (t < z1) zplus = face_side(pz, 2, c, ic, fc, chat);
 #pragma unroll
       for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     }
@@ -519,14 +510,14 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         mc_states(b, Uz0, d, lo, hi, ef);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bh[q] = lane_from_left(hi[q], hi[q]);
-        hll(face_side(bh, 0, c, ic, chat), face_side(lo, 0, c, ic, chat), fl);
+        hll(face_side(bh, 0, c, ic, fc, chat), face_side(lo, 0, c, ic, fc, chat), fl);
       }
       {
         T a[4], b[4], d[4];
         get4(sh.U[ty][tx + 2], a);
         get4(sh.U[ty + 1][tx + 2], b);
         get4(sh.U[ty + 3][tx + 2], d);
-        face_flux4(a, b, Uz0, d, 1, c, ic, chat, ef, fb);
+        face_flux4(a, b, Uz0, d, 1, c, ic, fc, chat, ef, fb);
       }
       put4(sh.fy[ty][tx], fb);
       // extra items on waves of different SIMDs (wave w runs on SIMD w mod 4)
@@ -539,7 +530,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[r + 2][c0 + 1], b);
         get4(sh.U[r + 2][c0 + 2], cc);
         get4(sh.U[r + 2][c0 + 3], d);
-        face_flux4(a, b, cc, d, 0, c, ic, chat, ef, f);
+        face_flux4(a, b, cc, d, 0, c, ic, fc, chat, ef, f);
         put4(sh.fxe[r][k], f);
       }
       if (ty == BY - 1) {
@@ -548,7 +539,7 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         get4(sh.U[BY][tx + 2], a);
         get4(sh.U[BY + 2][tx + 2], cc);
         get4(sh.U[BY + 3][tx + 2], d);
-        face_flux4(a, Uz0, cc, d, 1, c, ic, chat, ef, f);
+        face_flux4(a, Uz0, cc, d, 1, c, ic, fc, chat, ef, f);
         put4(sh.fy[BY][tx], f);
       }
       __syncthreads();

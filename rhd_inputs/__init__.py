@@ -47,6 +47,7 @@ def default_spec(**over):
         cv_alpha=0.0,
         bvals=((0.0,) * 4,) * 6,  # (E_r, F_x, F_y, F_z) of each "fixed" face
         kappa_law=None,           # (k0, T0, rho0, a, b): kappa = k0 (T/T0)^a (rho/rho0)^b
+        closure="m1",             # "m1" | "p1" (Eddington: T = I/3, speeds -+chat/sqrt(3))
     )
     for k, v in over.items():
         if k not in spec:

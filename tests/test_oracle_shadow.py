@@ -91,9 +91,11 @@ def test_m1_casts_a_sharp_shadow_without_emission(shadows):
 
 
 def test_emission_softens_the_shadow(shadows):
-    """With thermal emission the heated cloud re-radiates into its shadow, so the shadow
-    is brighter and less sharp than without emission, as the paper finds, yet still
-    darker than the lit region."""
+    """With thermal emission the exchange, split from transport, gives back as
+    isotropic radiation the beam energy the cloud's surface cells take up during a step
+    (the paper puts the softer shadow down to this operator-split implicit solver), so
+    the shadow is brighter and less sharp than without emission, yet still darker than
+    the lit region."""
     pb0, st0, y, _ = shadows[False]
     pb1, st1, _, cnt = shadows[True]
     T0 = ri.radiation_temperature(st0["Er"][0, :, -1]) / pb0["T1"]
