@@ -232,6 +232,68 @@ def cpu_baseline_marshak(ri, max_zone_updates=5e6):
     return {"kind": "oracle", "cores": 1, "rows": rows}
 
 
+def pulse_timing(P, ri, stream, n=512):
+    """The advection of a radiation pulse (Sec. 4.2.5) at the paper's 512 cells to
+    t = 2w/v, in FP64: the advected and the static run, with and without the O(beta tau)
+    terms, each gas step at the CFL step the GPU suggests with its subcycles. Reports
+    time per run and per gas step, and the largest relative differences of density and
+    gas temperature between the advected and the static run (the paper's measure)."""
+    import numpy as np
+    import torch
+    rows, finals = [], {}
+    for beta_tau in (True, False):
+        for advected in (True, False):
+            pb = ri.pulse_problem(n, advected=advected, beta_tau=beta_tau)
+            spec, chat = pb["spec"], pb["chat"]
+            with P.Solver(spec, stream=stream.cuda_stream) as s:
+                s.set_state(pb["state"])
+                s.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t, steps, subs = 0.0, 0, 0
+                while t < pb["t_end"] * (1.0 - 1e-12):
+                    dt, ns = s.suggest_dt(chat)
+                    dt = min(dt, pb["t_end"] - t)
+                    s.step(dt, chat, ns)
+                    t += dt
+                    steps += 1
+                    subs += ns
+                s.sync()
+                el = time.perf_counter() - t0
+                st, diag = s.get_state(), s.diagnostics()
+            finals[(beta_tau, advected)] = (pb, st)
+            rows.append({"workload": pb["name"], "gas_steps": steps, "subcycles": subs,
+                         "seconds": el, "us_per_gas_step": 1e6 * el / steps,
+                         "zone_subcycles_per_s": n * subs / el, "nonfinite": diag["nonfinite"]})
+    errors = {}
+    for beta_tau in (True, False):
+        (pa, sa), (ps, ss) = finals[(beta_tau, True)], finals[(beta_tau, False)]
+        Ta = ri.gas_temperature(pa["spec"], sa)[0, 0]
+        Ts = ri.gas_temperature(ps["spec"], ss)[0, 0]
+        key = "with_beta_tau" if beta_tau else "without_beta_tau"
+        errors[key] = {"rho": float(np.max(np.abs(sa["rho"][0, 0] / ss["rho"][0, 0] - 1.0))),
+                       "T_gas": float(np.max(np.abs(Ta / Ts - 1.0)))}
+    return {"cells": n, "precision": "fp64", "rows": rows, "max_rel_error": errors,
+            "paper_bounds": {"with_beta_tau": 0.066, "without_beta_tau": 0.077}}
+
+
+def cpu_baseline_pulse(ri, n=512, gas_steps=100):
+    """The FP64 oracle on the first gas steps of the advected pulse (a bounded sample)."""
+    import oracle
+    pb = ri.pulse_problem(n, advected=True, beta_tau=True)
+    spec, st, chat = pb["spec"], pb["state"], pb["chat"]
+    subs = 0
+    t0 = time.perf_counter()
+    for _ in range(gas_steps):
+        dt, ns, _ = oracle.suggest_dt(spec, st, chat)
+        st, _ = oracle.step(spec, st, dt, chat, ns)
+        subs += ns
+    el = time.perf_counter() - t0
+    return {"kind": "oracle", "cores": 1,
+            "sample": f"{n} cells, the first {gas_steps} gas steps ({subs} subcycles)",
+            "zone_subcycles_per_s": n * subs / el, "seconds": el}
+
+
 def shadow_timing(P, ri, stream, crossings=10.0):
     """The shadow test of Sec. 4.2.1 at the paper's 280 x 80 cells for 10 horizontal
     light-crossing times, without and with emission, in mixed precision and FP64, in one
@@ -445,8 +507,8 @@ def main():
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-marshak", action="store_true",
-                    help="skip the Marshak-wave and shadow-test timings (the paper's own 1D "
-                         "benchmark and its 2D shadow test)")
+                    help="skip the Marshak-wave, shadow-test and pulse-advection timings (the "
+                         "paper's own 1D benchmark, its 2D shadow test and its O(beta tau) test)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
@@ -591,13 +653,16 @@ def main():
         progress("Marshak wave timed")
         out["shadow"] = shadow_timing(P, ri, stream)
         progress("shadow test timed")
+        out["pulse"] = pulse_timing(P, ri, stream)
+        progress("pulse advection timed")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
         progress("oracle timed on the host")
         if not args.no_marshak:
             out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
             out["shadow"]["cpu_baseline"] = cpu_baseline_shadow(ri)
-            progress("oracle timed on the Marshak wave and the shadow test")
+            out["pulse"]["cpu_baseline"] = cpu_baseline_pulse(ri)
+            progress("oracle timed on the Marshak wave, the shadow test and the pulse")
     print(json.dumps(out), flush=True)
 
 

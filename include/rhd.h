@@ -69,7 +69,11 @@ extern "C" {
                                               (Eq. m1:simplifiedsource and S_e)            */
 #define RHD_RAD_ONLY            (1u << 4)  /* gas frozen: no gas transport, no correction  */
 #define RHD_PRECISION_MIXED     (1u << 5)  /* FP32 storage and stencils, FP64 exchange and
-                                              ledger; without it everything is FP64        */
+                                              ledger; without it everything is FP64. The
+                                              face fluxes form chat^2 c E_r in FP32: state
+                                              the problem in units where that stays well
+                                              below 3e38 (cgs values of dense, hot gas can
+                                              overflow it)                                 */
 #define RHD_OPACITY_LAW         (1u << 7)  /* kappa_P = kappa_F = k0 (T_gas/T0)^a (rho/rho0)^b
                                               (Sec. 4.2.1), kappa_law = {k0, T0, rho0, a, b},
                                               from the gas state at the start of each gas

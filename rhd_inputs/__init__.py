@@ -464,3 +464,65 @@ def shadow_problem(nx=280, ny=80, emission=False, precision="fp64", heat_capacit
 def radiation_temperature(Er):
     """T_rad = (E_r / a_R)^(1/4) in cgs."""
     return (np.asarray(Er) / A_RAD_CGS) ** 0.25
+
+
+def pulse_problem(n=512, advected=True, beta_tau=True, precision="fp64", units="code"):
+    """Advection of a radiation pulse (Sec. 4.2.5): a periodic slab x/w in
+    [-21.25, 21.25] with w = 20 cm, rho0 = 25 g/cm^3, T0 = 1.1e7 K, mean particle mass
+    1.67e-24 g, kappa_P = kappa_F = 0.4 cm^2/g, gamma = 5/3, chat = 100 a0 with
+    a0 = sqrt(gamma k_B T0 / mu). The gas temperature is T0 (1 + exp(-x^2/(2 w^2))) and
+    the density follows from pressure equilibrium with E_r = a_R T^4 (Eq. radpulse:rho,
+    with P0 = a_R T0^4 / (rho0 a0^2)); F = 0. The advected run moves the gas at
+    v = 3e6 cm/s and starts the pulse 2w to the left, so that after t = 2w/v both runs
+    centre it at x = 0; the unadvected run is the reference. theta = 0.51 (the paper's
+    default for its tests).
+
+    units="cgs" gives the problem as stated; units="code" (the default) the same problem
+    in units of w, w/a0, rho0, T0 and rho0 a0^2 (so a_R = P0, r_gas = 1/gamma,
+    kappa = rho0 kappa0 w = tau0, c = c/a0), whose values fit FP32: in cgs the fluxes
+    chat c E_r reach 1e34 and their products with the wave speeds overflow FP32."""
+    w, rho0, T0, mu, kappa0, v0 = 20.0, 25.0, 1.1e7, 1.67e-24, 0.4, 3e6
+    gamma = 5.0 / 3.0
+    r_cgs = 1.380649e-16 / mu
+    a0 = math.sqrt(gamma * r_cgs * T0)
+    P0 = A_RAD_CGS * T0 ** 4 / (rho0 * a0 ** 2)
+    if units == "cgs":
+        Lu, Du, Tu, Vu = 1.0, 1.0, 1.0, 1.0  # length, density, temperature, velocity units
+    elif units == "code":
+        Lu, Du, Tu, Vu = w, rho0, T0, a0
+    else:
+        raise ValueError(f"unknown units {units!r}")
+    Eu = Du * Vu ** 2  # energy density unit
+    a_rad = A_RAD_CGS * Tu ** 4 / Eu
+    r_gas = r_cgs * Tu / Vu ** 2
+    kappa = kappa0 * Du * Lu
+    L = 42.5 * w / Lu
+    spec = default_spec(nx=n, dx=L / n, gamma=gamma, c_light=C_CGS / Vu, a_rad=a_rad,
+                        r_gas=r_gas, cfl=0.4, theta_E=0.51, theta_F=0.51, exchange="full",
+                        beta_tau=beta_tau, bc="periodic", precision=precision,
+                        er_floor=1e-30 / Eu, rho_floor=1e-12 / Du, p_floor=1e-30 / Eu)
+    x = -0.5 * L + (np.arange(n) + 0.5) * spec["dx"]
+    v = (v0 if advected else 0.0) / Vu
+    t_end = 2.0 * w / v0 * Vu / Lu
+    xc = -v * t_end  # start 2w to the left when advected
+    d = (x - xc + 0.5 * L) % L - 0.5 * L  # periodic distance to the pulse centre
+    T = (T0 / Tu) * (1.0 + np.exp(-d ** 2 / (2.0 * (w / Lu) ** 2)))
+    Tr = T * Tu / T0
+    rho = (rho0 / Du) * (1.0 / Tr + gamma * P0 / 3.0 * (1.0 / Tr - Tr ** 3))
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=kappa, kF=kappa)
+    st["rho"][0, 0, :] = rho
+    st["mx"][0, 0, :] = rho * v
+    st["E"][0, 0, :] = rho * r_gas * T / (gamma - 1.0) + 0.5 * rho * v * v
+    st["Er"][0, 0, :] = a_rad * T ** 4
+    kind = ("advected" if advected else "static") + ("_betatau" if beta_tau else "")
+    return dict(name=f"pulse_{n}_{kind}", spec=spec, state=st, chat=100.0 * a0 / Vu,
+                t_end=t_end, x=x, w=w / Lu, T0=T0 / Tu, rho0=rho0 / Du, v=v, a0=a0 / Vu,
+                P0=P0, tau0=rho0 * kappa0 * w, units=units)
+
+
+def gas_temperature(spec, st):
+    """T = (gamma - 1)(E - rho v^2/2) / (rho r_gas)."""
+    rho = np.asarray(st["rho"])
+    ke = 0.5 * (np.asarray(st["mx"]) ** 2 + np.asarray(st["my"]) ** 2
+                + np.asarray(st["mz"]) ** 2) / rho
+    return (spec["gamma"] - 1.0) * (np.asarray(st["E"]) - ke) / (rho * spec["r_gas"])
