@@ -106,6 +106,7 @@ struct rhd {
   long long bytes = 0;
   bool in_batch = false;
   int variant = RHD_KERNELS_TILED;
+  bool tile_ok = true;         // every array the tiled radiation kernels touch holds <= 4 GiB
   int tile_rows = 8;
   int zchunk = 8;
   int fixed_mask = 0;          // bit f: face f is RHD_BC_FIXED (of an active dimension)
@@ -433,7 +434,7 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
   const double hr = dt / nsub;
   const bool three_d = G.act[0] && G.act[1] && G.act[2];
   // fixed faces run the per-cell kernels, which read their states
-  if (three_d && h->variant == RHD_KERNELS_TILED && !h->fixed_mask) {
+  if (three_d && h->variant == RHD_KERNELS_TILED && !h->fixed_mask && h->tile_ok) {
     for (int m = 0; m < nsub; ++m) {
       int rc = launch_tiled<T>(h, rad, rh, view, RK, T(0.5 * hr), T(hr));
       if (rc) return rc;
@@ -1031,6 +1032,10 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
   footprint(p, &N, &NP);
   h->N = int(N);
   h->NP = int(NP);
+  // the tiled radiation kernels address with 32-bit byte offsets; the padded half-step
+  // arrays are the largest they touch
+  h->tile_ok = (unsigned long long)NP * (unsigned long long)h->esize <= (1ull << 32);
+  if (!h->tile_ok) h->variant = RHD_KERNELS_PER_CELL;
   h->dxmin = min_width(p);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
@@ -1086,6 +1091,7 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
       h->zchunk = g_tuned[t].zchunk;
     }
   }
+  if (!h->tile_ok) h->variant = RHD_KERNELS_PER_CELL;
   lock.unlock();
   hipLaunchKernelGGL(rhdk::k_reset_counters, dim3(1), dim3(64), 0, h->stream, h->b.ctr);
   if (hipMemsetAsync(h->b.ledger, 0, 5 * sizeof(double), h->stream) != hipSuccess ||
@@ -1320,6 +1326,9 @@ int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk) {
   const bool rows_ok = tile_rows == 4 || tile_rows == 8 || (tile_rows == 16 && h->mixed);
   if (!rows_ok) return fail(h, RHD_EINVAL, "tile rows must be 4, 8 (or 16 in mixed precision)");
   if (zchunk < 1) return fail(h, RHD_EINVAL, "zchunk must be >= 1");
+  if (variant == RHD_KERNELS_TILED && !h->tile_ok)
+    return fail(h, RHD_EINVAL, "the tiled kernels need arrays of at most 4 GiB; this grid's "
+                               "half-step arrays hold %lld bytes", (long long)h->NP * h->esize);
   h->variant = variant;
   h->tile_rows = tile_rows;
   h->zchunk = zchunk;
@@ -1334,9 +1343,9 @@ int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, i
     return fail(h, RHD_EINVAL, "chat and dt_rad must be > 0 and reps >= 1");
   if (chat * dt_rad > h->p.cfl * h->dxmin * (1.0 + 1e-12))
     return fail(h, RHD_ECFL, "chat dt_rad exceeds K0 dx");
-  // fixed faces always run the per-cell kernels: nothing to choose
+  // fixed faces, and grids too large for the tiled kernels, run the per-cell kernels
   int rc = RHD_OK;
-  if (h->fixed_mask)
+  if (h->fixed_mask || !h->tile_ok)
     h->variant = RHD_KERNELS_PER_CELL;
   else
     rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
@@ -1612,6 +1621,7 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   if (!h->have_state) return bfail(b, RHD_ESTATE, "member has no state");
   if (!(h->G.act[0] && h->G.act[1] && h->G.act[2])) return bfail(b, RHD_EINVAL, "members must be 3D");
   if (h->fixed_mask) return bfail(b, RHD_EINVAL, "members cannot have fixed faces");
+  if (!h->tile_ok) return bfail(b, RHD_EINVAL, "members' arrays must hold at most 4 GiB each");
   if (!(chat > 0.0)) return bfail(b, RHD_EINVAL, "chat must be > 0");
   for (rhd_t* m : b->members)
     if (m == h) return bfail(b, RHD_EINVAL, "handle is already a member");

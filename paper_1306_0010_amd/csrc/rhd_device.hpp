@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace rhdk {
 
@@ -81,6 +82,20 @@ struct RadConst {
   int beta;    // O(beta tau) terms on
   int absorb;  // absorption-only mode: E_r damped with kappa_P on each stage
 };
+
+// Element i of a device array. With O32 the address is the array's base plus a 32-bit
+// byte offset: an SGPR pair and one VGPR, with no 64-bit address arithmetic per access.
+// The tiled radiation kernels use it; the host runs them only on grids whose arrays hold
+// at most 4 GiB each.
+template <bool O32, typename T>
+__device__ __forceinline__ T& elem(T* p, int i) {
+  if constexpr (O32) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T*>(reinterpret_cast<B*>(p) + unsigned(i) * unsigned(sizeof(T)));
+  } else {
+    return p[i];
+  }
+}
 
 // Radiation state (E_r, F_x, F_y, F_z) of each fixed (Dirichlet) face; bit f of mask
 // marks face f = x-, x+, y-, y+, z-, z+ as fixed.
@@ -387,17 +402,17 @@ __device__ __forceinline__ T flip(T v, int neg, int bit) {
   return (neg & bit) ? -v : v;
 }
 
-template <typename T>
+template <typename T, bool O32 = false>
 __device__ __forceinline__ FrozenRaw<T> frozen_load(const GasView<T>& g, int a, const int s[3],
                                                     bool need_v) {
   FrozenRaw<T> r;
-  r.rho = g.rho[a];
-  r.kF = g.kF ? g.kF[a] : g.kF_s;
-  r.kP = g.kP ? g.kP[a] : g.kP_s;
+  r.rho = elem<O32>(g.rho, a);
+  r.kF = g.kF ? elem<O32>(g.kF, a) : g.kF_s;
+  r.kP = g.kP ? elem<O32>(g.kP, a) : g.kP_s;
   if (need_v) {
-    r.m[0] = g.m[0][a];
-    r.m[1] = g.m[1][a];
-    r.m[2] = g.m[2][a];
+    r.m[0] = elem<O32>(g.m[0], a);
+    r.m[1] = elem<O32>(g.m[1], a);
+    r.m[2] = elem<O32>(g.m[2], a);
   } else {
     r.m[0] = r.m[1] = r.m[2] = T(0);
   }
@@ -485,15 +500,15 @@ __device__ __forceinline__ void rad_update(const RadConst<T>& K, T h, const T Uo
 
 // U^m of the boundary-mapped cell (i, j, k) as loaded; neg marks the flux components a
 // reflecting boundary flips (apply with unflip_rad before use).
-template <typename T>
+template <typename T, bool O32 = false>
 __device__ __forceinline__ void load_rad_raw(const RadPtrs<T>& R, const Geom& G, int i, int j,
                                              int k, T U[4], int& neg) {
   int s[3];
   const int a = mapped_cell(G, i, j, k, s);
-  U[0] = R.E[a];
-  U[1] = R.F[0][a];
-  U[2] = R.F[1][a];
-  U[3] = R.F[2][a];
+  U[0] = elem<O32>(R.E, a);
+  U[1] = elem<O32>(R.F[0], a);
+  U[2] = elem<O32>(R.F[1], a);
+  U[3] = elem<O32>(R.F[2], a);
   neg = neg_mask(s);
 }
 
@@ -609,12 +624,12 @@ __global__ void __launch_bounds__(256) k_rad_predict(RadPtrs<T> Um, RadPtrs<T> U
   rad_predict_cell(Um, Uh, gas, G, K, B, h, i, j, k);
 }
 
-template <typename T>
+template <typename T, bool O32 = false>
 __device__ __forceinline__ void load_padded4(const RadPtrs<T>& R, int p, T U[4]) {
-  U[0] = R.E[p];
-  U[1] = R.F[0][p];
-  U[2] = R.F[1][p];
-  U[3] = R.F[2][p];
+  U[0] = elem<O32>(R.E, p);
+  U[1] = elem<O32>(R.F[0], p);
+  U[2] = elem<O32>(R.F[1], p);
+  U[3] = elem<O32>(R.F[2], p);
 }
 
 // Radiation corrector at interior cell (i, j, k): MC-limited linear reconstruction of

@@ -226,8 +226,8 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   // and the gas data of the cell being updated
   T Un[4], Hn[4] = {T(0), T(0), T(0), T(0)};
   int nU, nH = 0;
-  load_rad_raw(Um, G, xl, yl, z0 - 1, Un, nU);
-  if (hrole) load_rad_raw(Um, G, hx, hy, z0, Hn, nH);
+  load_rad_raw<T, true>(Um, G, xl, yl, z0 - 1, Un, nU);
+  if (hrole) load_rad_raw<T, true>(Um, G, hx, hy, z0, Hn, nH);
   FrozenRaw<T> gn = {};
 
   FaceSide<T> zprev;  // z data of plane t-1
@@ -236,7 +236,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   for (int t = z0 - 1; t <= z1; ++t) {
     T U[4] = {Un[0], Un[1], Un[2], Un[3]};
     unflip_rad(U, nU);
-    if (t < z1) load_rad_raw(Um, G, xl, yl, t + 1, Un, nU);
+    if (t < z1) load_rad_raw<T, true>(Um, G, xl, yl, t + 1, Un, nU);
     const M1State<T> m = m1_state(U, fc, chat);
     // z face t-1/2, then plane t-1 is complete: its z faces are t-3/2 and t-1/2
     const FaceSide<T> fzs = side_dir(m, U, 2, c, ic, chat);
@@ -251,14 +251,14 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       bool ef, fc;
       rad_update(K, h, zprev.U, zprev.U, d, gz, out, ef, fc);
       const int p = padded_cell(G, x, y, t - 1);
-      Uh.E[p] = out[0];
-      Uh.F[0][p] = out[1];
-      Uh.F[1][p] = out[2];
-      Uh.F[2][p] = out[3];
+      elem<true>(Uh.E, p) = out[0];
+      elem<true>(Uh.F[0], p) = out[1];
+      elem<true>(Uh.F[1], p) = out[2];
+      elem<true>(Uh.F[2], p) = out[3];
     }
     if (t >= z0 && t < z1) {
       int s[3];
-      gn = frozen_load(gas, mapped_cell(G, xl, yl, t, s), s, need_v);
+      gn = frozen_load<T, true>(gas, mapped_cell(G, xl, yl, t, s), s, need_v);
     }
     zprev = fzs;
 #pragma unroll
@@ -282,7 +282,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
           sh.sy.put(BY + 1, tx, hs);
         else
           sh.sxe.put(hrow, tx < BY ? 0 : 3, hs);
-        if (t + 1 < z1) load_rad_raw(Um, G, hx, hy, t + 1, Hn, nH);
+        if (t + 1 < z1) load_rad_raw<T, true>(Um, G, hx, hy, t + 1, Hn, nH);
       }
       __syncthreads();
       T fb[4];
@@ -432,15 +432,15 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   T ring[RP][4];
 #pragma unroll
   for (int s = 0; s < RP; ++s)
-    if (rpos[s] >= 0) load_padded4(Uh, rcol[s] + z0 * zs, ring[s]);
+    if (rpos[s] >= 0) load_padded4<T, true>(Uh, rcol[s] + z0 * zs, ring[s]);
 
   const int x = x0 + tx, y = y0 + ty;
   const bool out_xy = x < n0 && y < n1;
   const int pcol = padded_cell(G, clamp_i(x, -2, n0 + 1), clamp_i(y, -2, n1 + 1), 0);
   T Uzm[4], Uz0[4], Uzp[4], Upp[4];
-  load_padded4(Uh, pcol + (z0 - 2) * zs, Uzm);
-  load_padded4(Uh, pcol + (z0 - 1) * zs, Uz0);
-  load_padded4(Uh, pcol + z0 * zs, Uzp);
+  load_padded4<T, true>(Uh, pcol + (z0 - 2) * zs, Uzm);
+  load_padded4<T, true>(Uh, pcol + (z0 - 1) * zs, Uz0);
+  load_padded4<T, true>(Uh, pcol + z0 * zs, Uzp);
   // U^m and the gas data of the cell updated at the next plane, loaded one plane ahead
   const bool need_v = K.beta != 0;
   const int s1[3] = {1, 1, 1};
@@ -460,10 +460,10 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
       if (t + 1 < z1) {
 #pragma unroll
         for (int s = 0; s < RP; ++s)
-          if (rpos[s] >= 0) load_padded4(Uh, rcol[s] + (t + 1) * zs, ring[s]);
+          if (rpos[s] >= 0) load_padded4<T, true>(Uh, rcol[s] + (t + 1) * zs, ring[s]);
       }
     }
-    if (t < z1) load_padded4(Uh, pcol + (t + 2) * zs, Upp);
+    if (t < z1) load_padded4<T, true>(Uh, pcol + (t + 2) * zs, Upp);
     // z: limited states of the own cell; the low z face pairs them with plane t-1
     {
       T mz[4], pz[4];
@@ -482,18 +482,18 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         rad_update(K, h, Uon, Uzm, d, gz, out, ef, fc);
         nef += ef ? 1ull : 0ull;
         nfc += fc ? 1ull : 0ull;
-        Um.E[a] = out[0];
-        Um.F[0][a] = out[1];
-        Um.F[1][a] = out[2];
-        Um.F[2][a] = out[3];
+        elem<true>(Um.E, a) = out[0];
+        elem<true>(Um.F[0], a) = out[1];
+        elem<true>(Um.F[1], a) = out[2];
+        elem<true>(Um.F[2], a) = out[3];
       }
       if (t >= z0 && t < z1 && out_xy) {
         const int a = x + n0 * (y + n1 * t);
-        gn = frozen_load(gas, a, s1, need_v);
-        Uon[0] = Um.E[a];
-        Uon[1] = Um.F[0][a];
-        Uon[2] = Um.F[1][a];
-        Uon[3] = Um.F[2][a];
+        gn = frozen_load<T, true>(gas, a, s1, need_v);
+        Uon[0] = elem<true>(Um.E, a);
+        Uon[1] = elem<true>(Um.F[0], a);
+        Uon[2] = elem<true>(Um.F[1], a);
+        Uon[3] = elem<true>(Um.F[2], a);
       }
       if (t < z1) zplus = face_side(pz, 2, c, ic, fc, chat);
 #pragma unroll
