@@ -294,6 +294,64 @@ def cpu_baseline_pulse(ri, n=512, gas_steps=100):
             "zone_subcycles_per_s": n * subs / el, "seconds": el}
 
 
+def shell_timing(P, ri, stream, n=128, every=0.005):
+    """The expanding-shell test of Sec. 4.4.2 at the paper's 128^3 octant to t = 0.124
+    (the shell reaches 2 r0), mixed precision, for chat/a0 = 860, 430 and 215: time of
+    the stepping (the sampling of <r> and <v_r> every `every` is outside the clock), gas
+    steps and subcycles, and the largest relative errors of <r> and <v_r> against the
+    trajectory of Eqs. radshell:odepos and radshell:odevel next to the paper's."""
+    import torch
+    paper = {860: (0.031, 0.070), 430: (0.053, 0.13), 215: (0.085, 0.23)}
+    rows = []
+    for chat in (860, 430, 215):
+        pb = ri.shell_expansion_problem(n, chat_over_a0=float(chat), precision="mixed")
+        spec = pb["spec"]
+        samples = [(0.0,) + ri.shell_moments(spec, pb["state"], pb["r"])]
+        with P.Solver(spec, stream=stream.cuda_stream) as s:
+            s.set_state(pb["state"])
+            s.sync()
+            torch.cuda.synchronize()
+            t, nxt, steps, subs, el = 0.0, every, 0, 0, 0.0
+            while t < pb["t_end"] * (1 - 1e-12):
+                t0 = time.perf_counter()
+                while t < nxt * (1 - 1e-12):
+                    dt, ns = s.suggest_dt(pb["chat"])
+                    dt = min(dt, nxt - t)
+                    s.step(dt, pb["chat"], ns)
+                    t += dt
+                    steps += 1
+                    subs += ns
+                s.sync()
+                el += time.perf_counter() - t0
+                samples.append((t,) + ri.shell_moments(spec, s.get_state(), pb["r"]))
+                nxt = min(nxt + every, pb["t_end"])
+            diag = s.diagnostics()
+        er, ev = ri.shell_errors(pb["M0"], samples)
+        rows.append({"workload": pb["name"], "chat_over_a0": chat, "gas_steps": steps,
+                     "subcycles": subs, "seconds": el, "zone_subcycles_per_s": n ** 3 * subs / el,
+                     "max_rel_error_r": er, "max_rel_error_vr": ev,
+                     "paper_max_rel_error_r": paper[chat][0], "paper_max_rel_error_vr": paper[chat][1],
+                     "final_r": samples[-1][1], "nonfinite": diag["nonfinite"]})
+    return {"cells": [n, n, n], "precision": "mixed", "rows": rows}
+
+
+def cpu_baseline_shell(ri, n=32, gas_steps=2):
+    """The FP64 oracle on the first gas steps of the shell test at 32^3 (a bounded sample)."""
+    import oracle
+    pb = ri.shell_expansion_problem(n, precision="fp64")
+    spec, st, chat = pb["spec"], pb["state"], pb["chat"]
+    subs = 0
+    t0 = time.perf_counter()
+    for _ in range(gas_steps):
+        dt, ns, _ = oracle.suggest_dt(spec, st, chat)
+        st, _ = oracle.step(spec, st, dt, chat, ns)
+        subs += ns
+    el = time.perf_counter() - t0
+    return {"kind": "oracle", "cores": 1,
+            "sample": f"{n}^3 cells, the first {gas_steps} gas steps ({subs} subcycles)",
+            "zone_subcycles_per_s": n ** 3 * subs / el, "seconds": el}
+
+
 def shadow_timing(P, ri, stream, crossings=10.0):
     """The shadow test of Sec. 4.2.1 at the paper's 280 x 80 cells for 10 horizontal
     light-crossing times, without and with emission, in mixed precision and FP64, in one
@@ -507,8 +565,8 @@ def main():
                     help="offered load as a multiple of the one-at-a-time capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-marshak", action="store_true",
-                    help="skip the Marshak-wave, shadow-test and pulse-advection timings (the "
-                         "paper's own 1D benchmark, its 2D shadow test and its O(beta tau) test)")
+                    help="skip the timings of the paper's own test problems (Marshak wave, "
+                         "shadow, pulse advection, expanding shell)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
@@ -655,6 +713,8 @@ def main():
         progress("shadow test timed")
         out["pulse"] = pulse_timing(P, ri, stream)
         progress("pulse advection timed")
+        out["shell"] = shell_timing(P, ri, stream)
+        progress("expanding shell timed")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
         progress("oracle timed on the host")
@@ -662,7 +722,8 @@ def main():
             out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
             out["shadow"]["cpu_baseline"] = cpu_baseline_shadow(ri)
             out["pulse"]["cpu_baseline"] = cpu_baseline_pulse(ri)
-            progress("oracle timed on the Marshak wave, the shadow test and the pulse")
+            out["shell"]["cpu_baseline"] = cpu_baseline_shell(ri)
+            progress("oracle timed on the Marshak wave, the shadow, pulse and shell tests")
     print(json.dumps(out), flush=True)
 
 

@@ -526,3 +526,221 @@ def gas_temperature(spec, st):
     ke = 0.5 * (np.asarray(st["mx"]) ** 2 + np.asarray(st["my"]) ** 2
                 + np.asarray(st["mz"]) ** 2) / rho
     return (spec["gamma"] - 1.0) * (np.asarray(st["E"]) - ke) / (rho * spec["r_gas"])
+
+
+# --------------------------------------------------------------------------
+# radiation-driven expanding shell (Sec. 4.4.2, the second shell test)
+# --------------------------------------------------------------------------
+
+MSUN_G = 1.989e33
+PC_CM = 3.0857e18
+
+
+def shell_parameters(Psi=2000.0, M_gmc=1e6 * MSUN_G, eps=0.5, kappa0=20.0, r0=5 * PC_CM,
+                     a0=2e5):
+    """The shell test's dimensional parameters and what follows from them: the cluster
+    luminosity L = Psi eps M_GMC, the shell mass (1 - eps) M_GMC, the Mach number
+    M0 = (L kappa0 / (4 pi r0 c a0^2))^(1/2) of Eq. radshell:mach0 and the optical depth
+    tau0 = M_sh kappa0 / (4 pi r0^2) of Eq. radshell:tau0."""
+    L = Psi * eps * M_gmc
+    M_sh = (1.0 - eps) * M_gmc
+    M0 = math.sqrt(L * kappa0 / (4.0 * math.pi * r0 * C_CGS * a0 ** 2))
+    tau0 = M_sh * kappa0 / (4.0 * math.pi * r0 ** 2)
+    return dict(L=L, M_sh=M_sh, M0=M0, tau0=tau0, c_over_a0=C_CGS / a0, r0=r0, a0=a0)
+
+
+class ShellProfile:
+    """Radial profiles of the shell test in code units (r0 = 1, rho0 = M_sh/(4/3 pi r0^3)
+    = 1, a0 = 1, so M_sh = 4 pi/3 and kappa = 3 tau0): the Gaussian shell of Eq.
+    radshell:rhoprofile with FWHM H, the source of Eq. radshell:sourceprofile with width
+    sigma_star, its flux F*(r) of Eq. radshell:fluxprofile, and the reduced flux f(r) of
+    the equilibrium ODE Eq. radshell:odefluxm1, integrated by fourth-order Runge-Kutta
+    outward and inward from the critical point (r_crit, 2 sqrt(3)/5) where Eq.
+    radshell:rcrit holds. Inward the regular solution meets the closure's singular value
+    f = 2 sqrt(3)/5 again near the source, where the streaming field of the source takes
+    over; inside that radius f is held at that value."""
+
+    def __init__(self, M0, tau0, c, H=0.1, sigma_star=0.05, h=5e-5, r_min=1e-3, r_max=4.0):
+        self.M0, self.tau0, self.c = M0, tau0, c
+        self.kappa = 3.0 * tau0
+        self.M_sh = 4.0 * math.pi / 3.0
+        self.L = M0 ** 2 * 4.0 * math.pi * c / self.kappa
+        self.H, self.sig_sh, self.sig_s = H, H / (2.0 * math.sqrt(2.0 * math.log(2.0))), sigma_star
+        self.f_crit = 2.0 * math.sqrt(3.0) / 5.0
+        self.r_crit = self._solve_rcrit()
+        self._integrate(h, r_min, r_max)
+
+    def rho(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        return (self.M_sh / (4.0 * math.pi * r ** 2 * math.sqrt(2.0 * math.pi) * self.sig_sh)
+                * np.exp(-(r - 1.0) ** 2 / (2.0 * self.sig_sh ** 2)))
+
+    def j(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        s = self.sig_s
+        return self.L / (2.0 * math.pi * s * s) ** 1.5 * np.exp(-r ** 2 / (2.0 * s * s))
+
+    def _bracket_F(self, r):
+        from scipy.special import erf
+        s = self.sig_s
+        return (erf(r / (math.sqrt(2.0) * s))
+                - 2.0 * r / math.sqrt(2.0 * math.pi * s * s) * np.exp(-r ** 2 / (2.0 * s * s)))
+
+    def F(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        return self.L / (4.0 * math.pi * r ** 2) * self._bracket_F(r)
+
+    def dlnF(self, r):
+        # d/dr of the bracket is 4 pi r^2 j / L (the bracket is the enclosed luminosity)
+        s = self.sig_s
+        dB = 2.0 * r ** 2 / (math.sqrt(2.0 * math.pi) * s ** 3) * np.exp(-r ** 2 / (2.0 * s * s))
+        return -2.0 / r + dB / self._bracket_F(r)
+
+    def _bracket(self, r, f):
+        q = math.sqrt(max(4.0 - 3.0 * f * f, 0.0))
+        return (self.dlnF(r) / 3.0 * (5.0 - 2.0 * q) + 2.0 / r * (2.0 - q)
+                + float(self.rho(r)) * self.kappa * f)
+
+    def dfdr(self, r, f):
+        q = math.sqrt(max(4.0 - 3.0 * f * f, 0.0))
+        return 3.0 * f * q / (5.0 * q - 8.0) * self._bracket(r, f)
+
+    def _solve_rcrit(self):
+        from scipy.optimize import brentq
+        g = lambda r: 3.0 * self.dlnF(r) + 4.0 / r + 2.0 * math.sqrt(3.0) * float(self.rho(r)) * self.kappa
+        return brentq(g, 1.0 + 0.1 * self.sig_sh, 1.0 + 10.0 * self.sig_sh)
+
+    def _crit_slope(self):
+        """f' at the critical point: with the bracket B(r, f) and q(f) = sqrt(4 - 3 f^2),
+        l'Hopital's rule on f' = 3 f q B / (5 q - 8) gives 5 q_f f'^2 = 3 f q (B_r + B_f f');
+        the regular solution is the root on which f grows outward."""
+        rc, fc, e = self.r_crit, self.f_crit, 1e-6
+        q = math.sqrt(4.0 - 3.0 * fc * fc)
+        qf = -3.0 * fc / q
+        Br = (self._bracket(rc + e, fc) - self._bracket(rc - e, fc)) / (2.0 * e)
+        Bf = (self._bracket(rc, fc + e) - self._bracket(rc, fc - e)) / (2.0 * e)
+        roots = np.roots([5.0 * qf, -3.0 * fc * q * Bf, -3.0 * fc * q * Br])
+        return float(max(roots.real))
+
+    def _rk4(self, r0, f0, r1, h):
+        n = max(1, int(math.ceil(abs(r1 - r0) / abs(h))))
+        hh = (r1 - r0) / n
+        rs, fs = [r0], [f0]
+        r, f = r0, f0
+        for _ in range(n):
+            k1 = self.dfdr(r, f)
+            k2 = self.dfdr(r + hh / 2, f + hh / 2 * k1)
+            k3 = self.dfdr(r + hh / 2, f + hh / 2 * k2)
+            k4 = self.dfdr(r + hh, f + hh * k3)
+            fn = f + hh / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+            if not (0.0 < fn < self.f_crit if hh < 0 else 0.0 < fn < 1.0):
+                break
+            r, f = r + hh, fn
+            rs.append(r)
+            fs.append(f)
+        return np.array(rs), np.array(fs)
+
+    def _integrate(self, h, r_min, r_max):
+        p, d = self._crit_slope(), 5e-4
+        ro, fo = self._rk4(self.r_crit + d, self.f_crit + p * d, r_max, h)
+        ri, fi = self._rk4(self.r_crit - d, self.f_crit - p * d, r_min, -h)
+        self.r_inner = float(ri[-1])  # where the inward solution meets f_crit again
+        self.slope = p
+        self._r = np.concatenate([ri[::-1], ro])
+        self._f = np.concatenate([fi[::-1], fo])
+        self.r_outer = float(ro[-1])
+
+    def f(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        out = np.interp(r, self._r, self._f)
+        out = np.where(r < self.r_inner, self.f_crit, out)
+        return np.where(r > self.r_outer, self._f[-1], out)
+
+    def E(self, r):
+        return self.F(r) / (self.c * self.f(r))
+
+
+_SHELL_PROFILES = {}
+
+
+def shell_profile(H=0.1, sigma_star=0.05):
+    """The ShellProfile of the paper's parameters (computed once per H, sigma_star)."""
+    key = (float(H), float(sigma_star))
+    if key not in _SHELL_PROFILES:
+        par = shell_parameters()
+        _SHELL_PROFILES[key] = ShellProfile(par["M0"], par["tau0"], par["c_over_a0"], H=H,
+                                            sigma_star=sigma_star)
+    return _SHELL_PROFILES[key]
+
+
+def shell_trajectory(M0, t):
+    """The shell radius and velocity of Eqs. radshell:odepos and radshell:odevel (from
+    r = r0 at rest, code units) at times t: r from inverting t(r)."""
+    from scipy.optimize import brentq
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    tr = lambda r: (math.sqrt(r) * math.sqrt(r - 1.0)
+                    + math.log(math.sqrt(r) + math.sqrt(r - 1.0))) / (M0 * math.sqrt(2.0))
+    r = np.array([1.0 if tt <= 0 else brentq(lambda x: tr(x) - tt, 1.0, 1e3) for tt in t])
+    v = M0 * math.sqrt(2.0) * np.sqrt(np.maximum(1.0 - 1.0 / r, 0.0))
+    return r, v
+
+
+def shell_expansion_problem(n=128, chat_over_a0=860.0, precision="mixed", H=0.1, sigma_star=0.05,
+                            rad_only=False):
+    """The expanding-shell test of Sec. 4.4.2 in code units (r0, rho0 = M_sh/(4/3 pi r0^3),
+    a0): the octant [0, 2]^3 with n^3 cells, reflecting faces at 0 and outflow faces at 2,
+    isothermal gas (c_s = 1) at rest in radiative equilibrium (no exchange), the Gaussian
+    shell of FWHM H at r = 1 with the density floor 1e-8, kappa = 3 tau0 for the flux,
+    the central source j*(r), the flux F*(r) r_hat and E_r = F*/(c f(r)) from the
+    equilibrium ODE; c = c/a0 = 1.5e5, chat = chat_over_a0 (860 in the paper, also 430
+    and 215); theta_F = 0.51 (the paper's default). The shell should reach r = 2 near
+    t = 0.12."""
+    par = shell_parameters()
+    c = par["c_over_a0"]
+    prof = shell_profile(H, sigma_star)
+    h = 2.0 / n
+    spec = default_spec(nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, c_light=c, iso_cs=1.0,
+                        isothermal=True, exchange="none", theta_F=0.51, cfl=0.4, rad_only=rad_only,
+                        bc=("reflect", "outflow", "reflect", "outflow", "reflect", "outflow"),
+                        rho_floor=1e-8, er_floor=1e-30, precision=precision)
+    X, Y, Z = cell_centres(spec)
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=0.0, kF=prof.kappa)
+    st["rho"][:] = np.maximum(prof.rho(r), 1e-8)
+    st["E"][:] = 0.0
+    Fr = prof.F(r)
+    st["Er"][:] = prof.E(r)
+    st["Fx"][:] = Fr * X / r
+    st["Fy"][:] = Fr * Y / r
+    st["Fz"][:] = Fr * Z / r
+    st["j"] = prof.j(r)
+    return dict(name=f"shell_{n}cubed_chat{int(chat_over_a0)}", spec=spec, state=st,
+                chat=float(chat_over_a0), M0=par["M0"], tau0=par["tau0"], profile=prof,
+                t_end=0.124, r=r)
+
+
+def shell_moments(spec, st, r=None):
+    """Density-weighted mean radius and radial velocity over the grid, Eqs.
+    radshell:ravgdef and radshell:vravgdef (uniform cells)."""
+    if r is None:
+        X, Y, Z = cell_centres(spec)
+        r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    else:
+        X, Y, Z = cell_centres(spec)
+    rho = np.asarray(st["rho"])
+    m = rho.sum()
+    vr = (np.asarray(st["mx"]) * X + np.asarray(st["my"]) * Y + np.asarray(st["mz"]) * Z) / r
+    return float((rho * r).sum() / m), float(vr.sum() / m)
+
+
+def shell_errors(M0, samples):
+    """Largest relative differences of the sampled (t, <r>, <v_r>) from the trajectory of
+    Eqs. radshell:odepos and radshell:odevel; the velocity from the first sample after
+    t = 0 (it starts at rest, where a relative error has no meaning)."""
+    t = np.array([s[0] for s in samples])
+    r = np.array([s[1] for s in samples])
+    v = np.array([s[2] for s in samples])
+    rex, vex = shell_trajectory(M0, t)
+    moving = t > 0
+    return (float(np.max(np.abs(r / rex - 1.0))),
+            float(np.max(np.abs(v[moving] / vex[moving] - 1.0))))
