@@ -107,6 +107,7 @@ struct rhd {
   bool in_batch = false;
   int variant = RHD_KERNELS_TILED;
   bool tile_ok = true;         // every array the tiled radiation kernels touch holds <= 4 GiB
+  bool law_fresh = false;      // the opacity law's kappa arrays match the current gas state
   int tile_rows = 8;
   int zchunk = 8;
   int fixed_mask = 0;          // bit f: face f is RHD_BC_FIXED (of an active dimension)
@@ -532,6 +533,9 @@ rhdk::ExchConst exch_const(const rhd_t* h, double chat, double dt) {
 template <typename T>
 int enqueue_opacity_law(rhd_t* h) {
   if (!(h->p.flags & RHD_OPACITY_LAW)) return RHD_OK;
+  // a frozen gas that no exchange heats keeps its temperature: the law's values of the
+  // last evaluation still hold
+  if (h->law_fresh) return RHD_OK;
   const rhd_params& p = h->p;
   rhdk::OpacityLaw L;
   L.k0 = p.kappa_law[0];
@@ -546,6 +550,7 @@ int enqueue_opacity_law(rhd_t* h) {
   hipLaunchKernelGGL(rhdk::k_opacity_law<T>, dim3(blocks_for(h->N, 256)), dim3(256), 0, h->stream,
                      gas_ptrs<T>(h->b.gas), as<T>(h->b.kP), as<T>(h->b.kF), L, h->N);
   HIP_TRY(h, hipGetLastError());
+  h->law_fresh = (p.flags & RHD_RAD_ONLY) && (p.flags & RHD_EXCHANGE_MASK) != RHD_EXCHANGE_FULL;
   return RHD_OK;
 }
 
@@ -616,7 +621,7 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
 
 // Steps 6 and the ledger: second-order gas source correction, then the FP64 ledger.
 template <typename T>
-int enqueue_post(rhd_t* h, double dt, double chat) {
+int enqueue_post(rhd_t* h, double dt, double chat, bool ledger = true) {
   const bool rad_only = (h->p.flags & RHD_RAD_ONLY) != 0;
   if (!rad_only) {
     const rhdk::GasConst<T> GK = gas_const<T>(h);
@@ -631,15 +636,15 @@ int enqueue_post(rhd_t* h, double dt, double chat) {
     tend(h, ti);
     HIP_TRY(h, hipGetLastError());
   }
-  return enqueue_ledger<T>(h, chat);
+  return ledger ? enqueue_ledger<T>(h, chat) : RHD_OK;
 }
 
 template <typename T>
-int enqueue_step(rhd_t* h, double dt, double chat, int nsub) {
+int enqueue_step(rhd_t* h, double dt, double chat, int nsub, bool ledger = true) {
   int rc = enqueue_pre<T>(h, dt, chat);
   if (rc) return rc;
   if (nsub > 0 && (rc = enqueue_subcycles<T>(h, dt, chat, nsub))) return rc;
-  return enqueue_post<T>(h, dt, chat);
+  return enqueue_post<T>(h, dt, chat, ledger);
 }
 
 constexpr int RUN_CHUNK = 1024;  // steps per launch of the fused 1D path
@@ -663,13 +668,14 @@ template <typename T>
 int run_impl(rhd_t* h, int nsteps, const double* dt, const int* nsub, double chat,
              const double* bvals) {
   if (!run_fused<T>(h)) {
+    // the ledger is taken once, after the last step
     for (int k = 0; k < nsteps; ++k) {
       run_faces(h, bvals, k, h->bval);
-      if (int rc = enqueue_step<T>(h, dt[k], chat, nsub[k])) return rc;
+      if (int rc = enqueue_step<T>(h, dt[k], chat, nsub[k], false)) return rc;
       h->steps += 1;
       h->subcycles += nsub[k];
     }
-    return RHD_OK;
+    return nsteps > 0 ? enqueue_ledger<T>(h, chat) : RHD_OK;
   }
   using Step = rhdk::RunStep<T>;
   if (!h->b.run_dev) {
@@ -808,6 +814,7 @@ int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double*
     h->kappa_scalar = false;
   }
   h->have_state = true;
+  h->law_fresh = false;
   return RHD_OK;
 }
 
