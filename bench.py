@@ -584,7 +584,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: a multi-GPU run is not "
+        print(json.dumps({"error": "the solver runs on one GPU: a multi-GPU run is not "
                                    "implemented (the one-GPU path is --gpus 1)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
