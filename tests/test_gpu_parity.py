@@ -150,6 +150,38 @@ def two_d_reflect(precision):
     return spec, st, 5.0, 3
 
 
+@case
+def one_d_along_z(precision):
+    """A column along z only (x and y inactive): the boundary mapping and the flux
+    directions of the last dimension alone, with reflecting ends and moving gas."""
+    spec = ri.default_spec(nz=160, dz=1 / 160, c_light=60.0, exchange="full", theta_E=0.51,
+                           beta_tau=True, bc=("periodic",) * 4 + ("reflect", "reflect"),
+                           precision=precision)
+    st = ri.smooth_random_state(spec, seed=9, amp=0.2, f_amp=0.3, kappa=(5.0, 5.0), v_amp=0.2)
+    return spec, st, 15.0, 3
+
+
+@case
+def two_d_xz_plane(precision):
+    """An x-z plane (y inactive) with outflow in x and periodic z."""
+    spec = ri.default_spec(nx=40, nz=30, dx=1 / 40, dz=1 / 30, c_light=30.0, exchange="full",
+                           bc=("outflow", "outflow", "periodic", "periodic", "periodic", "periodic"),
+                           precision=precision)
+    st = ri.smooth_random_state(spec, seed=10, amp=0.15, f_amp=0.4, kappa=(2.0, 3.0), v_amp=0.2)
+    return spec, st, 8.0, 2
+
+
+@case
+def two_d_yz_plane(precision):
+    """A y-z plane (x inactive) with reflecting y walls and outflow in z."""
+    spec = ri.default_spec(ny=24, nz=36, dy=1 / 24, dz=1 / 36, c_light=30.0, exchange="full",
+                           theta_E=0.7, bc=("periodic", "periodic", "reflect", "reflect", "outflow",
+                                            "outflow"), precision=precision)
+    st = ri.smooth_random_state(spec, seed=11, amp=0.15, f_amp=0.4, kappa=(2.0, 3.0), v_amp=0.2,
+                                with_j=True)
+    return spec, st, 8.0, 2
+
+
 VARIANTS = {"per_cell": (P.RHD_KERNELS_PER_CELL, 8, 16), "tiled": (P.RHD_KERNELS_TILED, 8, 16)}
 
 
