@@ -352,6 +352,33 @@ def cpu_baseline_shell(ri, n=32, gas_steps=2):
             "zone_subcycles_per_s": n ** 3 * subs / el, "seconds": el}
 
 
+def box_fp64_timing(P, ri, stream, n=128, steps=5, warmup=2):
+    """The headline box in FP64 throughout (state, stencils, exchange, ledger) on the
+    tiled kernels (8 rows x 8 planes): zone-updates/s over `steps` gas steps."""
+    import torch
+    pb = ri.c2_linear_box(n, precision="fp64")
+    spec, chat = pb["spec"], pb["chat"]
+    with P.Solver(spec, stream=stream.cuda_stream) as s:
+        s.set_kernel_variant(P.RHD_KERNELS_TILED, 8, 8)
+        s.set_state(pb["state"])
+
+        def one():
+            dt, ns = s.suggest_dt(chat)
+            s.step(dt, chat, ns)
+            return ns
+
+        for _ in range(warmup):
+            one()
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sub = sum(one() for _ in range(steps))
+        s.sync()
+        el = time.perf_counter() - t0
+    return {"workload": pb["name"], "precision": "fp64", "steps": steps,
+            "ms_per_step": 1e3 * el / steps, "zone_updates_per_s": n ** 3 * sub / el}
+
+
 def shadow_timing(P, ri, stream, crossings=10.0):
     """The shadow test of Sec. 4.2.1 at the paper's 280 x 80 cells for 10 horizontal
     light-crossing times, without and with emission, in mixed precision and FP64, in one
@@ -694,6 +721,10 @@ def main():
         out["roofline"] = roofline(kernels, spec, False, False, pb["name"])
         out["kernels"] = kernels
         out["kernel_ms_per_step"] = sum(t["total_ms"] for t in timing.values()) / args.steps
+
+    if args.precision == "mixed" and args.n == 128:
+        out["box_fp64"] = box_fp64_timing(P, ri, stream)
+        progress("FP64 box timed")
 
     out["diagnostics"] = {k: diag[k] for k in ("nonfinite", "rad_fclamp", "rad_efloor",
                                                "gas_rhofloor", "gas_pfloor", "exch_theta1",

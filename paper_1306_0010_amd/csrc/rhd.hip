@@ -768,6 +768,7 @@ int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double*
   if (!E && !iso) return fail(h, RHD_EINVAL, "E must be non-NULL for an ideal gas");
   const int N = h->N;
   int rc;
+  h->law_fresh = false;  // a new gas state: the law's values must be evaluated again
   if ((rc = upload_field<T>(h, rho, h->b.gas[0], N, host))) return rc;
   for (int q = 0; q < 3; ++q)
     if ((rc = upload_field<T>(h, mom + size_t(q) * N, h->b.gas[1 + q], N, host))) return rc;
@@ -814,7 +815,6 @@ int set_state_impl(rhd_t* h, const double* rho, const double* mom, const double*
     h->kappa_scalar = false;
   }
   h->have_state = true;
-  h->law_fresh = false;
   return RHD_OK;
 }
 

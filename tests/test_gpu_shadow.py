@@ -198,3 +198,36 @@ def test_exchange_that_rounds_the_radiation_away_is_floored(Er, case, precision)
     assert diag["nonfinite"] == 0
     assert np.all(ref["Er"] == spec["er_floor"]) and np.all(gpu["Er"] == floor)
     assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"exchange floor {case}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_opacity_law_follows_a_new_state(precision):
+    """With the gas frozen and absorption only, the law's values are kept between steps;
+    rhd_set_state with a hotter gas must bring new ones: a handle stepped on state A,
+    then given state B and stepped again, ends where a fresh handle on B ends, bit for
+    bit, and the oracle agrees."""
+    announce(f"opacity law cache {precision}")
+    pb = ri.shadow_problem(56, 16, emission=False, precision=precision)
+    spec, dt, chat = pb["spec"], pb["dt"], pb["chat"]
+    A = pb["state"]
+    B = ri.copy_state(A)
+    B["E"] = B["E"] * 1.7  # a hotter gas: a lower opacity under kappa ~ T^-3.5
+    with P.Solver(spec) as s:
+        s.set_state(A)
+        s.set_boundary(spec["bvals"])
+        s.run(np.full(3, dt), np.ones(3, dtype=np.int32), chat)
+        s.set_state(B)
+        s.run(np.full(3, dt), np.ones(3, dtype=np.int32), chat)
+        s.sync()
+        got = s.get_state()
+    with P.Solver(spec) as s:
+        s.set_state(B)
+        s.set_boundary(spec["bvals"])
+        s.run(np.full(3, dt), np.ones(3, dtype=np.int32), chat)
+        s.sync()
+        fresh = s.get_state()
+    for k in ri.FIELDS:
+        assert np.array_equal(got[k], fresh[k]), k
+    ref, _ = oracle.step(spec, B, dt, chat, 1, steps=3)
+    tol = FP64_TOL_BEAM if precision == "fp64" else TOL[precision]
+    assert_parity(spec, got, ref, tol, NORM[precision], label=f"law cache {precision}")
