@@ -602,6 +602,9 @@ def main():
                     help="radiation subcycles of the 256^3 point-source measurement (0 skips it)")
     ap.add_argument("--c4-steps", type=int, default=5,
                     help="gas steps of the 256^3 dusty-shell measurement (0 skips it)")
+    ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell"),
+                    help="run only this test problem's timing and print its record (for "
+                         "profiling one workload)")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the 256^3 point-source measurement and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -627,6 +630,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.only:
+        fn = {"marshak": marshak_timing, "shadow": shadow_timing, "pulse": pulse_timing,
+              "shell": shell_timing}[args.only]
+        print(json.dumps({args.only: fn(P, ri, stream)}), flush=True)
+        return
 
     if args.c3_only:
         print(json.dumps(c3_measurement(P, ri, stream, max(1, args.c3_subcycles),
