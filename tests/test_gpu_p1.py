@@ -137,3 +137,22 @@ def test_batch_of_m1_and_p1_members_equals_lone_handles():
     for pb, o, r in zip(pbs, outs, ref):
         assert_parity(pb["spec"], o, r, 1e-6, "max", label=f"batch {pb['spec']['closure']}")
     assert np.abs(outs[0]["Er"] - outs[1]["Er"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_p1_shadow_matches_oracle(precision):
+    """The P1 closure with the opacity law and the fixed beam face (the coarse shadow
+    test, 150 steps): the per-cell kernels against the oracle."""
+    announce(f"p1 shadow {precision}")
+    pb = ri.shadow_problem(56, 16, emission=False, precision=precision)
+    spec = dict(pb["spec"], closure="p1")
+    dt, chat, steps = pb["dt"], pb["chat"], 150
+    ref, _ = oracle.step(spec, pb["state"], dt, chat, 1, steps=steps)
+    with P.Solver(spec) as s:
+        s.set_state(pb["state"])
+        s.set_boundary(spec["bvals"])
+        s.run(np.full(steps, dt), np.ones(steps, dtype=np.int32), chat)
+        s.sync()
+        gpu, diag = s.get_state(), s.diagnostics()
+    assert diag["nonfinite"] == 0
+    assert_parity(spec, gpu, ref, TOL[precision], NORM[precision], label=f"p1 shadow {precision}")
