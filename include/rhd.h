@@ -55,7 +55,8 @@ extern "C" {
                                  beyond the face, in U^m and U^{m+1/2}; a cell beyond several
                                  fixed faces takes the last in the order x, y, z. The gas
                                  continues zero-gradient. Needs RHD_RAD_ONLY; such handles
-                                 run the per-cell radiation kernels and cannot join a batch.
+                                 run the face-split or per-cell radiation kernels (not the
+                                 tiled ones) and cannot join a batch.
                                  For driven problems such as the Marshak wave (Sec. 4.2.3). */
 
 /* rhd_params.flags */
@@ -248,7 +249,11 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
 /* Kernel variants of the radiation subcycle (rhd_set_kernel_variant). */
 #define RHD_KERNELS_PER_CELL  0   /* one thread per cell, every face flux evaluated twice     */
 #define RHD_KERNELS_TILED     1   /* x-y tiles in LDS marching along z, every face flux once;
-                                     3D grids only (other grids use the per-cell kernels)   */
+                                     3D grids without fixed faces only: other 2D and 3D
+                                     grids run the face-split kernels up to 2^17 cells, the
+                                     per-cell ones beyond; 1D grids the per-cell ones       */
+#define RHD_KERNELS_FACE_SPLIT 2  /* 64 cells per block, one wavefront per face of a cell,
+                                     fluxes met in LDS: for small grids of any dimension    */
 
 /* Select the kernels of the radiation subcycle: variant RHD_KERNELS_*, tile_rows the
    rows of a 64-wide tile (4, 8 or 16; FP64 handles 4 or 8), zchunk the z-planes one tile
@@ -257,7 +262,8 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
    tiled kernels address with 32-bit byte offsets: a grid whose padded arrays
    ((nx + 4)(ny + 4)(nz + 4) cells) exceed 4 GiB each (beyond ~1000^3 cells in mixed
    precision, ~800^3 in FP64) runs the per-cell kernels, and asking for the tiled ones
-   there is RHD_EINVAL. */
+   there is RHD_EINVAL. The face-split kernels index cells with 32-bit integers (any grid
+   rhd_create accepts). */
 int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk);
 
 /* Pick the fastest radiation-subcycle kernels for this handle's grid by timing them:

@@ -44,6 +44,7 @@ RHD_OPACITY_LAW = 1 << 7
 RHD_CLOSURE_P1 = 1 << 8
 RHD_KERNELS_PER_CELL = 0
 RHD_KERNELS_TILED = 1
+RHD_KERNELS_FACE_SPLIT = 2
 
 EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_device",
             "rhd_set_emission", "rhd_set_boundary", "rhd_step", "rhd_run", "rhd_suggest_dt", "rhd_ledger", "rhd_get_state",

@@ -424,6 +424,11 @@ rhdk::RadConst<T> rad_const(const rhd_t* h, double chat) {
   return RK;
 }
 
+// Grids that do not take the tiled kernels run the face-split ones up to this many cells
+// and the per-cell ones beyond (where the per-cell kernels fill the chip and the
+// face-split ones' extra closure evaluations and LDS round trip cost more than they save).
+constexpr int FACE_SPLIT_MAX_CELLS = 1 << 17;
+
 // nsub radiation Van Leer subcycles of dt/nsub with the gas frozen (Sec. 3.3, 3.4).
 template <typename T>
 int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
@@ -442,13 +447,38 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
     }
     return RHD_OK;
   }
-  dim3 gp, bp, gc, bc;
-  region_launch(G.ps, gp, bp);
-  region_launch(G.n, gc, bc);
   rhdk::FixedFaces<T> B{};
   B.mask = h->fixed_mask;
   for (int f = 0; f < 6; ++f)
     for (int q = 0; q < 4; ++q) B.v[f][q] = T(h->bval[f][q]);
+  // below ~1e5 cells the per-cell kernels leave most of the chip idle and wait on one
+  // thread's chain of faces; the face-split kernels spread a cell's faces over wavefronts.
+  // 1D grids keep the per-cell kernels by default: they share their device code with the
+  // one-workgroup kernel of rhd_run, so stepping and rhd_run agree bit for bit there.
+  const int roles = 2 * (G.act[0] + G.act[1] + G.act[2]);
+  const bool face_split = h->variant == RHD_KERNELS_FACE_SPLIT ||
+                          (h->variant == RHD_KERNELS_TILED && roles >= 4 &&
+                           h->N <= FACE_SPLIT_MAX_CELLS);
+  if (face_split && roles > 0) {
+    const dim3 block(rhdk::FS_LANES, roles);
+    const dim3 gp((h->NP + rhdk::FS_LANES - 1) / rhdk::FS_LANES);
+    const dim3 gc((h->N + rhdk::FS_LANES - 1) / rhdk::FS_LANES);
+    for (int m = 0; m < nsub; ++m) {
+      int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
+      hipLaunchKernelGGL(rhdk::k_rad_predict_fs<T>, gp, block, 0, h->stream, rad, rh, view, G, RK,
+                         B, T(0.5 * hr), h->NP);
+      tend(h, ti);
+      ti = tbegin(h, KC_RAD_CORRECT, h->N);
+      hipLaunchKernelGGL(rhdk::k_rad_correct_fs<T>, gc, block, 0, h->stream, rad, rh, view, G, RK,
+                         T(hr), h->N, h->b.ctr);
+      tend(h, ti);
+    }
+    HIP_TRY(h, hipGetLastError());
+    return RHD_OK;
+  }
+  dim3 gp, bp, gc, bc;
+  region_launch(G.ps, gp, bp);
+  region_launch(G.n, gc, bc);
   for (int m = 0; m < nsub; ++m) {
     int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
     hipLaunchKernelGGL(rhdk::k_rad_predict<T>, gp, bp, 0, h->stream, rad, rh, view, G, RK, B,
@@ -941,7 +971,8 @@ int autotune_impl(rhd_t* h, double chat, double dt_rad, int reps) {
   Cand cands[32];
   int nc = 0;
   cands[nc++] = {RHD_KERNELS_PER_CELL, 8, 16};
-  if (three_d) {
+  cands[nc++] = {RHD_KERNELS_FACE_SPLIT, 8, 16};
+  if (three_d && !h->fixed_mask && h->tile_ok) {
     const int rows_list[3] = {4, 8, 16};
     const int zc_list[4] = {6, 8, 12, 16};
     for (int r : rows_list) {
@@ -1328,7 +1359,8 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out) {
 
 int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk) {
   if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
-  if (variant != RHD_KERNELS_PER_CELL && variant != RHD_KERNELS_TILED)
+  if (variant != RHD_KERNELS_PER_CELL && variant != RHD_KERNELS_TILED &&
+      variant != RHD_KERNELS_FACE_SPLIT)
     return fail(h, RHD_EINVAL, "unknown kernel variant %d", variant);
   const bool rows_ok = tile_rows == 4 || tile_rows == 8 || (tile_rows == 16 && h->mixed);
   if (!rows_ok) return fail(h, RHD_EINVAL, "tile rows must be 4, 8 (or 16 in mixed precision)");
@@ -1350,13 +1382,10 @@ int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, i
     return fail(h, RHD_EINVAL, "chat and dt_rad must be > 0 and reps >= 1");
   if (chat * dt_rad > h->p.cfl * h->dxmin * (1.0 + 1e-12))
     return fail(h, RHD_ECFL, "chat dt_rad exceeds K0 dx");
-  // fixed faces, and grids too large for the tiled kernels, run the per-cell kernels
-  int rc = RHD_OK;
-  if (h->fixed_mask || !h->tile_ok)
-    h->variant = RHD_KERNELS_PER_CELL;
-  else
-    rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
-                  : autotune_impl<double>(h, chat, dt_rad, reps);
+  // fixed faces, and grids too large for the tiled kernels, choose between the per-cell
+  // and the face-split kernels
+  const int rc = h->mixed ? autotune_impl<float>(h, chat, dt_rad, reps)
+                          : autotune_impl<double>(h, chat, dt_rad, reps);
   if (variant) *variant = h->variant;
   if (tile_rows) *tile_rows = h->tile_rows;
   if (zchunk) *zchunk = h->zchunk;

@@ -704,6 +704,223 @@ __global__ void __launch_bounds__(256) k_rad_correct(RadPtrs<T> Um, RadPtrs<T> U
 }
 
 // ---------------------------------------------------------------------------
+// face-split radiation stages (small grids)
+// ---------------------------------------------------------------------------
+//
+// On grids of a few thousand cells the per-cell kernels above wait on one thread's
+// chain of work: every face of its cell in turn. Here a block takes 64 consecutive cells
+// and one wavefront per face of a cell: role 2 s is the low face and role 2 s + 1 the
+// high face of the s-th active dimension (in the order x, y, z). Each wavefront evaluates
+// its face flux for the 64 cells with the device code of the per-cell kernels, the
+// fluxes meet in LDS, and the first wavefront forms the divergence in the per-cell
+// kernels' order and updates the cells. The arithmetic is the per-cell kernels'; the
+// compiler may contract its multiply-adds differently in the two, so results agree to
+// rounding.
+
+constexpr int FS_LANES = 64;
+constexpr int FS_MAX_ROLES = 6;
+
+template <typename T>
+struct FaceFluxes {
+  T f[4][FS_MAX_ROLES][FS_LANES];  // [component][role][lane]
+};
+
+// The s-th active dimension.
+__device__ __forceinline__ int active_dim(const Geom& G, int s) {
+  int d = 0;
+  for (; d < 2; ++d) {
+    if (G.act[d]) {
+      if (s == 0) break;
+      --s;
+    }
+  }
+  return d;
+}
+
+// The flux through the low (high = false) or high face normal to D of cell (i, j, k),
+// whose state is U0, from the first-order states of U^m.
+template <int D, typename T>
+__device__ __forceinline__ void predict_face(const RadPtrs<T>& Um, const Geom& G,
+                                             const RadConst<T>& K, const FixedFaces<T>& B,
+                                             const T U0[4], int i, int j, int k, bool high,
+                                             T f[4]) {
+  constexpr int di = D == 0, dj = D == 1, dk = D == 2;
+  const M1State<T> m0 = m1_state(U0, K.fclo, K.chat);
+  FaceSide<T> own;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) own.U[q] = U0[q];
+  m1_dir(m0, D, K.c, K.inv_c, K.chat, own.Phi, own.lmin, own.lmax);
+  T Un[4];
+  if (high) {
+    load_rad_bc(Um, G, B, i + di, j + dj, k + dk, Un);
+    hll(own, face_side(Un, D, K.c, K.inv_c, K.fclo, K.chat), f);
+  } else {
+    load_rad_bc(Um, G, B, i - di, j - dj, k - dk, Un);
+    hll(face_side(Un, D, K.c, K.inv_c, K.fclo, K.chat), own, f);
+  }
+}
+
+// The flux through the low or high face normal to D of the cell at padded index pc, whose
+// half-step state is Uc, from the MC-limited reconstruction of U^{m+1/2}.
+template <int D, typename T>
+__device__ __forceinline__ void correct_face(const RadPtrs<T>& Uh, const Geom& G,
+                                             const RadConst<T>& K, const T Uc[4], int pc,
+                                             bool high, T f[4]) {
+  const int stride = D == 0 ? 1 : (D == 1 ? G.ps[0] : G.ps[0] * G.ps[1]);
+  T L[4], R[4];
+  if (high) {
+    T Um1[4], Up1[4], Up2[4];
+    load_padded4(Uh, pc - stride, Um1);
+    load_padded4(Uh, pc + stride, Up1);
+    load_padded4(Uh, pc + 2 * stride, Up2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T s0 = mc_half_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
+      const T sp = mc_half_slope(Up1[q] - Uc[q], Up2[q] - Up1[q]);
+      L[q] = Uc[q] + s0;
+      R[q] = Up1[q] - sp;
+    }
+  } else {
+    T Um2[4], Um1[4], Up1[4];
+    load_padded4(Uh, pc - 2 * stride, Um2);
+    load_padded4(Uh, pc - stride, Um1);
+    load_padded4(Uh, pc + stride, Up1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T sm = mc_half_slope(Um1[q] - Um2[q], Uc[q] - Um1[q]);
+      const T s0 = mc_half_slope(Uc[q] - Um1[q], Up1[q] - Uc[q]);
+      L[q] = Um1[q] + sm;
+      R[q] = Uc[q] - s0;
+    }
+  }
+  L[0] = vmax(L[0], K.er_floor);
+  R[0] = vmax(R[0], K.er_floor);
+  rad_hll(L, R, D, K.c, K.inv_c, K.fclo, K.chat, f);
+}
+
+// The divergence of the fluxes in LDS for lane l, summed over the active dimensions in
+// the order x, y, z as the per-cell kernels sum it.
+template <typename T>
+__device__ __forceinline__ void face_divergence(const FaceFluxes<T>& sh, const Geom& G,
+                                                const RadConst<T>& K, int l, T div[4]) {
+  int r = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) div[q] += (sh.f[q][r + 1][l] - sh.f[q][r][l]) * K.inv_w[d];
+    r += 2;
+  }
+}
+
+// Predictor over the padded region; block b covers padded cells [64 b, 64 b + 64), with
+// blockDim = (64, 2 x the active dimensions).
+template <typename T>
+__global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
+    k_rad_predict_fs(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas, Geom G, RadConst<T> K,
+                     FixedFaces<T> B, T h, int NP) {
+  __shared__ FaceFluxes<T> sh;
+  const int lane = int(threadIdx.x), role = int(threadIdx.y);
+  const unsigned pu = blockIdx.x * unsigned(FS_LANES) + unsigned(lane);
+  const bool live = pu < unsigned(NP);
+  const int p = int(pu);
+  int i = 0, j = 0, k = 0;
+  if (live) {
+    const int q = p / G.ps[0];
+    i = p - q * G.ps[0] - G.g[0];
+    j = q % G.ps[1] - G.g[1];
+    k = q / G.ps[1] - G.g[2];
+  }
+  const int fb = (live && B.mask) ? fixed_face(G, B.mask, i, j, k) : -1;
+  T U0[4] = {T(0), T(0), T(0), T(0)};
+  if (live && fb < 0) {
+    load_rad_bc(Um, G, B, i, j, k, U0);
+    const int d = active_dim(G, role >> 1);
+    const bool high = (role & 1) != 0;
+    T f[4];
+    if (d == 0)
+      predict_face<0>(Um, G, K, B, U0, i, j, k, high, f);
+    else if (d == 1)
+      predict_face<1>(Um, G, K, B, U0, i, j, k, high, f);
+    else
+      predict_face<2>(Um, G, K, B, U0, i, j, k, high, f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh.f[q][role][lane] = f[q];
+  }
+  __syncthreads();
+  if (role != 0 || !live) return;
+  T out[4];
+  if (fb >= 0) {
+    fixed_state(B, fb, out);
+  } else {
+    T div[4] = {T(0), T(0), T(0), T(0)};
+    face_divergence(sh, G, K, lane, div);
+    int s[3];
+    const int a = mapped_cell(G, i, j, k, s);
+    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+    bool ef, fc;
+    rad_update(K, h, U0, U0, div, fz, out, ef, fc);
+  }
+  Uh.E[p] = out[0];
+  Uh.F[0][p] = out[1];
+  Uh.F[1][p] = out[2];
+  Uh.F[2][p] = out[3];
+}
+
+// Corrector over the interior; block b covers cells [64 b, 64 b + 64), with blockDim as
+// for the predictor.
+template <typename T>
+__global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
+    k_rad_correct_fs(RadPtrs<T> Um, RadPtrs<T> Uh, GasView<T> gas, Geom G, RadConst<T> K, T h,
+                     int N, unsigned long long* ctr) {
+  __shared__ FaceFluxes<T> sh;
+  const int lane = int(threadIdx.x), role = int(threadIdx.y);
+  const unsigned au = blockIdx.x * unsigned(FS_LANES) + unsigned(lane);
+  const bool live = au < unsigned(N);
+  const int a = int(au);
+  int pc = 0;
+  T Uc[4] = {T(0), T(0), T(0), T(0)};
+  if (live) {
+    const int q = a / G.n[0];
+    const int i = a - q * G.n[0];
+    const int j = q % G.n[1];
+    const int k = q / G.n[1];
+    pc = padded_cell(G, i, j, k);
+    load_padded4(Uh, pc, Uc);
+    const int d = active_dim(G, role >> 1);
+    const bool high = (role & 1) != 0;
+    T f[4];
+    if (d == 0)
+      correct_face<0>(Uh, G, K, Uc, pc, high, f);
+    else if (d == 1)
+      correct_face<1>(Uh, G, K, Uc, pc, high, f);
+    else
+      correct_face<2>(Uh, G, K, Uc, pc, high, f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh.f[q][role][lane] = f[q];
+  }
+  __syncthreads();
+  if (role != 0) return;
+  // the first wavefront, all 64 lanes, down to the counters
+  bool ef = false, fc = false;
+  if (live) {
+    T div[4] = {T(0), T(0), T(0), T(0)};
+    face_divergence(sh, G, K, lane, div);
+    const int s[3] = {1, 1, 1};
+    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+    T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+    T out[4];
+    rad_update(K, h, Uo, Uc, div, fz, out, ef, fc);
+    Um.E[a] = out[0];
+    Um.F[0][a] = out[1];
+    Um.F[1][a] = out[2];
+    Um.F[2][a] = out[3];
+  }
+  wave_add(ctr + CTR_RAD_EFLOOR, ef ? 1ull : 0ull);
+  wave_add(ctr + CTR_RAD_FCLAMP, fc ? 1ull : 0ull);
+}
+
+// ---------------------------------------------------------------------------
 // gas subsystem
 // ---------------------------------------------------------------------------
 

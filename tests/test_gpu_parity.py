@@ -29,6 +29,9 @@ NORM = {"fp64": "max", "mixed": "l1"}
 # enter the HLL dissipation term, so FP64 results agree to ~sqrt(eps) times the share of
 # that term instead of ~eps; 1e-10 bounds it with a margin of three over what is seen.
 FP64_TOL_BRANCH_POINT = {"dusty_shell_32": 1e-10}
+# The shadow problem's beam enters at f = 1 exactly, across the whole fixed face: the
+# same branch point, reached by every lit cell, whose FP64 results agree to ~sqrt(eps).
+FP64_TOL_BEAM = 2e-8
 
 
 def announce(name):
@@ -182,10 +185,11 @@ def two_d_yz_plane(precision):
     return spec, st, 8.0, 2
 
 
-VARIANTS = {"per_cell": (P.RHD_KERNELS_PER_CELL, 8, 16), "tiled": (P.RHD_KERNELS_TILED, 8, 16)}
+VARIANTS = {"per_cell": (P.RHD_KERNELS_PER_CELL, 8, 16), "tiled": (P.RHD_KERNELS_TILED, 8, 16),
+            "face_split": (P.RHD_KERNELS_FACE_SPLIT, 8, 16)}
 
 
-@pytest.mark.parametrize("variant", ["per_cell", "tiled"])
+@pytest.mark.parametrize("variant", ["per_cell", "tiled", "face_split"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_step_matches_oracle(name, precision, variant):
@@ -216,6 +220,52 @@ def test_tile_shapes_agree_with_per_cell_kernels(rows, zchunk, precision):
     a, _ = run_gpu(spec, st, 2, chat, dt, ns, (P.RHD_KERNELS_PER_CELL, 8, 16))
     b, _ = run_gpu(spec, st, 2, chat, dt, ns, (P.RHD_KERNELS_TILED, rows, zchunk))
     assert_parity(spec, b, a, 1e-13 if precision == "fp64" else 2e-6, "max", label="tile vs per-cell")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", sorted(CASES) + ["shadow_fixed_face", "beam_fixed_faces_3d"])
+def test_face_split_kernels_equal_per_cell_kernels(name, precision):
+    """The face-split kernels evaluate the per-cell kernels' face fluxes with the same
+    code and sum them in the same order; the compiler may still contract multiply-adds
+    differently in the two kernels, so the states agree to rounding (the bar against the
+    oracle), on every grid dimension and boundary kind, fixed faces included (the coarse
+    shadow problem, whose beam sits at the branch point f = 1, and a 3D box with two fixed
+    faces)."""
+    announce(f"face split vs per cell {name} {precision}")
+    if name == "shadow_fixed_face":
+        pb = ri.shadow_problem(56, 16, emission=True, precision=precision, heat_capacity=1e-6)
+        spec, st, dt, chat, ns, steps = pb["spec"], pb["state"], pb["dt"], pb["chat"], 1, 6
+    elif name == "beam_fixed_faces_3d":
+        spec = ri.default_spec(nx=20, ny=12, nz=10, dx=1 / 20, dy=1 / 12, dz=1 / 10, c_light=10.0,
+                               exchange="full", rad_only=True, bc=("fixed", "outflow", "reflect", "fixed",
+                                                    "periodic", "periodic"), precision=precision)
+        st = ri.smooth_random_state(spec, seed=5, amp=0.2, f_amp=0.3, kappa=(1.0, 4.0), v_amp=0.1,
+                                    with_j=True)
+        spec["bvals"] = [[4.0, 3.0, 0.5, -0.2], [0.0] * 4, [0.0] * 4, [2.0, 0.1, -1.5, 0.3],
+                         [0.0] * 4, [0.0] * 4]
+        chat = 10.0
+        dt, ns = step_sizes(spec, st, chat)
+        steps = 3
+    else:
+        spec, st, chat, steps = CASES[name](precision)
+        dt, ns = step_sizes(spec, st, chat)
+    runs = []
+    for v in ("per_cell", "face_split"):
+        with P.Solver(spec) as s:
+            s.set_kernel_variant(*VARIANTS[v])
+            s.set_state(st)
+            if "bvals" in spec:
+                s.set_boundary(spec["bvals"])
+            for _ in range(steps):
+                s.step(dt, chat, ns)
+            s.sync()
+            runs.append((s.get_state(), s.diagnostics()))
+    (a, da), (b, db) = runs
+    assert da["nonfinite"] == 0 and db["nonfinite"] == 0
+    tol = TOL[precision]
+    if precision == "fp64":
+        tol = FP64_TOL_BRANCH_POINT.get(name, FP64_TOL_BEAM if name == "shadow_fixed_face" else tol)
+    assert_parity(spec, b, a, tol, NORM[precision], label=f"face split vs per cell {name}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -341,7 +391,8 @@ def test_autotune_keeps_state_and_result(precision):
         before = s.get_state()
         d0 = s.diagnostics()
         v, rows, zc = s.autotune(chat, dt / ns, reps=2)
-        assert v in (P.RHD_KERNELS_PER_CELL, P.RHD_KERNELS_TILED) and rows in (4, 8, 16) and zc >= 1
+        assert v in (P.RHD_KERNELS_PER_CELL, P.RHD_KERNELS_TILED, P.RHD_KERNELS_FACE_SPLIT)
+        assert rows in (4, 8, 16) and zc >= 1
         after = s.get_state()
         for k in ri.FIELDS:
             assert np.array_equal(before[k], after[k]), k
