@@ -833,7 +833,14 @@ __global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
   }
   const int fb = (live && B.mask) ? fixed_face(G, B.mask, i, j, k) : -1;
   T U0[4] = {T(0), T(0), T(0), T(0)};
+  // the first wavefront issues the cell's gas loads before its face, off the critical path
+  FrozenRaw<T> raw{};
   if (live && fb < 0) {
+    if (role == 0) {
+      int s[3];
+      const int a = mapped_cell(G, i, j, k, s);
+      raw = frozen_load(gas, a, s, K.beta != 0);
+    }
     load_rad_bc(Um, G, B, i, j, k, U0);
     const int d = active_dim(G, role >> 1);
     const bool high = (role & 1) != 0;
@@ -855,9 +862,7 @@ __global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
   } else {
     T div[4] = {T(0), T(0), T(0), T(0)};
     face_divergence(sh, G, K, lane, div);
-    int s[3];
-    const int a = mapped_cell(G, i, j, k, s);
-    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
+    const Frozen<T> fz = frozen_make(raw, K.beta != 0);
     bool ef, fc;
     rad_update(K, h, U0, U0, div, fz, out, ef, fc);
   }
@@ -880,7 +885,18 @@ __global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
   const int a = int(au);
   int pc = 0;
   T Uc[4] = {T(0), T(0), T(0), T(0)};
+  // the first wavefront issues the cell's gas and U^m loads before its face
+  FrozenRaw<T> raw{};
+  T Uo[4] = {T(0), T(0), T(0), T(0)};
   if (live) {
+    if (role == 0) {
+      const int s[3] = {1, 1, 1};
+      raw = frozen_load(gas, a, s, K.beta != 0);
+      Uo[0] = Um.E[a];
+      Uo[1] = Um.F[0][a];
+      Uo[2] = Um.F[1][a];
+      Uo[3] = Um.F[2][a];
+    }
     const int q = a / G.n[0];
     const int i = a - q * G.n[0];
     const int j = q % G.n[1];
@@ -906,9 +922,7 @@ __global__ void __launch_bounds__(FS_LANES * FS_MAX_ROLES)
   if (live) {
     T div[4] = {T(0), T(0), T(0), T(0)};
     face_divergence(sh, G, K, lane, div);
-    const int s[3] = {1, 1, 1};
-    const Frozen<T> fz = frozen_at(gas, a, s, K.beta != 0);
-    T Uo[4] = {Um.E[a], Um.F[0][a], Um.F[1][a], Um.F[2][a]};
+    const Frozen<T> fz = frozen_make(raw, K.beta != 0);
     T out[4];
     rad_update(K, h, Uo, Uc, div, fz, out, ef, fc);
     Um.E[a] = out[0];
