@@ -559,13 +559,7 @@ rhdk::ExchConst exch_const(const rhd_t* h, double chat, double dt) {
   return X;
 }
 
-// Refill the per-cell opacities from the law (RHD_OPACITY_LAW) for the current state.
-template <typename T>
-int enqueue_opacity_law(rhd_t* h) {
-  if (!(h->p.flags & RHD_OPACITY_LAW)) return RHD_OK;
-  // a frozen gas that no exchange heats keeps its temperature: the law's values of the
-  // last evaluation still hold
-  if (h->law_fresh) return RHD_OK;
+rhdk::OpacityLaw law_params(const rhd_t* h) {
   const rhd_params& p = h->p;
   rhdk::OpacityLaw L;
   L.k0 = p.kappa_law[0];
@@ -577,8 +571,19 @@ int enqueue_opacity_law(rhd_t* h) {
   L.T_iso = p.iso_cs * p.iso_cs / p.r_gas;
   L.cv_4 = (p.flags & RHD_GAS_CV_T3) ? 4.0 / p.cv_alpha : 0.0;
   L.mode = (p.flags & RHD_ISOTHERMAL) ? 1 : ((p.flags & RHD_GAS_CV_T3) ? 2 : 0);
+  return L;
+}
+
+// Refill the per-cell opacities from the law (RHD_OPACITY_LAW) for the current state.
+template <typename T>
+int enqueue_opacity_law(rhd_t* h) {
+  if (!(h->p.flags & RHD_OPACITY_LAW)) return RHD_OK;
+  // a frozen gas that no exchange heats keeps its temperature: the law's values of the
+  // last evaluation still hold
+  if (h->law_fresh) return RHD_OK;
+  const rhd_params& p = h->p;
   hipLaunchKernelGGL(rhdk::k_opacity_law<T>, dim3(blocks_for(h->N, 256)), dim3(256), 0, h->stream,
-                     gas_ptrs<T>(h->b.gas), as<T>(h->b.kP), as<T>(h->b.kF), L, h->N);
+                     gas_ptrs<T>(h->b.gas), as<T>(h->b.kP), as<T>(h->b.kF), law_params(h), h->N);
   HIP_TRY(h, hipGetLastError());
   h->law_fresh = (p.flags & RHD_RAD_ONLY) && (p.flags & RHD_EXCHANGE_MASK) != RHD_EXCHANGE_FULL;
   return RHD_OK;
@@ -595,16 +600,22 @@ int enqueue_pre(rhd_t* h, double dt, double chat) {
   auto rad = rad_ptrs<T>(h->b.rad);
   const T* kFp = h->kappa_scalar ? nullptr : as<T>(h->b.kF);
   const T* kPp = h->kappa_scalar ? nullptr : as<T>(h->b.kP);
-  // an opacity law is evaluated once per gas step, from the state at its start
-  if (int rc = enqueue_opacity_law<T>(h)) return rc;
+  // an opacity law is evaluated once per gas step, from the state at its start; when the
+  // exchange runs, inside it (each cell before its own exchange), one launch fewer
+  const bool exchange = mode == RHD_EXCHANGE_FULL && !iso;
+  const bool law_in_exchange = exchange && (p.flags & RHD_OPACITY_LAW) && !h->law_fresh;
+  if (!law_in_exchange)
+    if (int rc = enqueue_opacity_law<T>(h)) return rc;
 
   // implicit energy exchange over dt_gas (FP64)
-  if (mode == RHD_EXCHANGE_FULL && !iso) {
+  if (exchange) {
     const rhdk::ExchConst X = exch_const(h, chat, dt);
     const int ti = tbegin(h, KC_EXCHANGE, h->N);
     const int eb = std::min(EXCH_BLOCKS, blocks_for(h->N, rhdk::EXCH_THREADS));
+    T* lawP = law_in_exchange ? as<T>(h->b.kP) : nullptr;
+    T* lawF = law_in_exchange ? as<T>(h->b.kF) : nullptr;
     hipLaunchKernelGGL(rhdk::k_exchange<T>, dim3(eb), dim3(rhdk::EXCH_THREADS), 0, h->stream, gas,
-                       rad, kPp, h->kP_s, X, h->N, h->b.exch_partials);
+                       rad, kPp, h->kP_s, X, h->N, h->b.exch_partials, law_params(h), lawP, lawF);
     tend(h, ti);
     hipLaunchKernelGGL(rhdk::k_exchange_final, dim3(1), dim3(rhdk::EXCH_THREADS), 0, h->stream,
                        h->b.exch_partials, eb, h->b.ctr);

@@ -1340,6 +1340,28 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
 
 // Exchange of cell a over X.dt (FP64 whatever T is): new gas energy and E_r, and the
 // solver statistics of the cell added to the running counts.
+// The opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.2.1).
+struct OpacityLaw {
+  double k0, T0, rho0, a, b;
+  double gm1_over_r;  // (gamma - 1) / r_gas: T = gm1_over_r e / rho for the ideal gas
+  double T_iso;       // c_s^2 / r_gas for the isothermal gas
+  double cv_4;        // 4 / cv_alpha when c_v = cv_alpha T^3: T^4 = cv_4 e
+  int mode;           // 0 ideal gas, 1 isothermal, 2 c_v = alpha T^3
+};
+
+// The law's opacity of cell a from its gas temperature and density, in FP64.
+template <typename T>
+__device__ __forceinline__ double law_kappa(const GasPtrs<T>& g, const OpacityLaw& L, int a) {
+  const double rho = double(g.rho[a]);
+  double Tg = L.T_iso;
+  if (L.mode != 1) {
+    const double m0 = double(g.m[0][a]), m1 = double(g.m[1][a]), m2 = double(g.m[2][a]);
+    const double e = double(g.E[a]) - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+    Tg = L.mode == 2 ? sqrt(sqrt(L.cv_4 * e)) : L.gm1_over_r * e / rho;
+  }
+  return L.k0 * pow(Tg / L.T0, L.a) * pow(rho / L.rho0, L.b);
+}
+
 template <typename T>
 __device__ __forceinline__ void exchange_cell(const GasPtrs<T>& Ug, const RadPtrs<T>& Ur,
                                               const T* kP, double kP_s, const ExchConst& X, int a,
@@ -1377,12 +1399,21 @@ constexpr int EXCH_STATS = 4;
 template <typename T>
 __global__ void __launch_bounds__(EXCH_THREADS) k_exchange(GasPtrs<T> Ug, RadPtrs<T> Ur,
                                                            const T* kP, double kP_s, ExchConst X,
-                                                           int N, unsigned long long* part) {
+                                                           int N, unsigned long long* part,
+                                                           OpacityLaw L, T* lawP, T* lawF) {
   __shared__ unsigned long long sh[EXCH_STATS][EXCH_THREADS / 64];
   unsigned n_th1 = 0, n_bis = 0, n_it = 0, it_max = 0;
   const int stride = int(gridDim.x * blockDim.x);
-  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride)
+  for (int a = int(blockIdx.x * blockDim.x + threadIdx.x); a < N; a += stride) {
+    if (lawP) {
+      // the opacity law from the state before the exchange, as k_opacity_law would leave
+      // it; the exchange then reads kappa_P back from the same array (kP == lawP)
+      const T k = T(law_kappa(Ug, L, a));
+      lawP[a] = k;
+      lawF[a] = k;
+    }
     exchange_cell(Ug, Ur, kP, kP_s, X, a, n_th1, n_bis, n_it, it_max);
+  }
   unsigned long long v[EXCH_STATS] = {n_th1, n_bis, n_it, it_max};
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -1570,14 +1601,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_vmax_final(const T* partials, i
 // opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.2.1)
 // ---------------------------------------------------------------------------
 
-struct OpacityLaw {
-  double k0, T0, rho0, a, b;
-  double gm1_over_r;  // (gamma - 1) / r_gas: T = gm1_over_r e / rho for the ideal gas
-  double T_iso;       // c_s^2 / r_gas for the isothermal gas
-  double cv_4;        // 4 / cv_alpha when c_v = cv_alpha T^3: T^4 = cv_4 e
-  int mode;           // 0 ideal gas, 1 isothermal, 2 c_v = alpha T^3
-};
-
 // The one absorption opacity of every cell (kappa_P = kappa_F) from its gas temperature
 // and density, in FP64, stored as T.
 template <typename T>
@@ -1585,16 +1608,9 @@ __global__ void __launch_bounds__(256) k_opacity_law(GasPtrs<T> g, T* kP, T* kF,
                                                      int N) {
   const int a = int(blockIdx.x * blockDim.x + threadIdx.x);
   if (a >= N) return;
-  const double rho = double(g.rho[a]);
-  double Tg = L.T_iso;
-  if (L.mode != 1) {
-    const double m0 = double(g.m[0][a]), m1 = double(g.m[1][a]), m2 = double(g.m[2][a]);
-    const double e = double(g.E[a]) - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
-    Tg = L.mode == 2 ? sqrt(sqrt(L.cv_4 * e)) : L.gm1_over_r * e / rho;
-  }
-  const double k = L.k0 * pow(Tg / L.T0, L.a) * pow(rho / L.rho0, L.b);
-  kP[a] = T(k);
-  kF[a] = T(k);
+  const T k = T(law_kappa(g, L, a));
+  kP[a] = k;
+  kF[a] = k;
 }
 
 // ---------------------------------------------------------------------------
