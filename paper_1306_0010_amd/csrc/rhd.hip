@@ -451,6 +451,16 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
   B.mask = h->fixed_mask;
   for (int f = 0; f < 6; ++f)
     for (int q = 0; q < 4; ++q) B.v[f][q] = T(h->bval[f][q]);
+  // a small 1D grid along x runs all nsub subcycles in one workgroup, one launch
+  if (h->variant == RHD_KERNELS_TILED && G.act[0] && !G.act[1] && !G.act[2] &&
+      h->N <= rhdk::run1d_max_cells<T>()) {
+    const int ti = tbegin(h, KC_RUN_1D, (long long)h->N * nsub);
+    hipLaunchKernelGGL(rhdk::k_subcycles_1d<T>, dim3(1), dim3(rhdk::RUN1D_THREADS), 0, h->stream,
+                       rad, rh, view, G, RK, B, hr, nsub, h->b.ctr);
+    tend(h, ti);
+    HIP_TRY(h, hipGetLastError());
+    return RHD_OK;
+  }
   // below ~1e5 cells the per-cell kernels leave most of the chip idle and wait on one
   // thread's chain of faces; the face-split kernels spread a cell's faces over wavefronts.
   // 1D grids keep the per-cell kernels by default: they share their device code with the
@@ -983,6 +993,9 @@ int autotune_impl(rhd_t* h, double chat, double dt_rad, int reps) {
   int nc = 0;
   cands[nc++] = {RHD_KERNELS_PER_CELL, 8, 16};
   cands[nc++] = {RHD_KERNELS_FACE_SPLIT, 8, 16};
+  // on grids the tiled kernels do not take, the default choice (the one-workgroup kernel
+  // on a small 1D grid, face-split or per-cell by size otherwise)
+  if (!(three_d && !h->fixed_mask && h->tile_ok)) cands[nc++] = {RHD_KERNELS_TILED, 8, 8};
   if (three_d && !h->fixed_mask && h->tile_ok) {
     const int rows_list[3] = {4, 8, 16};
     const int zc_list[4] = {6, 8, 12, 16};

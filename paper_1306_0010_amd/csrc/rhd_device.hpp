@@ -1641,6 +1641,47 @@ constexpr int run1d_max_cells() {
 // result is the same bit for bit; what goes is the launch latency between the stages,
 // which dominates at these sizes. Every loop runs a bounded count, so the workgroup
 // always finishes. Exchange statistics go to part[0 .. EXCH_STATS) as one block record.
+// ns radiation Van Leer subcycles of length hr on a 1D grid along x by one workgroup of
+// RUN1D_THREADS threads (thread tid): each stage a loop over the cells with a barrier
+// after it, the per-cell device code of k_rad_predict and k_rad_correct. nef and nfc
+// count the E_r floors and flux clamps of the thread's cells.
+template <typename T>
+__device__ __forceinline__ void subcycles_1d(const RadPtrs<T>& Um, const RadPtrs<T>& Uh,
+                                             const GasView<T>& view, const Geom& G,
+                                             const RadConst<T>& K, const FixedFaces<T>& B,
+                                             double hr, int ns, int tid, unsigned long long& nef,
+                                             unsigned long long& nfc) {
+  const int n0 = G.n[0], g0 = G.g[0];
+  const T hp = T(0.5 * hr), hc = T(hr);
+  for (int m = 0; m < ns; ++m) {
+    for (int p = tid; p < n0 + 2 * g0; p += RUN1D_THREADS)
+      rad_predict_cell(Um, Uh, view, G, K, B, hp, p - g0, 0, 0);
+    __syncthreads();
+    for (int a = tid; a < n0; a += RUN1D_THREADS) {
+      bool ef = false, fc = false;
+      rad_correct_cell(Um, Uh, view, G, K, hc, a, 0, 0, ef, fc);
+      nef += ef ? 1ull : 0ull;
+      nfc += fc ? 1ull : 0ull;
+    }
+    __syncthreads();
+  }
+}
+
+// The ns subcycles of one gas step of a small 1D grid along x in one launch of one
+// workgroup (in place of 2 ns launches of the per-cell kernels, whose results it gives
+// bit for bit).
+template <typename T>
+__global__ void __launch_bounds__(RUN1D_THREADS) k_subcycles_1d(RadPtrs<T> Um, RadPtrs<T> Uh,
+                                                                GasView<T> view, Geom G,
+                                                                RadConst<T> K, FixedFaces<T> B,
+                                                                double hr, int ns,
+                                                                unsigned long long* ctr) {
+  unsigned long long nef = 0, nfc = 0;
+  subcycles_1d(Um, Uh, view, G, K, B, hr, ns, int(threadIdx.x), nef, nfc);
+  wave_add(ctr + CTR_RAD_EFLOOR, nef);
+  wave_add(ctr + CTR_RAD_FCLAMP, nfc);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RUN1D_THREADS) k_run_1d(GasPtrs<T> Ug, RadPtrs<T> Um,
                                                           RadPtrs<T> Uh, GasView<T> view, Geom G,
@@ -1651,7 +1692,7 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_run_1d(GasPtrs<T> Ug, RadPtrs
                                                           unsigned long long* ctr) {
   __shared__ unsigned long long sh[EXCH_STATS][RUN1D_THREADS / 64];
   const int tid = int(threadIdx.x);
-  const int n0 = G.n[0], g0 = G.g[0];
+  const int n0 = G.n[0];
   unsigned n_th1 = 0, n_bis = 0, n_it = 0, it_max = 0;
   unsigned long long nef = 0, nfc = 0;
   for (int k = 0; k < nsteps; ++k) {
@@ -1671,20 +1712,7 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_run_1d(GasPtrs<T> Ug, RadPtrs
     for (int f = 0; f < 6; ++f)
 #pragma unroll
       for (int q = 0; q < 4; ++q) B.v[f][q] = steps[k].bv[f][q];
-    const double hr = dt / ns;
-    const T hp = T(0.5 * hr), hc = T(hr);
-    for (int m = 0; m < ns; ++m) {
-      for (int p = tid; p < n0 + 2 * g0; p += RUN1D_THREADS)
-        rad_predict_cell(Um, Uh, view, G, K, B, hp, p - g0, 0, 0);
-      __syncthreads();
-      for (int a = tid; a < n0; a += RUN1D_THREADS) {
-        bool ef = false, fc = false;
-        rad_correct_cell(Um, Uh, view, G, K, hc, a, 0, 0, ef, fc);
-        nef += ef ? 1ull : 0ull;
-        nfc += fc ? 1ull : 0ull;
-      }
-      __syncthreads();
-    }
+    subcycles_1d(Um, Uh, view, G, K, B, dt / ns, ns, tid, nef, nfc);
   }
   wave_add(ctr + CTR_RAD_EFLOOR, nef);
   wave_add(ctr + CTR_RAD_FCLAMP, nfc);

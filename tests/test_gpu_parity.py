@@ -269,6 +269,50 @@ def test_face_split_kernels_equal_per_cell_kernels(name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["one_d_exchange", "pulse_beta_tau", "pulse_fixed_face"])
+def test_one_workgroup_subcycles_equal_per_cell_kernels(name, precision):
+    """A small 1D grid along x runs the subcycles of a step in one workgroup by default,
+    with the per-cell kernels' device code: the states and counters agree bit for bit
+    with the per-cell kernels', on a coupled step with the exchange, the pulse with its
+    O(beta tau) terms, and a rad-only grid with a fixed face."""
+    announce(f"one-workgroup subcycles vs per cell {name} {precision}")
+    if name == "one_d_exchange":
+        spec, st, chat, steps = one_d_exchange(precision)
+        dt, ns = step_sizes(spec, st, chat)
+    elif name == "pulse_beta_tau":
+        pb = ri.pulse_problem(256, advected=True, beta_tau=True, precision=precision)
+        spec, st, chat, steps = pb["spec"], pb["state"], pb["chat"], 4
+        dt, ns = step_sizes(spec, st, chat)
+    else:
+        spec = ri.default_spec(nx=700, dx=1 / 700, c_light=10.0, exchange="full", rad_only=True,
+                               bc=("fixed", "outflow", "periodic", "periodic", "periodic",
+                                   "periodic"), precision=precision)
+        st = ri.smooth_random_state(spec, seed=8, amp=0.2, f_amp=0.3, kappa=(2.0, 5.0))
+        spec["bvals"] = [[3.0, 2.5, 0.1, 0.0]] + [[0.0] * 4] * 5
+        chat, steps = 10.0, 3
+        dt, ns = step_sizes(spec, st, chat)
+    runs = []
+    for v in (VARIANTS["per_cell"], (P.RHD_KERNELS_TILED, 8, 8)):
+        with P.Solver(spec) as s:
+            s.set_kernel_variant(*v)
+            s.set_state(st)
+            if "bvals" in spec:
+                s.set_boundary(spec["bvals"])
+            for _ in range(steps):
+                s.step(dt, chat, ns)
+            s.sync()
+            runs.append((s.get_state(), s.diagnostics()))
+    (a, da), (b, db) = runs
+    assert ns > 1 and da["subcycles"] == db["subcycles"] == steps * ns
+    for k in ri.FIELDS:
+        if a.get(k) is not None:
+            assert np.array_equal(a[k], b[k]), k
+    for k in ("rad_efloor", "rad_fclamp", "exch_theta1", "exch_bisect", "newton_iters",
+              "nonfinite"):
+        assert da[k] == db[k], k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_c1_gaussian_diffusion_full_run(precision):
     announce(f"c1 {precision}")
     pb = ri.c1_diffusion()
