@@ -251,9 +251,10 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
 #define RHD_KERNELS_TILED     1   /* x-y tiles in LDS marching along z, every face flux once;
                                      3D grids without fixed faces only: other 2D and 3D
                                      grids run the face-split kernels up to 2^17 cells, the
-                                     per-cell ones beyond; 1D grids along x of up to 1024
-                                     cells (FP64) or 2048 (mixed) run all subcycles of a step
-                                     in one workgroup, other 1D grids the per-cell kernels  */
+                                     per-cell ones beyond; 1D grids along x of up to 512
+                                     cells (FP64) or 1024 (mixed) run all subcycles of a step
+                                     in one workgroup when the step has several or the grid
+                                     at most 256 cells, other 1D steps the per-cell kernels */
 #define RHD_KERNELS_FACE_SPLIT 2  /* 64 cells per block, one wavefront per face of a cell,
                                      fluxes met in LDS: for small grids of any dimension    */
 

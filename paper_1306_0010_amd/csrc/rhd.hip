@@ -451,9 +451,12 @@ int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
   B.mask = h->fixed_mask;
   for (int f = 0; f < 6; ++f)
     for (int q = 0; q < 4; ++q) B.v[f][q] = T(h->bval[f][q]);
-  // a small 1D grid along x runs all nsub subcycles in one workgroup, one launch
+  // a small 1D grid along x runs all nsub subcycles in one workgroup, one launch. Measured:
+  // that wins where the subcycles are several or the grid tiny; one subcycle of a few
+  // hundred cells or more, or a grid of more than half a cell per thread (FP64) or one
+  // (FP32), runs faster as the two launches spread over the chip
   if (h->variant == RHD_KERNELS_TILED && G.act[0] && !G.act[1] && !G.act[2] &&
-      h->N <= rhdk::run1d_max_cells<T>()) {
+      h->N <= rhdk::run1d_max_cells<T>() / 2 && (nsub >= 2 || h->N <= 256)) {
     const int ti = tbegin(h, KC_RUN_1D, (long long)h->N * nsub);
     hipLaunchKernelGGL(rhdk::k_subcycles_1d<T>, dim3(1), dim3(rhdk::RUN1D_THREADS), 0, h->stream,
                        rad, rh, view, G, RK, B, hr, nsub, h->b.ctr);

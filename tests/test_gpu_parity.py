@@ -284,7 +284,7 @@ def test_one_workgroup_subcycles_equal_per_cell_kernels(name, precision):
         spec, st, chat, steps = pb["spec"], pb["state"], pb["chat"], 4
         dt, ns = step_sizes(spec, st, chat)
     else:
-        spec = ri.default_spec(nx=700, dx=1 / 700, c_light=10.0, exchange="full", rad_only=True,
+        spec = ri.default_spec(nx=400, dx=1 / 400, c_light=10.0, exchange="full", rad_only=True,
                                bc=("fixed", "outflow", "periodic", "periodic", "periodic",
                                    "periodic"), precision=precision)
         st = ri.smooth_random_state(spec, seed=8, amp=0.2, f_amp=0.3, kappa=(2.0, 5.0))
