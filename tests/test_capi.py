@@ -27,6 +27,24 @@ def test_library_exports_every_declared_function():
     assert sorted(P.EXPORTED) == names
 
 
+def test_binding_constants_match_the_header():
+    """Every integer macro of include/rhd.h that the binding also defines has the same
+    value there (flags, boundary kinds, kernel variants, status codes)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    macros = {}
+    for name, expr in re.findall(r"#define\s+(RHD_[A-Z0-9_]+)\s+(.+)", text):
+        expr = expr.strip()
+        m = re.fullmatch(r"\(?\s*1u?\s*<<\s*(\d+)\s*\)?", expr)
+        if m:
+            macros[name] = 1 << int(m.group(1))
+        elif re.fullmatch(r"-?\d+", expr):
+            macros[name] = int(expr)
+    shared = [n for n in macros if hasattr(P, n)]
+    assert "RHD_KERNELS_FACE_SPLIT" in shared and len(shared) >= 10
+    for n in shared:
+        assert getattr(P, n) == macros[n], n
+
+
 def test_default_params():
     p = P.rhd_default_params(16, 8, 1)
     assert (p.nx, p.ny, p.nz) == (16, 8, 1)
