@@ -155,3 +155,27 @@ def test_relaxation_trajectory_and_order(theta, order):
     assert errs[-1] < (0.02 if order == 1 else 5e-4)
     for s in slopes:
         assert s == pytest.approx(order, abs=0.25)
+
+
+def test_absorption_only_damps_E_with_kappa_P_and_F_with_kappa_F():
+    """Absorption-only mode (Sec. 3.4): E_r decays by absorption alone, dE/dt =
+    -chat rho kappa_P E (Eq. source:stiff:radenergy:soln is its theta-scheme), while F
+    decays with kappa_F (Eq. source:stiff:radmomentum:soln). In a uniform box transport
+    vanishes, so the subcycled result must converge to the two exponentials, at second
+    order for theta = 1/2. Distinct kappa_P and kappa_F make a swap of the two opacities
+    converge to the wrong rate. The gas energy is left alone in this mode."""
+    spec = ri.default_spec(nx=4, dx=0.25, c_light=1.0, exchange="absorb_only", rad_only=True,
+                           theta_F=0.5, bc="periodic")
+    kP, kF, F0, t = 3.0, 0.5, 0.01, 0.5
+    st = ri.uniform_state(spec, rho=1.0, P=1.0, Er=1.0, F=(F0, 0.0, 0.0), kP=kP, kF=kF)
+    errs = []
+    for steps in (16, 32, 64):
+        s2, cnt = oracle.step(spec, st, t / steps, 1.0, 1, steps=steps)
+        assert cnt["rad_fclamp"] == 0 and cnt["rad_efloor"] == 0
+        eE = abs(float(s2["Er"].mean()) / math.exp(-kP * t) - 1.0)
+        eF = abs(float(s2["Fx"].mean()) / (F0 * math.exp(-kF * t)) - 1.0)
+        errs.append((eE, eF))
+        assert np.array_equal(s2["E"], st["E"])
+    assert errs[-1][0] < 1e-3 and errs[-1][1] < 1e-5, errs
+    for a, b in zip(errs, errs[1:]):
+        assert a[0] / b[0] > 3.5 and a[1] / b[1] > 3.5, errs

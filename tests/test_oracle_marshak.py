@@ -127,6 +127,40 @@ def marshak_run():
     chi = (np.arange(128) + 0.5) * spec["dx"] * math.sqrt(3.0)
     return chi, out
 
+@pytest.mark.parametrize("bl,br", [((1.0, 0.3), (0.5, -0.1)), ((0.2, -0.1), (0.9, 0.4))])
+def test_fixed_face_holds_its_state_through_the_half_step(bl, br):
+    """Reading of the fixed (Dirichlet) face: its ghost cells hold the face state in
+    U^m and in the predicted U^{m+1/2}. With the Eddington (P1) closure and no opacity
+    the radiation subsystem is linear with speeds -+a, a = chat/sqrt(3), and the HLL
+    flux of Eq. hyperbolic:hllflux2 with those speeds is the upwind flux: its component
+    along the right-going characteristic w+ = E + sqrt(3) F/c is a w+(U_L), whatever
+    U_R. At a fixed left face the two ghost cells of U^{m+1/2} are equal, so the
+    limited slope of the ghost next to the face is zero and U_L is the face state. With
+    the right face fixed at the state of the cells next to it, the conservative update
+    then moves sum_i w+_i by exactly (dt/dx) a (w+(left face) - w+(right face)) in one
+    subcycle, however the interior varies."""
+    N, c, chat = 16, 1.0, 1.0
+    bc = ("fixed", "fixed") + ("periodic",) * 4
+    spec = ri.default_spec(nx=N, dx=1.0 / N, c_light=c, exchange="none", rad_only=True,
+                           theta_F=1.0, bc=bc, closure="p1",
+                           bvals=((bl[0], bl[1], 0.0, 0.0), (br[0], br[1], 0.0, 0.0))
+                           + ((0.0,) * 4,) * 4)
+    st = ri.uniform_state(spec, rho=1.0, P=1.0, Er=br[0], F=(br[1], 0.0, 0.0), kP=0.0, kF=0.0)
+    x = (np.arange(N) + 0.5) / N
+    st["Er"][0, 0, :] = br[0] + 0.4 * np.exp(-((x - 0.2) / 0.1) ** 2)
+    st["Fx"][0, 0, :] = br[1] + 0.2 * np.cos(9.0 * x) * (x < 0.6)  # right end uniform
+    dt = 0.4 / N / chat
+
+    def wplus(E, F):
+        return E + math.sqrt(3.0) * F / c
+
+    s2, cnt = oracle.step(spec, st, dt, chat, 1)
+    assert cnt["rad_fclamp"] == 0 and cnt["rad_efloor"] == 0
+    moved = float(wplus(s2["Er"], s2["Fx"]).sum() - wplus(st["Er"], st["Fx"]).sum())
+    expect = dt * N * chat / math.sqrt(3.0) * (wplus(*bl) - wplus(*br))
+    assert moved == pytest.approx(expect, rel=1e-13, abs=1e-14)
+
+
 
 def test_marshak_wave_approaches_the_diffusion_solution(marshak_run):
     """The paper's finding: the M1 solution differs from Su & Olson's diffusion solution
