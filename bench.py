@@ -1,22 +1,21 @@
 #!/usr/bin/env python3
-"""Throughput of the operator-split gray M1 radiation-hydrodynamics step on one MI355X.
+"""Throughput of the gray M1 radiation-hydrodynamics hot path on one MI355X.
 
-One benchmark step is one pass of the whole hot path on the 128^3 periodic
-linear-perturbation box (rho = P = E_r = 1, kappa = 10, chat = 20 a0, c = 1e4 a0,
-seeded random-phase perturbations of RMS 1e-4), mixed precision:
-  radiation-modified CFL time step (synchronises once to read v_max)
-  -> FP64 implicit energy exchange -> gas Van Leer predictor and corrector
-  -> nsub (= 20 here) radiation Van Leer subcycles -> second-order gas source
-  correction -> FP64 ledger with non-finite check.
-The state stays resident in HBM; nothing is copied to the host inside the timed
-region except the one v_max value per step.
+Headline: the 256^3 concentrated-source grid (outflow faces, static gas with a Gaussian
+core of peak density 1e3 and sigma = 8 cells, emissivity j = 1 in the central 4^3 cells,
+kappa_F = 1.2766 so that the core column is ~50, chat = c = 1, mixed precision). One
+benchmark step is one radiation-only gas step of 10 Van Leer subcycles (each a predictor
+and a corrector launch) followed by the FP64 ledger with its non-finite check; the
+default 20 timed steps are the workload's 200 subcycles, from its initial state. The
+state stays resident in HBM; nothing is copied to the host inside the timed region.
 
-Prints one JSON line: the radiation zone-update rate (cells x subcycles per second),
-the roofline of the dominant kernel from HIP-event timings of its launches inside the
-timed region (against the FP32 VALU roof, which bounds it, with its algorithmic HBM
-bandwidth beside it), the same for 200 subcycles of the 256^3 concentrated-source grid,
-full gas steps of the 256^3 dusty shell, the served-batch latencies, and the FP64 CPU oracle timed on a bounded sample of the
-same input.
+Prints one JSON line: the radiation zone-update rate (cells x subcycles per second); the
+roofline of the dominant kernel from HIP-event timings of its launches inside a timed
+pass of its own: its algorithmic HBM bytes against the 8 TB/s peak, with its FP32 VALU
+lane-slot rate beside it; the FP64 CPU oracle timed on a bounded sample of the same input
+on the host's cores. Extra keys hold the coupled operator-split step on the 128^3 linear
+box, the 256^3 dusty shell over its 100 gas steps, the served batch of 512 requests with
+its p50/p99 latencies, and the paper's own test problems.
 """
 from __future__ import annotations
 
@@ -38,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # v_rcp/v_sqrt/v_rsq_f32 interleaved with FMAs run at 1/2.9 of the FMA-only rate on
 # gfx950, i.e. about 1.9 slots each)
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+# published MI355X FP32 vector peak (packed FMA: 4 flops per lane and clock)
+FP32_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 # tile shapes (rows, z chunk) that rhd_autotune picked for the two grids on MI355X
@@ -131,21 +132,32 @@ def kernel_table(timing, spec, has_j, kappa_field):
 
 
 def roofline(kernels, spec, has_j, kappa_field, workload):
-    """The dominant kernel against the FP32 VALU roof (it is bound by arithmetic), with
-    its algorithmic HBM bandwidth beside it."""
+    """The dominant radiation kernel: its algorithmic HBM bandwidth (bytes it must move
+    per cell x cells per launch / average launch time) against the 8 TB/s peak, with the
+    measured HBM traffic per launch when the counters were taken on the current kernel
+    sources. Its FP32 VALU lane-slot rate stands beside it: non-packed slots (an FMA is one
+    slot, a reciprocal or square root two) against 256 CUs x 64 lanes x 2.4 GHz =
+    39.3 T slots/s, and, as an upper bound in flops (every slot an FMA of 2 flops),
+    against the published 157.3 TFLOP/s FP32 peak (which counts packed FMAs)."""
     rad = {k: v for k, v in kernels.items() if k.startswith("rad_")}
     dom = max(rad, key=lambda k: rad[k]["share"])
     k = rad[dom]
     bpc = algorithmic_bytes_per_cell(dom, spec, has_j, kappa_field)
     traffic = measured_traffic(dom, workload)
-    return {"bound": "alu", "achieved": k["algorithmic_Tslots_per_s"], "peak": VALU_PEAK_TSLOTS,
-            "unit": "TFLOP/s", "frac": k["algorithmic_Tslots_per_s"] / VALU_PEAK_TSLOTS,
-            "traffic": traffic, "kernel": dom, "avg_us": k["avg_us"],
-            "slots_per_cell": k["slots_per_cell"], "cells_per_launch": k["cells_per_launch"],
-            "unit_note": "FP32 VALU lane slots (non-packed; reciprocal/square root = 2)",
-            "hbm_algorithmic": {"achieved_GBps": k["algorithmic_GBps"], "peak_GBps": HBM_PEAK_GBS,
-                                "frac": k["algorithmic_GBps"] / HBM_PEAK_GBS,
-                                "bytes_per_cell": bpc}}
+    slots = k["algorithmic_Tslots_per_s"]
+    return {"bound": "hbm", "achieved": k["algorithmic_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": k["algorithmic_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": dom, "avg_us": k["avg_us"], "bytes_per_cell": bpc,
+            "cells_per_launch": k["cells_per_launch"],
+            "algorithmic_bytes_per_launch": bpc * k["cells_per_launch"],
+            "traffic_over_algorithmic": None if traffic is None
+            else traffic / (bpc * k["cells_per_launch"]),
+            "valu": {"unit": "T lane-slots/s", "achieved": slots,
+                     "slots_per_cell": k["slots_per_cell"],
+                     "peak_nonpacked": VALU_PEAK_TSLOTS, "frac_nonpacked": slots / VALU_PEAK_TSLOTS,
+                     "flops_upper_bound_TFLOPs": 2.0 * slots,
+                     "published_fp32_peak_TFLOPs": FP32_PEAK_TFLOPS,
+                     "frac_of_published_upper_bound": 2.0 * slots / FP32_PEAK_TFLOPS}}
 
 
 MARSHAK_N = (32, 128, 512, 2048)
@@ -425,10 +437,73 @@ def cpu_baseline_shadow(ri, steps=2000):
             "zone_updates_per_s": 56 * 16 * steps / el, "seconds": el}
 
 
-def cpu_baseline(pb, nz_slab=32):
-    """The FP64 oracle (single thread, as it stands) on a bounded sample of the same
-    input: the first nz_slab z-planes of the 128^3 box as a periodic slab, one full
-    gas step with its CFL subcycles."""
+def host_info():
+    """Cores and CPU model of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def oracle_threads(fn, jobs, threads):
+    """Run fn(job) for every job on `threads` Python threads; the oracle's entry points
+    are ctypes calls, which release the GIL, so the threads run on separate cores.
+    Returns the wall time."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(fn, jobs))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_c3(ri, cut=64, subcycles=20, max_threads=16):
+    """The FP64 oracle (as it stands) on a bounded sample of the headline workload: the
+    central cut^3 cells of the 256^3 concentrated-source input (the core and the
+    emitting cells, outflow faces), one radiation-only gas step of `subcycles`
+    subcycles. Timed once on one thread, then with one copy of the same sample per
+    thread on up to max_threads threads (the host's CPU share)."""
+    import numpy as np
+    import oracle
+    pb = ri.c3_point_source(256, precision="fp64")
+    n = pb["spec"]["nx"]
+    lo = (n - cut) // 2
+    sl = (slice(lo, lo + cut),) * 3
+    spec = dict(pb["spec"], nx=cut, ny=cut, nz=cut, precision="fp64")
+    st = {k: (np.ascontiguousarray(v[sl]) if isinstance(v, np.ndarray) else v)
+          for k, v in pb["state"].items()}
+    dt = pb["dt"] * subcycles
+    info = host_info()
+    threads = max(1, min(max_threads, info["usable_cpus"]))
+
+    def one(_):
+        oracle.step(spec, st, dt, pb["chat"], subcycles)
+
+    el1 = oracle_threads(one, [0], 1)
+    elp = oracle_threads(one, list(range(threads)), threads)
+    zu = cut ** 3 * subcycles
+    return {"value": threads * zu / elp, "unit": "zone-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"central {cut}^3 cells of the 256^3 concentrated-source input (core and "
+                      f"emitting cells, outflow faces), {subcycles} radiation subcycles, FP64; one "
+                      f"copy per thread on {threads} threads ({elp:.1f} s wall), and one thread "
+                      f"alone ({el1:.1f} s)",
+            "single_core_value": zu / el1, **info}
+
+
+def cpu_baseline_c2(pb, nz_slab=32):
+    """The FP64 oracle (single thread, as it stands) on a bounded sample of the 128^3
+    box: its first nz_slab z-planes as a periodic slab, one full gas step with its CFL
+    subcycles."""
     import oracle
     import numpy as np
     spec = dict(pb["spec"], nz=nz_slab, precision="fp64")
@@ -445,76 +520,159 @@ def cpu_baseline(pb, nz_slab=32):
                       f"128^3 input, FP64, {el:.1f} s"}
 
 
-def c3_measurement(P, ri, stream, subcycles, tune):
-    """The concentrated-source grid (256^3, outflow, static gas with a Gaussian core,
-    central emitting cells, chat = c = 1): one call of `subcycles` radiation subcycles
-    with the state resident on the device, per-kernel HIP-event timing inside it."""
+def c3_headline(P, ri, stream, steps, warmup, nsub, tune):
+    """The concentrated-source grid (256^3): `warmup` untimed steps, then the initial
+    state again and `steps` timed steps of `nsub` radiation subcycles each (rhd_step of
+    a radiation-only gas step: nsub x [predictor, corrector], then the FP64 ledger),
+    bracketed by device synchronisations. A second pass of the same steps with HIP-event
+    timing of every launch gives the per-kernel averages."""
     import torch
     pb = ri.c3_point_source(256)
     spec, chat = pb["spec"], pb["chat"]
-    dt_rad = pb["dt"]
+    dt_gas = pb["dt"] * nsub
     ncell = spec["nx"] * spec["ny"] * spec["nz"]
     with P.Solver(spec, stream=stream.cuda_stream) as s:
         s.set_state(pb["state"])
         if tune:
-            tile = s.autotune(chat, dt_rad, 3) + ("autotune",)
+            tile = s.autotune(chat, pb["dt"], 3) + ("autotune",)
         else:
             tile = (P.RHD_KERNELS_TILED,) + TILE_C3 + ("fixed",)
             s.set_kernel_variant(*tile[:3])
-        s.step(dt_rad * 4, chat, 4)  # warm-up
+        for _ in range(warmup):
+            s.step(dt_gas, chat, nsub)
+        s.set_state(pb["state"])
         s.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.step(dt_rad * subcycles, chat, subcycles)
+        for _ in range(steps):
+            s.step(dt_gas, chat, nsub)
         s.sync()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         diag = s.diagnostics()
-        # per-kernel HIP-event timing in a pass of its own
+        s.set_state(pb["state"])
         P.rhd_set_timing(s.h, 1)
-        nt = min(subcycles, 50)
-        s.step(dt_rad * nt, chat, nt)
+        for _ in range(steps):
+            s.step(dt_gas, chat, nsub)
         s.sync()
         timing = P.rhd_get_timing(s.h)
+        P.rhd_set_timing(s.h, 0)
     kernels = kernel_table(timing, spec, True, False)
-    out = {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]],
-           "subcycles": subcycles, "value": ncell * subcycles / el, "unit": "zone-updates/s",
-           "elapsed_s": el, "roofline": roofline(kernels, spec, True, False, pb["name"]),
-           "kernels": {k: v for k, v in kernels.items() if k.startswith("rad_")},
-           "nonfinite": diag["nonfinite"]}
-    out["kernels_choice"] = {"tile_rows": tile[1], "zchunk": tile[2], "picked_by": tile[3]}
-    return out
+    rl = roofline(kernels, spec, True, False, pb["name"])
+    sub_bytes = sum(algorithmic_bytes_per_cell(k, spec, True, False) * kernels[k]["cells_per_launch"]
+                    for k in ("rad_predict", "rad_correct"))
+    sub_us = kernels["rad_predict"]["avg_us"] + kernels["rad_correct"]["avg_us"]
+    return {"pb": pb, "elapsed": el, "zone_updates": ncell * nsub * steps, "diag": diag,
+            "kernels": kernels, "roofline": rl, "tile": tile,
+            "subcycle": {"us": sub_us, "algorithmic_bytes": sub_bytes,
+                         "algorithmic_GBps": sub_bytes / (sub_us * 1e-6) / 1e9,
+                         "zone_updates_per_s_from_kernels": ncell / (sub_us * 1e-6)}}
 
 
-def c4_measurement(P, ri, stream, steps):
+def c2_measurement(P, ri, stream, steps=10, warmup=3, precision="mixed", n=128):
+    """The coupled operator-split step on the 128^3 periodic linear-perturbation box
+    (CFL step with one v_max read per gas step, FP64 exchange, gas Van Leer, 20 radiation
+    subcycles, gas source correction, FP64 ledger): `steps` gas steps after `warmup`,
+    then a pass with per-kernel HIP-event timing."""
+    import torch
+    pb = ri.c2_linear_box(n, precision=precision)
+    spec, chat = pb["spec"], pb["chat"]
+    ncell = spec["nx"] * spec["ny"] * spec["nz"]
+    with P.Solver(spec, stream=stream.cuda_stream) as s:
+        s.set_state(pb["state"])
+        s.set_kernel_variant(P.RHD_KERNELS_TILED, *TILE_C2)
+
+        def one():
+            dt, ns = s.suggest_dt(chat)
+            s.step(dt, chat, ns)
+            return ns
+
+        for _ in range(warmup):
+            one()
+        s.set_state(pb["state"])
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sub = sum(one() for _ in range(steps))
+        s.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diag = s.diagnostics()
+        s.set_state(pb["state"])
+        P.rhd_set_timing(s.h, 1)
+        for _ in range(steps):
+            one()
+        s.sync()
+        timing = P.rhd_get_timing(s.h)
+        P.rhd_set_timing(s.h, 0)
+    kernels = kernel_table(timing, spec, False, False)
+    return {"workload": pb["name"], "grid": [n, n, n], "precision": precision,
+            "gas_steps": steps, "subcycles_per_step": sub / steps,
+            "value": ncell * sub / el, "unit": "zone-updates/s",
+            "gas_step_zone_updates_per_s": ncell * steps / el, "ms_per_gas_step": 1e3 * el / steps,
+            "roofline": roofline(kernels, spec, False, False, pb["name"]), "kernels": kernels,
+            "kernel_ms_per_step": sum(t["total_ms"] for t in timing.values()) / steps,
+            "nonfinite": diag["nonfinite"], "cache_note": "the 128^3 working set (~80 MB) fits "
+            "in the 256 MB memory-side cache: its HBM figures are cache-resident"}
+
+
+def c4_measurement(P, ri, stream, steps, over=20.0):
     """The dusty-shell grid (256^3, isothermal gas, outflow faces, radiative equilibrium,
-    lognormal shell and a central source, chat = 20 v_max at t = 0): `steps` full gas
-    steps with CFL-limited subcycles, the state resident on the device."""
+    lognormal shell and a central source). chat is held fixed through the run (Sec. 3.2),
+    at `over` times the largest v_max of a pilot run of the same `steps` gas steps, which
+    itself holds chat at `over` times the initial v_max: the source accelerates the gas,
+    so v_max grows through the run. The timed run then takes `steps` CFL-limited gas steps
+    with nsub = ceil(chat / v_max) subcycles each from the initial state, the state
+    resident on the device; one v_max read per gas step."""
     import torch
     pb = ri.c4_dusty_shell(256)
     spec = pb["spec"]
     ncell = spec["nx"] * spec["ny"] * spec["nz"]
-    with P.Solver(spec, stream=stream.cuda_stream) as s:
-        s.set_state(pb["state"])
-        s.suggest_dt(1.0)
-        chat = pb["chat_over_vmax"] * s.diagnostics()["vmax"]
-        s.set_kernel_variant(P.RHD_KERNELS_TILED, *TILE_C3)
-        dt, ns = s.suggest_dt(chat)
-        s.step(dt, chat, ns)  # warm-up step
-        s.sync()
-        torch.cuda.synchronize()
-        sub = 0
-        t0 = time.perf_counter()
+
+    def run(s, chat, record):
+        vmax, nsubs = [], []
         for _ in range(steps):
             dt, ns = s.suggest_dt(chat)
+            if record:
+                vmax.append(s.diagnostics()["vmax"])
             s.step(dt, chat, ns)
-            sub += ns
+            nsubs.append(ns)
+        return vmax, nsubs
+
+    with P.Solver(spec, stream=stream.cuda_stream) as s:
+        s.set_kernel_variant(P.RHD_KERNELS_TILED, *TILE_C3)
+        s.set_state(pb["state"])
+        s.suggest_dt(1.0)
+        v0 = s.diagnostics()["vmax"]
+        chat0 = over * v0
+        t0 = time.perf_counter()
+        pilot_v, pilot_n = run(s, chat0, True)
+        pilot_s = time.perf_counter() - t0
+        chat = over * max(pilot_v)
+        s.set_state(pb["state"])
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, nsubs = run(s, chat, False)
         s.sync()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         diag = s.diagnostics()
-    return {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]], "gas_steps": steps,
-            "subcycles_per_step": sub / steps, "chat": chat, "value": ncell * sub / el,
+        # the v_max trajectory of the timed run, outside the clock
+        s.set_state(pb["state"])
+        vmax, _ = run(s, chat, True)
+        s.sync()
+    sub = sum(nsubs)
+    ratio = [chat / v for v in vmax]
+    return {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]],
+            "gas_steps": steps, "chat": chat,
+            "chat_choice": f"{over:g} x the largest v_max of a {steps}-step pilot run at "
+                           f"chat = {over:g} x v_max(t=0) = {chat0:.4g} (pilot: v_max from "
+                           f"{pilot_v[0]:.4g} to {max(pilot_v):.4g}, mean nsub "
+                           f"{sum(pilot_n) / steps:.1f}, {pilot_s:.1f} s)",
+            "subcycles": sub, "subcycles_per_step": sub / steps, "nsub_min": min(nsubs),
+            "nsub_max": max(nsubs), "chat_over_vmax_min": min(ratio),
+            "chat_over_vmax_max": max(ratio), "value": ncell * sub / el,
             "unit": "zone-updates/s", "gas_step_zone_updates_per_s": ncell * steps / el,
             "elapsed_s": el, "nonfinite": diag["nonfinite"],
             "tile": {"tile_rows": TILE_C3[0], "zchunk": TILE_C3[1]}}
@@ -525,88 +683,101 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving(count, load):
+def c5_prepare(count, workers):
+    """The seeded perturbations of the served stream's requests, synthesised on `workers`
+    processes forked before anything touches the GPU (each request's two random-phase
+    fields take up to a second at 192^3)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    import rhd_inputs as ri
+    reqs = ri.c5_requests(count=count)
+    t0 = time.perf_counter()
+    ctx = multiprocessing.get_context("fork")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        pert = dict(zip((r["id"] for r in reqs), ex.map(ri.c5_perturbations, reqs, chunksize=4)))
+    return pert, time.perf_counter() - t0
+
+
+SERVE_MODES = ("one_at_a_time", "native_server", "batched", "concurrent")
+
+
+def serving(count, load, pert, modes=("one_at_a_time", "native_server")):
     """The served-batch workload: a stream of independent periodic boxes (32^3..192^3,
     kappa log-uniform in [1, 1e3], chat/a0 in [5, 50], 20 gas steps each). The
     one-at-a-time capacity is measured first with every request queued at t = 0; the
     Poisson arrivals are then scaled so that the offered load is ``load`` times that
-    capacity, and the same stream is served with packed-tile batching, with concurrent
-    per-solve streams, through the native server and one at a time. The capacity of each
-    mode (all requests queued at t = 0) closes the measurement."""
+    capacity, and the same stream is served in each mode: one at a time (one handle and
+    stream per request, in arrival order), through the native server (continuous
+    batching over packed tile lists), and, when asked, with the Python batching loops
+    (packed tiles, or concurrent per-solve streams). The capacity of each served mode
+    (every request queued at t = 0) closes the measurement."""
     import rhd_inputs as ri
     from paper_1306_0010_amd import serve
 
     reqs = ri.c5_requests(count=count, load=load)
-    problems = {}  # each request's initial state is synthesised once and reused
 
     def make(r):
-        if r["id"] not in problems:
-            problems[r["id"]] = ri.c5_problem(r)
-        return problems[r["id"]]
+        return ri.c5_problem(r, perturbations=pert[r["id"]], compact=True)
 
+    fns = {"one_at_a_time": lambda rs: serve.serve_serial(rs, make, variant=serve.DEFAULT_VARIANT),
+           "native_server": lambda rs: serve.serve_native(rs, make),
+           "batched": lambda rs: serve.serve_batched(rs, make),
+           "concurrent": lambda rs: serve.serve_concurrent(rs, make,
+                                                           variant=serve.DEFAULT_VARIANT)}
     at_zero = [dict(r, arrival=0.0) for r in reqs]
-    cap, _ = serve.serve_serial(at_zero, make, variant=serve.DEFAULT_VARIANT)
+    cap, _ = fns["one_at_a_time"](at_zero)
     service = cap["elapsed_s"] / count
     progress(f"serving: one-at-a-time capacity measured ({cap['elapsed_s']:.1f} s)")
     timed = [dict(r, arrival=r["arrival"] * service) for r in reqs]
-    batched, _ = serve.serve_batched(timed, make)
-    progress("serving: batched stream done")
-    concurrent, _ = serve.serve_concurrent(timed, make, variant=serve.DEFAULT_VARIANT)
-    progress("serving: concurrent stream done")
-    native, _ = serve.serve_native(timed, make)
-    progress("serving: native-server stream done")
-    serial, _ = serve.serve_serial(timed, make, variant=serve.DEFAULT_VARIANT)
-    progress("serving: one-at-a-time stream done")
-    # capacity: every request queued at t = 0
-    cap_b, _ = serve.serve_batched(at_zero, make)
-    cap_c, _ = serve.serve_concurrent(at_zero, make, variant=serve.DEFAULT_VARIANT)
-    cap_n, _ = serve.serve_native(at_zero, make)
-    progress("serving: capacities measured")
-    capacity = {m: c["zone_updates_per_s"] for m, c in
-                (("batched", cap_b), ("concurrent", cap_c), ("native_server", cap_n),
-                 ("one_at_a_time", cap))}
-    return {"requests": count, "offered_load": load,
-            "one_at_a_time_capacity_requests_per_s": 1.0 / service,
-            "batched": batched, "concurrent": concurrent, "native_server": native,
-            "one_at_a_time": serial,
-            "batched_over_one_at_a_time_zone_updates": batched["zone_updates_per_s"]
-            / serial["zone_updates_per_s"],
-            "concurrent_over_one_at_a_time_zone_updates": concurrent["zone_updates_per_s"]
-            / serial["zone_updates_per_s"],
-            "native_server_over_one_at_a_time_zone_updates": native["zone_updates_per_s"]
-            / serial["zone_updates_per_s"],
-            "capacity_zone_updates_per_s": capacity}
+    out = {"requests": count, "offered_load": load,
+           "one_at_a_time_capacity_requests_per_s": 1.0 / service,
+           "total_zone_updates": cap["zone_updates"]}
+    for m in modes:
+        out[m], _ = fns[m](timed)
+        progress(f"serving: {m} stream done ({out[m]['elapsed_s']:.1f} s)")
+    base = out["one_at_a_time"]["zone_updates_per_s"] if "one_at_a_time" in out else None
+    capacity = {"one_at_a_time": cap["zone_updates_per_s"]}
+    for m in modes:
+        if m == "one_at_a_time":
+            continue
+        if base:
+            out[f"{m}_over_one_at_a_time_zone_updates"] = out[m]["zone_updates_per_s"] / base
+        c, _ = fns[m](at_zero)
+        capacity[m] = c["zone_updates_per_s"]
+        progress(f"serving: {m} capacity measured ({c['elapsed_s']:.1f} s)")
+    out["capacity_zone_updates_per_s"] = capacity
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
-    ap.add_argument("--n", type=int, default=128, help="grid side of the box (default 128)")
-    ap.add_argument("--serve-requests", type=int, default=48,
-                    help="requests in the served-batch measurement (0 skips it; 512 is the "
-                         "full stream)")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps of the headline (10 radiation subcycles each)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nsub", type=int, default=10,
+                    help="radiation subcycles per headline step (default 10)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the served-batch measurement (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=1.2,
                     help="offered load as a multiple of the one-at-a-time capacity")
+    ap.add_argument("--serve-modes", default="one_at_a_time,native_server",
+                    help="comma-separated served modes: " + ", ".join(SERVE_MODES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-marshak", action="store_true",
                     help="skip the timings of the paper's own test problems (Marshak wave, "
                          "shadow, pulse advection, expanding shell)")
-    ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tile shapes by timing the candidates (rhd_autotune) instead "
                          "of the shapes the tuner picked for these grids before")
-    ap.add_argument("--c3-subcycles", type=int, default=200,
-                    help="radiation subcycles of the 256^3 point-source measurement (0 skips it)")
-    ap.add_argument("--c4-steps", type=int, default=5,
+    ap.add_argument("--c4-steps", type=int, default=100,
                     help="gas steps of the 256^3 dusty-shell measurement (0 skips it)")
-    ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell"),
-                    help="run only this test problem's timing and print its record (for "
+    ap.add_argument("--no-c2", action="store_true", help="skip the 128^3 coupled box")
+    ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell", "c2", "c4"),
+                    help="run only this workload's timing and print its record (for "
                          "profiling one workload)")
-    ap.add_argument("--c3-only", action="store_true",
-                    help="run only the 256^3 point-source measurement and print its line")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline (no CPU baseline) and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB once "
                          "(device to device): the reference dispatch for scaling hardware "
@@ -614,16 +785,32 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU: a multi-GPU run is not "
+        print(json.dumps({"error": "this build runs on one GPU: a run on several GPUs is not "
                                    "implemented (the one-GPU path is --gpus 1)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import numpy as np
+    import rhd_inputs as ri
+
+    # host-only work first, before anything touches the GPU: the oracle baseline of the
+    # headline, and the served stream's inputs (synthesised on forked processes)
+    only = args.only or args.headline_only
+    cpu = None
+    if not args.no_cpu_baseline and not only:
+        cpu = cpu_baseline_c3(ri)
+        progress(f"oracle timed on the headline sample ({cpu['cores']} threads)")
+    pert = None
+    modes = [m for m in args.serve_modes.split(",") if m]
+    for m in modes:
+        if m not in SERVE_MODES:
+            raise SystemExit(f"unknown served mode {m!r}")
+    if args.serve_requests > 0 and not only:
+        pert, el = c5_prepare(args.serve_requests, max(1, min(16, host_info()["usable_cpus"])))
+        progress(f"served stream synthesised ({el:.1f} s)")
+
     import torch
 
     import paper_1306_0010_amd as P
-    import rhd_inputs as ri
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
@@ -633,33 +820,10 @@ def main():
 
     if args.only:
         fn = {"marshak": marshak_timing, "shadow": shadow_timing, "pulse": pulse_timing,
-              "shell": shell_timing}[args.only]
+              "shell": shell_timing, "c2": c2_measurement,
+              "c4": lambda P_, ri_, st_: c4_measurement(P_, ri_, st_, args.c4_steps)}[args.only]
         print(json.dumps({args.only: fn(P, ri, stream)}), flush=True)
         return
-
-    if args.c3_only:
-        print(json.dumps(c3_measurement(P, ri, stream, max(1, args.c3_subcycles),
-                                        args.autotune)), flush=True)
-        return
-
-    pb = ri.c2_linear_box(args.n, precision=args.precision)
-    spec, chat = pb["spec"], pb["chat"]
-    ncell = spec["nx"] * spec["ny"] * spec["nz"]
-    solver = P.Solver(spec, stream=stream.cuda_stream)
-    solver.set_state(pb["state"])
-    h = solver.h
-
-    def one_step():
-        dt, ns = solver.suggest_dt(chat)
-        solver.step(dt, chat, ns)
-        return ns
-
-    if args.autotune:
-        dt0, ns0 = solver.suggest_dt(chat)
-        tile = solver.autotune(chat, dt0 / ns0, 3) + ("autotune",)
-    else:
-        tile = (P.RHD_KERNELS_TILED,) + TILE_C2 + ("fixed",)
-        solver.set_kernel_variant(*tile[:3])
 
     if args.copy_calibration_mib > 0:
         # two reference dispatches of known size: a device-to-device copy and an
@@ -674,34 +838,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        one_step()
-    solver.sync()
-    torch.cuda.synchronize()
-
-    subcycles = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        subcycles += one_step()
-    torch.cuda.synchronize()
-    solver.sync()
-    elapsed = time.perf_counter() - t0
-    diag = solver.diagnostics()
-    timing = {}
-    if not args.no_kernel_timing:
-        # per-kernel HIP-event timing in a pass of its own, so that the event records
-        # do not sit between the kernels of the timed region
-        P.rhd_set_timing(h, 1)
-        for _ in range(args.steps):
-            one_step()
-        solver.sync()
-        timing = P.rhd_get_timing(h)
-        P.rhd_set_timing(h, 0)
-    solver.close()
-    progress(f"headline workload timed ({elapsed:.2f} s)")
-
-    value = ncell * subcycles / elapsed
+    hl = c3_headline(P, ri, stream, args.steps, args.warmup, args.nsub, args.autotune)
+    progress(f"headline timed ({hl['elapsed']:.3f} s)")
+    pb, tile = hl["pb"], hl["tile"]
+    spec = pb["spec"]
+    value = hl["zone_updates"] / hl["elapsed"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -709,43 +850,40 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * hl["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "mixed" else "f64",
-        "dtype_detail": ("f32 state and stencils, f64 energy exchange and ledger"
-                         if args.precision == "mixed" else "f64 throughout"),
+        "dtype": "f32",
+        "dtype_detail": "f32 state and stencils, f64 ledger (no exchange in this workload)",
         "data": "synthetic",
         "config": {"workload": pb["name"], "grid": [spec["nx"], spec["ny"], spec["nz"]],
-                   "precision": args.precision, "chat": chat, "c": spec["c_light"],
-                   "kappa": 10.0, "subcycles_per_step": subcycles / args.steps,
-                   "gas_step_zone_updates_per_s": ncell * args.steps / elapsed},
+                   "precision": "mixed", "chat": pb["chat"], "c": spec["c_light"],
+                   "kappa_F": 1.2766, "subcycles_per_step": args.nsub,
+                   "subcycles_timed": args.nsub * args.steps,
+                   "kernels": {"variant": "tiled" if tile[0] == P.RHD_KERNELS_TILED else "other",
+                               "tile_rows": tile[1], "zchunk": tile[2], "picked_by": tile[3]}},
+        "roofline": hl["roofline"],
     }
-
-    out["config"]["kernels"] = {"variant": "tiled" if tile[0] == P.RHD_KERNELS_TILED else "per_cell",
-                                "tile_rows": tile[1], "zchunk": tile[2], "picked_by": tile[3]}
-    if timing:
-        kernels = kernel_table(timing, spec, False, False)
-        out["roofline"] = roofline(kernels, spec, False, False, pb["name"])
-        out["kernels"] = kernels
-        out["kernel_ms_per_step"] = sum(t["total_ms"] for t in timing.values()) / args.steps
-
-    if args.precision == "mixed" and args.n == 128:
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    out["kernels"] = hl["kernels"]
+    out["subcycle"] = hl["subcycle"]
+    out["diagnostics"] = {k: hl["diag"][k] for k in ("nonfinite", "rad_fclamp", "rad_efloor")}
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_c2:
+        out["c2_linear_box"] = c2_measurement(P, ri, stream)
+        progress("128^3 coupled box timed")
         out["box_fp64"] = box_fp64_timing(P, ri, stream)
-        progress("FP64 box timed")
-
-    out["diagnostics"] = {k: diag[k] for k in ("nonfinite", "rad_fclamp", "rad_efloor",
-                                               "gas_rhofloor", "gas_pfloor", "exch_theta1",
-                                               "exch_bisect", "newton_max")}
-    if args.c3_subcycles > 0 and args.precision == "mixed":
-        out["c3_point_source"] = c3_measurement(P, ri, stream, args.c3_subcycles, args.autotune)
-        progress("256^3 point source timed")
-    if args.c4_steps > 0 and args.precision == "mixed":
+        progress("128^3 box in FP64 timed")
+    if args.c4_steps > 0:
         out["c4_dusty_shell"] = c4_measurement(P, ri, stream, args.c4_steps)
         progress("256^3 dusty shell timed")
-    if args.serve_requests > 0:
-        out["serving"] = serving(args.serve_requests, args.serve_load)
+    if pert is not None:
+        out["serving"] = serving(args.serve_requests, args.serve_load, pert, modes)
+        del pert
     if not args.no_marshak:
         out["marshak"] = marshak_timing(P, ri, stream)
         progress("Marshak wave timed")
@@ -756,14 +894,14 @@ def main():
         out["shell"] = shell_timing(P, ri, stream)
         progress("expanding shell timed")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pb)
-        progress("oracle timed on the host")
+        if not args.no_c2:
+            out["c2_linear_box"]["cpu_baseline"] = cpu_baseline_c2(ri.c2_linear_box(128))
         if not args.no_marshak:
             out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
             out["shadow"]["cpu_baseline"] = cpu_baseline_shadow(ri)
             out["pulse"]["cpu_baseline"] = cpu_baseline_pulse(ri)
             out["shell"]["cpu_baseline"] = cpu_baseline_shell(ri)
-            progress("oracle timed on the Marshak wave, the shadow, pulse and shell tests")
+        progress("oracle timed on the other workloads")
     print(json.dumps(out), flush=True)
 
 

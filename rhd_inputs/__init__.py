@@ -228,18 +228,38 @@ def c5_requests(count=512, seed=BASE_SEED + 5, sizes=tuple(range(32, 193, 16)),
     return reqs
 
 
-def c5_problem(req, precision="mixed"):
-    """The initial state of one served request (see ``c5_requests``)."""
+def c5_perturbations(req):
+    """The seeded density and E_r perturbations of one served request (random-phase
+    modes over integer wavenumbers 1..8, RMS 1e-4 each), shape (nz, ny, nx)."""
+    shape = (req["nz"], req["ny"], req["nx"])
+    rng = np.random.default_rng(req["seed"])
+    drho = random_phase_field(shape, 1, 8, 1e-4, rng)
+    dEr = random_phase_field(shape, 1, 8, 1e-4, rng)
+    return drho, dEr
+
+
+def c5_spec(req, precision="mixed"):
     a0 = math.sqrt(5.0 / 3.0)
     nx, ny, nz = req["nx"], req["ny"], req["nz"]
-    spec = default_spec(nx=nx, ny=ny, nz=nz, dx=1.0 / nx, dy=1.0 / ny, dz=1.0 / nz,
+    return default_spec(nx=nx, ny=ny, nz=nz, dx=1.0 / nx, dy=1.0 / ny, dz=1.0 / nz,
                         gamma=5.0 / 3.0, c_light=1e4 * a0, exchange="full",
                         precision=precision, bc="periodic")
-    st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=req["kappa"], kF=req["kappa"])
-    rng = np.random.default_rng(req["seed"])
-    shape = st["rho"].shape
-    st["rho"] += random_phase_field(shape, 1, 8, 1e-4, rng)
-    st["Er"] += random_phase_field(shape, 1, 8, 1e-4, rng)
+
+
+def c5_problem(req, precision="mixed", perturbations=None, compact=False):
+    """The initial state of one served request (see ``c5_requests``). With compact, the
+    uniform fields are scalars (broadcast by the consumers) instead of full arrays."""
+    a0 = math.sqrt(5.0 / 3.0)
+    spec = c5_spec(req, precision)
+    drho, dEr = c5_perturbations(req) if perturbations is None else perturbations
+    if compact:
+        st = {"rho": 1.0 + drho, "mx": 0.0, "my": 0.0, "mz": 0.0,
+              "E": 1.0 / (spec["gamma"] - 1.0), "Er": 1.0 + dEr, "Fx": 0.0, "Fy": 0.0,
+              "Fz": 0.0, "kP": np.array([req["kappa"]]), "kF": np.array([req["kappa"]])}
+    else:
+        st = uniform_state(spec, rho=1.0, P=1.0, Er=1.0, kP=req["kappa"], kF=req["kappa"])
+        st["rho"] += drho
+        st["Er"] += dEr
     return dict(name=f"c5_request_{req['id']}", spec=spec, state=st,
                 chat=req["chat_over_a0"] * a0, dt=None, nsub=None, steps=req["steps"])
 

@@ -22,6 +22,7 @@ from scipy.optimize import brentq
 
 import oracle
 import rhd_inputs as ri
+from linear_rhd import linear_rhd_matrix
 
 
 # ---------------------------------------------------------------------------
@@ -146,32 +147,6 @@ def test_point_source_steady_flux():
 # ---------------------------------------------------------------------------
 # linear RHD waves (Sec. 4.3.4)
 # ---------------------------------------------------------------------------
-
-def linear_rhd_matrix(k, g, P0, C, Ch, tau, b):
-    """d/dt of (d rho, d v, d p, d E_r, G = dF/c) for a perturbation exp(i k x) about
-    a static equilibrium (rho0 = a0 = 1, a_R T0^4 = P0), linearised from
-    Eq. mixedframe:graysystem with the closure at f = 0 (P = E_r / 3) and the
-    simplified O(beta tau) term of Eq. m1:simplifiedsource switched by b."""
-    ik = 1j * k
-    bt = b * (4.0 / 3.0) * tau * P0 / C
-    A = np.zeros((5, 5), complex)
-    A[0, 1] = -ik
-    A[1, 1] = -bt
-    A[1, 2] = -ik
-    A[1, 4] = tau
-    A[2, 0] = (g - 1) * C * tau * 4 * P0
-    A[2, 1] = -ik
-    A[2, 2] = -(g - 1) * C * tau * 4 * P0 * g
-    A[2, 3] = (g - 1) * C * tau
-    A[3, 0] = -Ch * tau * 4 * P0
-    A[3, 2] = Ch * tau * 4 * P0 * g
-    A[3, 3] = -Ch * tau
-    A[3, 4] = -Ch * ik
-    A[4, 1] = Ch * bt
-    A[4, 3] = -Ch * ik / 3.0
-    A[4, 4] = -Ch * tau
-    return A
-
 
 def bvp_roots_printed(g, P0, C, Ch, tl):
     """Roots z = a0 k / omega of Eq. radlinearwave:bvp:dispersion as printed."""
@@ -474,3 +449,49 @@ def test_radiation_force_time_centred():
     assert abs(m - m_exact) / m_exact > 1e-4
     F = float(st2["Fx"].mean())
     assert F == pytest.approx(F0 * math.exp(-chat * rk * dt), rel=1e-3)
+
+
+def c2_mode_errors(spec, chat, st0, st, t, kmax):
+    """For every integer wavevector with 1 <= |n| <= kmax (half space): |n|, the distance
+    of the measured Fourier coefficients of (rho - 1, E_r - 1) from the linear-theory
+    prediction, and their change over the run, both over |R0| + |E0|."""
+    from linear_rhd import c2_mode_prediction
+    n = spec["nx"]
+    R0, E0 = np.fft.fftn(st0["rho"] - 1.0), np.fft.fftn(st0["Er"] - 1.0)
+    R1, E1 = np.fft.fftn(st["rho"] - 1.0), np.fft.fftn(st["Er"] - 1.0)
+    rows = []
+    for kz in range(-kmax, kmax + 1):
+        for ky in range(-kmax, kmax + 1):
+            for kx in range(0, kmax + 1):
+                kk = math.sqrt(kx * kx + ky * ky + kz * kz)
+                if kk < 1 or kk > kmax:
+                    continue
+                i = (kz % n, ky % n, kx % n)
+                pr, pe = c2_mode_prediction(spec, chat, 10.0, t, R0[i], E0[i], (kx, ky, kz))
+                amp = abs(R0[i]) + abs(E0[i])
+                rows.append((kk, abs(R1[i] - pr) / amp, abs(E1[i] - pe) / amp,
+                             max(abs(pr - R0[i]), abs(pe - E0[i])) / amp))
+    return np.array(rows)
+
+
+@pytest.mark.slow
+def test_linear_box_modes_follow_linear_theory():
+    """The 3D linear-perturbation box (rho = P = E_r = 1, kappa = 10, chat = 20 a0,
+    c = 1e4 a0, random-phase modes 1 <= |n| <= 8 in rho and E_r) at 32^3, 10 CFL gas
+    steps: every Fourier mode with |n| <= 3 follows the 5x5 linear system of Sec. 4.3.4
+    (acoustic waves with radiative diffusion and the stiff exchange) to within the
+    scheme's truncation error, which grows like (k dx)^2: at most 1 % of the mode's
+    initial amplitude for |n| <= 2 (measured 0.6 %) and 8 % for |n| <= 3 (5 %), while
+    the modes change by 10-80 % over the run."""
+    pb = ri.c2_linear_box(32, precision="fp64")
+    spec, st0, chat = pb["spec"], pb["state"], pb["chat"]
+    st, t = st0, 0.0
+    for _ in range(10):
+        dt, ns, _ = oracle.suggest_dt(spec, st, chat)
+        st, _ = oracle.step(spec, st, dt, chat, ns)
+        t += dt
+    rows = c2_mode_errors(spec, chat, st0, st, t, 3)
+    low = rows[rows[:, 0] <= 2.0 + 1e-9]
+    assert max(low[:, 1].max(), low[:, 2].max()) < 0.01, low
+    assert max(rows[:, 1].max(), rows[:, 2].max()) < 0.08, rows
+    assert low[:, 3].min() > 0.1 and low[:, 3].max() > 10 * low[:, 1].max()
