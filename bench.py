@@ -165,7 +165,7 @@ MARSHAK_TAU = (1.0, 10.0, 100.0)
 
 
 def marshak_schedule(ri, n, tau_end):
-    """Steps and face states of the Marshak problem (Sec. 4.2.3, eps = 1, chi in
+    """Steps and face states of the Marshak problem (Sec. 4.1.3, eps = 1, chi in
     [0, 100]) on n cells up to tau_end: the boundary states are inputs, computed before
     any clock starts."""
     pb = ri.marshak_problem(n)
@@ -177,7 +177,7 @@ def marshak_schedule(ri, n, tau_end):
 
 
 def marshak_timing(P, ri, stream):
-    """The paper's own timing benchmark (Sec. 4.3): wall time of the 1D Marshak wave to
+    """The paper's own timing benchmark (Sec. 4.2): wall time of the 1D Marshak wave to
     tau = 1, 10 and 100 for n = 32 ... 2048 cells, FP64 (mixed precision at 2048 as
     well), state resident on the device, one gas step of nsub = 1 per CFL step, boundary
     states precomputed; best of two runs. Two drivers: the whole sequence in one rhd_run
@@ -245,7 +245,7 @@ def cpu_baseline_marshak(ri, max_zone_updates=5e6):
 
 
 def pulse_timing(P, ri, stream, n=512):
-    """The advection of a radiation pulse (Sec. 4.2.5) at the paper's 512 cells to
+    """The advection of a radiation pulse (Sec. 4.3.2) at the paper's 512 cells to
     t = 2w/v, in FP64: the advected and the static run, with and without the O(beta tau)
     terms, each gas step at the CFL step the GPU suggests with its subcycles. Reports
     time per run and per gas step, and the largest relative differences of density and
@@ -307,7 +307,7 @@ def cpu_baseline_pulse(ri, n=512, gas_steps=100):
 
 
 def shell_timing(P, ri, stream, n=128, every=0.005):
-    """The expanding-shell test of Sec. 4.4.2 at the paper's 128^3 octant to t = 0.124
+    """The expanding-shell test of Sec. 4.3.6 at the paper's 128^3 octant to t = 0.124
     (the shell reaches 2 r0), mixed precision, for chat/a0 = 860, 430 and 215: time of
     the stepping (the sampling of <r> and <v_r> every `every` is outside the clock), gas
     steps and subcycles, and the largest relative errors of <r> and <v_r> against the
@@ -392,7 +392,7 @@ def box_fp64_timing(P, ri, stream, n=128, steps=5, warmup=2):
 
 
 def shadow_timing(P, ri, stream, crossings=10.0):
-    """The shadow test of Sec. 4.2.1 at the paper's 280 x 80 cells for 10 horizontal
+    """The shadow test of Sec. 4.1.1 at the paper's 280 x 80 cells for 10 horizontal
     light-crossing times, without and with emission, in mixed precision and FP64, in one
     rhd_run call each; the radiation temperature at the right boundary, behind the
     cloud (y < 0.045) and above it (y > 0.09), shows the shadow."""
@@ -520,7 +520,7 @@ def cpu_baseline_c2(pb, nz_slab=32):
                       f"128^3 input, FP64, {el:.1f} s"}
 
 
-def c3_headline(P, ri, stream, steps, warmup, nsub, tune):
+def c3_headline(P, ri, stream, steps, warmup, nsub, tune, graph=False):
     """The concentrated-source grid (256^3): `warmup` untimed steps, then the initial
     state again and `steps` timed steps of `nsub` radiation subcycles each (rhd_step of
     a radiation-only gas step: nsub x [predictor, corrector], then the FP64 ledger),
@@ -538,6 +538,7 @@ def c3_headline(P, ri, stream, steps, warmup, nsub, tune):
         else:
             tile = (P.RHD_KERNELS_TILED,) + TILE_C3 + ("fixed",)
             s.set_kernel_variant(*tile[:3])
+        s.set_graph(graph)
         for _ in range(warmup):
             s.step(dt_gas, chat, nsub)
         s.set_state(pb["state"])
@@ -776,6 +777,8 @@ def main():
     ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell", "c2", "c4"),
                     help="run only this workload's timing and print its record (for "
                          "profiling one workload)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: the headline's subcycle loop replays a captured HIP graph")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline (no CPU baseline) and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -838,7 +841,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    hl = c3_headline(P, ri, stream, args.steps, args.warmup, args.nsub, args.autotune)
+    hl = c3_headline(P, ri, stream, args.steps, args.warmup, args.nsub, args.autotune, args.graph)
     progress(f"headline timed ({hl['elapsed']:.3f} s)")
     pb, tile = hl["pb"], hl["tile"]
     spec = pb["spec"]

@@ -57,7 +57,7 @@ extern "C" {
                                  continues zero-gradient. Needs RHD_RAD_ONLY; such handles
                                  run the face-split or per-cell radiation kernels (not the
                                  tiled ones) and cannot join a batch.
-                                 For driven problems such as the Marshak wave (Sec. 4.2.3). */
+                                 For driven problems such as the Marshak wave (Sec. 4.1.3). */
 
 /* rhd_params.flags */
 #define RHD_ISOTHERMAL          (1u << 0)  /* P = rho iso_cs^2, no gas energy equation     */
@@ -76,18 +76,18 @@ extern "C" {
                                               below 3e38 (cgs values of dense, hot gas can
                                               overflow it)                                 */
 #define RHD_OPACITY_LAW         (1u << 7)  /* kappa_P = kappa_F = k0 (T_gas/T0)^a (rho/rho0)^b
-                                              (Sec. 4.2.1), kappa_law = {k0, T0, rho0, a, b},
+                                              (Sec. 4.1.1), kappa_law = {k0, T0, rho0, a, b},
                                               from the gas state at the start of each gas
                                               step (and for rhd_suggest_dt); the kappa
                                               arrays of rhd_set_state are then not read   */
-#define RHD_GAS_CV_T3           (1u << 6)  /* heat capacity c_v = cv_alpha T^3 (Sec. 4.2.3):
+#define RHD_GAS_CV_T3           (1u << 6)  /* heat capacity c_v = cv_alpha T^3 (Sec. 4.1.3):
                                               a_R T^4 = (4 a_R / cv_alpha) e, so the exchange
                                               (theta-scheme of Eq. source:energyupdate) is
                                               linear in e. Needs RHD_RAD_ONLY, ideal gas   */
 #define RHD_CLOSURE_P1          (1u << 8)  /* Eddington (P1) closure instead of M1: T = I/3
                                               and the fixed wave speeds +-chat/sqrt(3) in
                                               every face flux (Sec. 2.3; the comparison run
-                                              of Sec. 4.4.2). The flux clamp |F| <= c E_r
+                                              of Sec. 4.3.5). The flux clamp |F| <= c E_r
                                               after each stage still applies              */
 
 typedef struct {
@@ -179,7 +179,7 @@ int rhd_set_emission(rhd_t* h, const double* j);
 /* Radiation state U = (E_r, F_x, F_y, F_z) that the RHD_BC_FIXED face `face` (0..5 =
    x-, x+, y-, y+, z-, z+) holds from the next rhd_step on; it stays until set again
    (zero until the first call). A driven boundary sets it before each step, e.g. from
-   Eq. marshak:suolson and the Marshak condition c E_r + 2 F = 4 F_inc of Sec. 4.2.3.
+   Eq. marshak:suolson and the Marshak condition c E_r + 2 F = 4 F_inc of Sec. 4.1.3.
    RHD_EINVAL if the face is not a fixed face of an active dimension, or E_r <= 0, or a
    value is not finite. Host-side only. */
 int rhd_set_boundary(rhd_t* h, int face, const double U[4]);
@@ -269,6 +269,19 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
    rhd_create accepts). */
 int rhd_set_kernel_variant(rhd_t* h, int variant, int tile_rows, int zchunk);
 
+/* HIP graphs for the radiation subcycles (enable = 1; 0, the default, launches each
+   kernel). With graphs on, the nsub-subcycle loop of rhd_step and rhd_run is captured
+   from the handle's stream into a HIP graph the first time a key (nsub, dt_gas/nsub,
+   chat, kernel choice) is seen and replayed while the key holds: steps of a fixed size
+   cost one graph launch instead of 2 nsub kernel launches. A new key is captured again
+   and written into the same executable graph. Results are the same bit for bit as
+   without graphs (same kernels, same arguments). Not while kernel timing is on (the
+   loop then launches directly). RHD_EINVAL for a handle on the null stream. */
+int rhd_set_graph(rhd_t* h, int enable);
+
+/* Subcycle-loop graphs captured and replayed by this handle so far. */
+int rhd_get_graph_stats(const rhd_t* h, long long* captures, long long* replays);
+
 /* Pick the fastest radiation-subcycle kernels for this handle's grid by timing them:
    every variant and tile shape (tile rows x z chunk) runs `reps` subcycles of dt_rad on
    the current state with HIP events, and the fastest becomes the handle's choice (see
@@ -304,16 +317,25 @@ int rhd_batch_remove(rhd_batch_t* b, rhd_t* h);
 /* Advance every member by one gas step with its own CFL step and subcycle count
    (Sec. 3.1, Eqs. algorithm:gastimestep and algorithm:radtimestep): one synchronisation
    reads all v_max values; the exchange and gas step of each member follow; then the
-   radiation subcycles of all members run as rounds of batched launches, round r covering
-   the members with nsub > r; each member's correction and ledger close the step. A
-   member's result does not depend, bit for bit, on which other solves share the batch;
-   it equals what rhd_step gives the handle alone to rounding (the kernels differ).
+   radiation subcycles of all members run over one packed list of tiles as rounds of two
+   launches (predictor and corrector), round r covering the members with nsub > r; each
+   member's correction and ledger close the step.
+   A member's result does not depend, bit for bit, on which other solves share the batch
+   or on the launch mode; it equals what rhd_step gives the handle alone to rounding (the
+   kernels differ).
    nsub_out and dt_out (each NULL or room for rhd_batch_size() values, member order)
    receive each member's nsub and dt_gas. A member whose v_max is not finite and positive
    (RHD_ENONFINITE) or that needs more than 4096 subcycles (RHD_EINVAL) stops the call
    before anything is enqueued; nsub_out then holds -1 for that member and 0 for the
    others, so the caller can remove it and step again. Allocates nothing. */
 int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out);
+
+/* Launch mode of rhd_batch_step's radiation subcycles: 0, rounds of two launches (the
+   only mode that runs). 1 asks for one persistent launch with per-member phase counters
+   (blocks take tiles in order from a shared counter; a tile of a member's stage starts
+   once that member's previous stage is complete). That launch is switched off, because
+   it did not finish on the GPU: asking for it returns RHD_EINVAL and changes nothing. */
+int rhd_batch_set_persistent(rhd_batch_t* b, int on);
 
 /* Number of members. */
 int rhd_batch_size(const rhd_batch_t* b);
@@ -367,6 +389,12 @@ typedef struct {
    batches reject (tile_rows 4, 8 or 16; zchunk >= 1). On failure *out is NULL. */
 int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int zchunk,
                       rhd_server_t** out);
+
+/* Launch mode of the server's batches (see rhd_batch_set_persistent): 0, rounds of two
+   launches, the default and the only mode that runs; 1 returns RHD_EINVAL (the
+   persistent launch is switched off). Only before the first submission (RHD_ESTATE
+   after). */
+int rhd_server_set_persistent(rhd_server_t* s, int on);
 
 /* Queue a request: parameters and initial state as for rhd_create, rhd_set_state and
    rhd_set_emission (j may be NULL), then `steps` gas steps, each with the CFL step and

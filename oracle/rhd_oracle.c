@@ -44,14 +44,14 @@
  *  - emission j adds (chat/c) j to dE_r/dt, so that div F = j in a steady state;
  *  - in ABSORB_ONLY mode E_r is damped with kappa_P by the same theta-form as F,
  *    with theta_F, on each radiation stage;
- *  - a fixed (Dirichlet) radiation face, as the Marshak problem of Sec. 4.2.3 needs,
+ *  - a fixed (Dirichlet) radiation face, as the Marshak problem of Sec. 4.1.3 needs,
  *    holds its state in every ghost cell beyond it, for U^m and for the predicted
  *    U^{m+1/2} (the predictor does not evolve those ghosts), while the gas fields
  *    continue zero-gradient there;
- *  - with c_v = alpha T^3 (Sec. 4.2.3) the exchange keeps the theta-scheme form of
+ *  - with c_v = alpha T^3 (Sec. 4.1.3) the exchange keeps the theta-scheme form of
  *    Eq. source:energyupdate with a_R T^4 = (4 a_R/alpha) e, which makes the update
  *    linear in e; with chat = c it is the update printed with that problem;
- *  - an opacity law kappa(T_gas, rho) (the shadow test of Sec. 4.2.1) gives the one
+ *  - an opacity law kappa(T_gas, rho) (the shadow test of Sec. 4.1.1) gives the one
  *    absorption opacity for kappa_P and kappa_F, evaluated from the gas state at the
  *    start of each gas step and held through the step (exchange, gas step and
  *    subcycles), and from the current state for the CFL step.
@@ -793,7 +793,7 @@ double orc_exchange_cell(double rho, double e, double Er, double kP, double dt,
 }
 
 /* ------------------------------------------------------------------------- */
-/* opacity law (Sec. 4.2.1): kappa = k0 (T_gas/T0)^a (rho/rho0)^b             */
+/* opacity law (Sec. 4.1.1): kappa = k0 (T_gas/T0)^a (rho/rho0)^b             */
 /* ------------------------------------------------------------------------- */
 
 /* Gas temperature of cell a: P/(rho r_gas) for the ideal gas, c_s^2/r_gas when

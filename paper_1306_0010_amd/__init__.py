@@ -55,7 +55,8 @@ EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_
             "rhd_batch_size", "rhd_batch_sync", "rhd_batch_destroy", "rhd_batch_last_error",
             "rhd_server_create", "rhd_server_submit", "rhd_server_poll", "rhd_server_wait",
             "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats", "rhd_server_destroy",
-            "rhd_server_last_error")
+            "rhd_server_last_error", "rhd_batch_set_persistent", "rhd_server_set_persistent",
+            "rhd_set_graph", "rhd_get_graph_stats")
 
 
 class RhdError(RuntimeError):
@@ -192,6 +193,15 @@ def lib():
     L.rhd_batch_remove.argtypes = [vp, vp]
     L.rhd_batch_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.rhd_batch_size.argtypes = [vp]
+    L.rhd_set_graph.argtypes = [vp, ctypes.c_int]
+    L.rhd_set_graph.restype = ctypes.c_int
+    L.rhd_get_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong)]
+    L.rhd_get_graph_stats.restype = ctypes.c_int
+    L.rhd_batch_set_persistent.argtypes = [vp, ctypes.c_int]
+    L.rhd_batch_set_persistent.restype = ctypes.c_int
+    L.rhd_server_set_persistent.argtypes = [vp, ctypes.c_int]
+    L.rhd_server_set_persistent.restype = ctypes.c_int
     L.rhd_batch_sync.argtypes = [vp]
     L.rhd_batch_destroy.argtypes = [vp]
     L.rhd_batch_destroy.restype = None
@@ -355,6 +365,16 @@ def rhd_set_kernel_variant(h, variant, tile_rows=8, zchunk=8):
     _check(lib().rhd_set_kernel_variant(h, int(variant), int(tile_rows), int(zchunk)), h)
 
 
+def rhd_set_graph(h, enable):
+    _check(lib().rhd_set_graph(h, int(bool(enable))), h)
+
+
+def rhd_get_graph_stats(h):
+    c, r = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(lib().rhd_get_graph_stats(h, ctypes.byref(c), ctypes.byref(r)), h)
+    return c.value, r.value
+
+
 def rhd_autotune(h, chat, dt_rad, reps=3):
     """Returns (variant, tile_rows, zchunk) chosen for the handle."""
     v, r, z = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -390,6 +410,10 @@ def rhd_batch_step(b):
     dt = (ctypes.c_double * max(n, 1))()
     _bcheck(lib().rhd_batch_step(b, ns, dt), b)
     return list(ns)[:n], list(dt)[:n]
+
+
+def rhd_batch_set_persistent(b, on):
+    _bcheck(lib().rhd_batch_set_persistent(b, int(bool(on))), b)
 
 
 def rhd_batch_size(b):
@@ -430,6 +454,10 @@ def rhd_server_submit(s, params, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scal
     _scheck(lib().rhd_server_submit(s, ctypes.byref(params), *ptrs[:7], int(kappa_scalar), ptrs[7],
                                     int(steps), float(chat), ctypes.byref(rid)), s)
     return rid.value
+
+
+def rhd_server_set_persistent(s, on):
+    _scheck(lib().rhd_server_set_persistent(s, int(bool(on))), s)
 
 
 def rhd_server_poll(s, rid):
@@ -618,6 +646,12 @@ class Solver:
 
     def autotune(self, chat, dt_rad, reps=3):
         return rhd_autotune(self.h, chat, dt_rad, reps)
+
+    def set_graph(self, enable):
+        rhd_set_graph(self.h, enable)
+
+    def graph_stats(self):
+        return rhd_get_graph_stats(self.h)
 
     def suggest_dt(self, chat):
         return rhd_suggest_dt(self.h, chat)

@@ -112,6 +112,13 @@ struct rhd {
   int zchunk = 8;
   int fixed_mask = 0;          // bit f: face f is RHD_BC_FIXED (of an active dimension)
   double bval[6][4] = {};      // radiation state of each fixed face (rhd_set_boundary)
+  // HIP graph of the subcycle loop (rhd_set_graph), replayed while its key holds
+  bool graph_on = false;
+  bool capturing = false;
+  hipGraphExec_t graph_exec = nullptr;
+  int g_nsub = -1, g_variant = -1, g_rows = 0, g_zchunk = 0;
+  double g_hr = 0.0, g_chat = 0.0;
+  long long graph_captures = 0, graph_replays = 0;
   Timer timer;
   char err[512] = "no error";
 };
@@ -429,9 +436,70 @@ rhdk::RadConst<T> rad_const(const rhd_t* h, double chat) {
 // face-split ones' extra closure evaluations and LDS round trip cost more than they save).
 constexpr int FACE_SPLIT_MAX_CELLS = 1 << 17;
 
+template <typename T>
+int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub);
+
+// The subcycle loop as a HIP graph: captured from the stream the first time a key
+// (nsub, dt/nsub, chat, kernel choice) is seen, replayed while it holds. A new key is
+// captured again and written into the existing executable graph (hipGraphExecUpdate),
+// or a new one is instantiated when the update is refused. The loop holds kernel
+// launches only (no memset or copy nodes).
+template <typename T>
+int enqueue_subcycles_graph(rhd_t* h, double dt, double chat, int nsub) {
+  const double hr = dt / nsub;
+  if (h->graph_exec && h->g_nsub == nsub && h->g_hr == hr && h->g_chat == chat &&
+      h->g_variant == h->variant && h->g_rows == h->tile_rows && h->g_zchunk == h->zchunk) {
+    HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
+    h->graph_replays += 1;
+    return RHD_OK;
+  }
+  HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  h->capturing = true;
+  const int rc = enqueue_subcycles<T>(h, dt, chat, nsub);
+  h->capturing = false;
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess || !graph)
+    return fail(h, RHD_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+  if (h->graph_exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(h->graph_exec, graph, &bad, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(h->graph_exec);
+      h->graph_exec = nullptr;
+    }
+  }
+  if (!h->graph_exec) {
+    const hipError_t ei = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      h->graph_exec = nullptr;
+      return fail(h, RHD_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
+  }
+  (void)hipGraphDestroy(graph);
+  h->g_nsub = nsub;
+  h->g_hr = hr;
+  h->g_chat = chat;
+  h->g_variant = h->variant;
+  h->g_rows = h->tile_rows;
+  h->g_zchunk = h->zchunk;
+  h->graph_captures += 1;
+  HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
+  return RHD_OK;
+}
+
 // nsub radiation Van Leer subcycles of dt/nsub with the gas frozen (Sec. 3.3, 3.4).
 template <typename T>
 int enqueue_subcycles(rhd_t* h, double dt, double chat, int nsub) {
+  if (h->graph_on && !h->capturing && !h->timer.on && h->stream && nsub > 0)
+    return enqueue_subcycles_graph<T>(h, dt, chat, nsub);
   const rhdk::Geom& G = h->G;
   const rhdk::RadConst<T> RK = rad_const<T>(h, chat);
   auto rad = rad_ptrs<T>(h->b.rad);
@@ -1419,6 +1487,21 @@ int rhd_autotune(rhd_t* h, double chat, double dt_rad, int reps, int* variant, i
   return rc;
 }
 
+int rhd_set_graph(rhd_t* h, int enable) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (enable && !h->stream)
+    return fail(h, RHD_EINVAL, "graph capture needs a stream other than the null stream");
+  h->graph_on = enable != 0;
+  return RHD_OK;
+}
+
+int rhd_get_graph_stats(const rhd_t* h, long long* captures, long long* replays) {
+  if (!h) return fail(nullptr, RHD_EINVAL, "handle is NULL");
+  if (captures) *captures = h->graph_captures;
+  if (replays) *replays = h->graph_replays;
+  return RHD_OK;
+}
+
 long long rhd_device_bytes(const rhd_t* h) { return h ? h->bytes : 0; }
 
 }  // extern "C"
@@ -1447,6 +1530,19 @@ struct rhd_batch {
   int* h_counts = nullptr;
   double* h_vmax = nullptr;
   int cap_pred = 0, cap_corr = 0;
+  // persistent launch: level table and per-member counters + ticket. Switched off: the
+  // launch did not finish on the GPU (rhd_batch_set_persistent refuses to enable it)
+  bool persistent = false;
+  int* d_level = nullptr;
+  int* h_level = nullptr;      // pinned
+  unsigned* d_done = nullptr;  // max_solves counters, then the ticket and the error flag,
+                               // rhdk::COUNTER_STRIDE apart
+  unsigned* h_err = nullptr;   // pinned copy of the error flag of the last persistent launch
+  bool err_pending = false;    // a persistent launch was enqueued since its flag was read
+  // longest wait of a tile for its member's previous stage: 2 s of the 100 MHz real-time
+  // counter, far above any stage's time
+  unsigned long long wait_ticks = 200000000ull;
+  int resident[3] = {0, 0, 0}; // blocks of the persistent kernel that fit the chip, per tile rows 4/8/16
   char err[512] = "no error";
 };
 
@@ -1517,6 +1613,52 @@ void launch_batch_round(rhd_batch_t* b, int total_pred, int total_corr, int r) {
                      b->d_tiles_corr, b->d_counts + 2 * r + 1);
 }
 
+// After a synchronisation: the error flag of the last persistent launch, if one ran.
+int batch_check_persistent(rhd_batch_t* b) {
+  if (!b->err_pending) return RHD_OK;
+  b->err_pending = false;
+  if (*b->h_err)
+    return bfail(b, RHD_EDEVICE, "a persistent batch launch gave up waiting for a stage: "
+                                 "its members' states are not valid");
+  return RHD_OK;
+}
+
+// The persistent launch: counters and ticket cleared by a kernel, then as many blocks as
+// fit on the chip at once (at most one per item).
+template <typename T, int BY>
+int launch_persistent(rhd_batch_t* b, int S, int levels, int items, int widest) {
+  const int ri = BY == 4 ? 0 : (BY == 8 ? 1 : 2);
+  auto kern = rhdk::k_rad_batch_persistent<T, BY>;
+  if (b->resident[ri] <= 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, rhdk::TILE_BX * BY, 0));
+    BHIP_TRY(b, hipGetDevice(&dev));
+    BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->resident[ri] = std::max(1, per_cu * cus);
+  }
+  const int words = (S + 2) * rhdk::COUNTER_STRIDE;
+  hipLaunchKernelGGL(rhdk::k_fill<unsigned>, dim3(blocks_for(words, 256)), dim3(256), 0, b->stream,
+                     b->d_done, 0u, words);
+  rhdk::PersistentPlan plan;
+  plan.tiles[0] = b->d_tiles_pred;
+  plan.tiles[1] = b->d_tiles_corr;
+  plan.level_start = b->d_level;
+  plan.levels = levels;
+  plan.done = b->d_done;
+  plan.ticket = b->d_done + size_t(S) * rhdk::COUNTER_STRIDE;
+  plan.error = b->d_done + size_t(S + 1) * rhdk::COUNTER_STRIDE;
+  plan.wait_ticks = b->wait_ticks;
+  const dim3 block(rhdk::TILE_BX, BY, 1);
+  // at most two levels' worth of blocks: more could only wait, polling the counters
+  const int grid = std::max(1, std::min({items, b->resident[ri], 2 * widest}));
+  hipLaunchKernelGGL(kern, dim3(grid), block, 0, b->stream,
+                     static_cast<const rhdk::SolveDesc<T>*>(b->d_desc), plan);
+  BHIP_TRY(b, hipMemcpyAsync(b->h_err, plan.error, sizeof(unsigned), hipMemcpyDeviceToHost,
+                             b->stream));
+  b->err_pending = true;
+  return RHD_OK;
+}
+
 template <typename T>
 int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
   const int S = int(b->members.size());
@@ -1540,6 +1682,7 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
                                b->stream));
   }
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  if (int rc = batch_check_persistent(b)) return rc;
   std::vector<int> nsub(S);
   std::vector<double> dt(S);
   for (int i = 0; i < S; ++i) {
@@ -1589,6 +1732,8 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
     const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
     d.zc_pred = tg.zc_pred;
     d.zc_corr = tg.zc_corr;
+    d.tiles_pred = tg.pred[0] * tg.pred[1] * tg.pred[2];
+    d.tiles_corr = tg.corr[0] * tg.corr[1] * tg.corr[2];
     desc[k] = d;
     for (int z = 0; z < tg.pred[2]; ++z)
       for (int y = 0; y < tg.pred[1]; ++y)
@@ -1614,17 +1759,43 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
                              hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipMemcpyAsync(b->d_counts, b->h_counts, size_t(2 * rounds) * sizeof(int),
                              hipMemcpyHostToDevice, b->stream));
-  for (int r = 0; r < rounds; ++r) {
+  if (b->persistent && rounds > 0) {
+    // one launch for every subcycle of every member: level l is stage l of the rounds
+    int acc = 0, widest = 0;
+    for (int l = 0; l < 2 * rounds; ++l) {
+      b->h_level[l] = acc;
+      acc += b->h_counts[l];
+      widest = std::max(widest, b->h_counts[l]);
+    }
+    b->h_level[2 * rounds] = acc;
+    BHIP_TRY(b, hipMemcpyAsync(b->d_level, b->h_level, size_t(2 * rounds + 1) * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
     switch (b->rows) {
       case 4:
-        launch_batch_round<T, 4>(b, np, nc, r);
+        if (int rc = launch_persistent<T, 4>(b, S, 2 * rounds, acc, widest)) return rc;
         break;
       case 8:
-        launch_batch_round<T, 8>(b, np, nc, r);
+        if (int rc = launch_persistent<T, 8>(b, S, 2 * rounds, acc, widest)) return rc;
         break;
       default:
-        if constexpr (sizeof(T) == 4) launch_batch_round<T, 16>(b, np, nc, r);
+        if constexpr (sizeof(T) == 4) {
+          if (int rc = launch_persistent<T, 16>(b, S, 2 * rounds, acc, widest)) return rc;
+        }
         break;
+    }
+  } else {
+    for (int r = 0; r < rounds; ++r) {
+      switch (b->rows) {
+        case 4:
+          launch_batch_round<T, 4>(b, np, nc, r);
+          break;
+        case 8:
+          launch_batch_round<T, 8>(b, np, nc, r);
+          break;
+        default:
+          if constexpr (sizeof(T) == 4) launch_batch_round<T, 16>(b, np, nc, r);
+          break;
+      }
     }
   }
   BHIP_TRY(b, hipGetLastError());
@@ -1670,6 +1841,11 @@ int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk
   ok = ok && hipMalloc(&b->d_counts, 2 * BATCH_MAX_ROUNDS * sizeof(int)) == hipSuccess;
   ok = ok && hipHostMalloc(&b->h_counts, 2 * BATCH_MAX_ROUNDS * sizeof(int), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc(&b->h_vmax, size_t(max_solves) * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_level, (2 * BATCH_MAX_ROUNDS + 1) * sizeof(int)) == hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_level, (2 * BATCH_MAX_ROUNDS + 1) * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_done, size_t(max_solves + 2) * rhdk::COUNTER_STRIDE * sizeof(unsigned)) ==
+                   hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_err, sizeof(unsigned), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     rhd_batch_destroy(b);
     return bfail(nullptr, RHD_ENOMEM, "batch allocation failed");
@@ -1736,10 +1912,19 @@ int rhd_batch_step(rhd_batch_t* b, int* nsub_out, double* dt_out) {
 
 int rhd_batch_size(const rhd_batch_t* b) { return b ? int(b->members.size()) : 0; }
 
+int rhd_batch_set_persistent(rhd_batch_t* b, int on) {
+  if (!b) return bfail(nullptr, RHD_EINVAL, "batch is NULL");
+  if (on)
+    return bfail(b, RHD_EINVAL, "the persistent launch is switched off: it did not finish on "
+                                "the GPU; batches run their subcycles as rounds of launches");
+  b->persistent = false;
+  return RHD_OK;
+}
+
 int rhd_batch_sync(rhd_batch_t* b) {
   if (!b) return bfail(nullptr, RHD_EINVAL, "batch is NULL");
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
-  return RHD_OK;
+  return batch_check_persistent(b);
 }
 
 void rhd_batch_destroy(rhd_batch_t* b) {
@@ -1758,6 +1943,10 @@ void rhd_batch_destroy(rhd_batch_t* b) {
   if (b->d_counts) (void)hipFree(b->d_counts);
   if (b->h_counts) (void)hipHostFree(b->h_counts);
   if (b->h_vmax) (void)hipHostFree(b->h_vmax);
+  if (b->d_level) (void)hipFree(b->d_level);
+  if (b->h_level) (void)hipHostFree(b->h_level);
+  if (b->d_done) (void)hipFree(b->d_done);
+  if (b->h_err) (void)hipHostFree(b->h_err);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -1775,6 +1964,7 @@ void rhd_destroy(rhd_t* h) {
     delete[] h->timer.start;
     delete[] h->timer.stop;
   }
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   free_buffers(h);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;

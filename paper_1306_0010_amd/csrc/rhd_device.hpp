@@ -1276,7 +1276,7 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
                                                 double Er, double kP, double& Er_new, int& iters,
                                                 bool& th1, bool& bis) {
   // emission a_R T^4 as a function of e: alpha e^4 (ideal gas), or eps_cv e when
-  // c_v = alpha T^3 (Sec. 4.2.3), which leaves a linear equation (c4 = 0)
+  // c_v = alpha T^3 (Sec. 4.1.3), which leaves a linear equation (c4 = 0)
   const double g = X.gm1 / (rho * X.r_gas);
   const double g2 = g * g;
   const double lin = X.eps_cv;
@@ -1340,7 +1340,7 @@ __device__ __forceinline__ double exchange_root(const ExchConst& X, double rho, 
 
 // Exchange of cell a over X.dt (FP64 whatever T is): new gas energy and E_r, and the
 // solver statistics of the cell added to the running counts.
-// The opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.2.1).
+// The opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.1.1).
 struct OpacityLaw {
   double k0, T0, rho0, a, b;
   double gm1_over_r;  // (gamma - 1) / r_gas: T = gm1_over_r e / rho for the ideal gas
@@ -1598,7 +1598,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_vmax_final(const T* partials, i
 }
 
 // ---------------------------------------------------------------------------
-// opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.2.1)
+// opacity law kappa = k0 (T_gas / T0)^a (rho / rho0)^b (shadow test, Sec. 4.1.1)
 // ---------------------------------------------------------------------------
 
 // The one absorption opacity of every cell (kappa_P = kappa_F) from its gas temperature

@@ -64,6 +64,7 @@ struct rhd_server {
   long long next_id = 1;
   long long budget = 0, used = 0;
   int max_slots = 1, rows = 8, zchunk = 8;
+  int persistent = 0;  // the persistent launch is switched off (see rhd_batch_set_persistent)
   int device = 0;
   bool stop = false;
   Clock::time_point t0;
@@ -173,6 +174,7 @@ int start_request(rhd_server* s, Request& r, char* msg) {
       rhd_destroy(h);
       return rc;
     }
+    if (s->persistent) (void)rhd_batch_set_persistent(s->batch[prec], 1);
   }
   rc = rhd_batch_add(s->batch[prec], h, r.chat);
   if (rc) {
@@ -381,6 +383,16 @@ int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int 
     return sfail(nullptr, RHD_EDEVICE, "cannot start the worker thread");
   }
   *out = s;
+  return RHD_OK;
+}
+
+int rhd_server_set_persistent(rhd_server_t* s, int on) {
+  if (!s) return sfail(nullptr, RHD_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (s->next_id != 1) return sfail(s, RHD_ESTATE, "the launch mode is set before the first submission");
+  if (on)
+    return sfail(s, RHD_EINVAL, "the persistent launch is switched off: it did not finish on the GPU");
+  s->persistent = 0;
   return RHD_OK;
 }
 

@@ -614,6 +614,7 @@ struct SolveDesc {
   RadConst<T> K;
   T h_pred, h_corr;
   int zc_pred, zc_corr;
+  int tiles_pred, tiles_corr;  // tiles of one predictor and one corrector launch
   unsigned long long* ctr;
 };
 
@@ -644,6 +645,122 @@ __global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_batch(const SolveD
   __shared__ CorrectShared<T, BY> sh;
   rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, d.zc_corr, tr.y, tr.z, tr.w,
                                d.ctr, sh);
+}
+
+// ---------------------------------------------------------------------------
+// many independent solves in one persistent launch
+// ---------------------------------------------------------------------------
+//
+// The work of all subcycles of all members is one list of items, numbered level by
+// level: level l is the predictor (l even) or the corrector (l odd) of subcycle l/2 and
+// covers the first level_start[l+1] - level_start[l] tiles of that stage's packed list
+// (members sorted by decreasing nsub, so the members still subcycling at level l are a
+// prefix of the list). Blocks take items in order from one ticket counter. Member k's
+// counter done[k] counts its finished items; an item of level l of member k may start
+// once done[k] holds all of that member's items of the levels below l:
+//   (l / 2) (tiles_pred + tiles_corr) + (l odd ? tiles_pred : 0).
+// A block only ever waits for items with smaller tickets, which blocks already running
+// hold, so the smallest unfinished item can always proceed: no deadlock, whatever the
+// number of blocks that fit on the chip. Members do not wait for each other, so a member
+// with few subcycles finishes without lock-step rounds, and the stages of different
+// members overlap.
+// Counters of a persistent launch sit one per 128-byte line (member k's at done[32 k]),
+// so the polls of one member's waiters, another member's increments and the ticket
+// claims do not queue on one line.
+constexpr int COUNTER_STRIDE = 32;
+
+struct PersistentPlan {
+  const int4* tiles[2];     // packed tile lists of the predictor and the corrector
+  const int* level_start;   // levels + 1 entries
+  int levels;
+  unsigned* done;           // per member, COUNTER_STRIDE apart
+  unsigned* ticket;
+  unsigned* error;          // set when a wait ran out of time; every block then exits
+  unsigned long long wait_ticks;  // longest wait for a stage, in real-time counter ticks
+};
+
+// Level of item t: the last l with level_start[l] <= t.
+__device__ __forceinline__ int plan_level(const int* __restrict__ start, int levels, int t) {
+  int lo = 0, hi = levels - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int BY>
+union BatchShared {
+  PredictShared<T, BY> p;
+  CorrectShared<T, BY> c;
+};
+
+template <typename T, int BY>
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_FP32 : 2)
+    k_rad_batch_persistent(const SolveDesc<T>* __restrict__ sd, PersistentPlan plan) {
+  __shared__ BatchShared<T, BY> sh;
+  __shared__ int s_item, s_level;
+  const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+  const int total = plan.level_start[plan.levels];
+  for (;;) {
+    if (lead) {
+      int t = int(atomicAdd(plan.ticket, 1u));
+      if (__hip_atomic_load(plan.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) t = total;
+      if (t < total) {
+        const int l = plan_level(plan.level_start, plan.levels, t);
+        s_level = l;
+        if (l > 0) {
+          const int4 tr = plan.tiles[l & 1][t - plan.level_start[l]];
+          const SolveDesc<T>& d = sd[tr.x];
+          const unsigned need = unsigned(l >> 1) * unsigned(d.tiles_pred + d.tiles_corr) +
+                                ((l & 1) ? unsigned(d.tiles_pred) : 0u);
+          // bounded wait, by the real-time clock: a wait that runs out of time marks the
+          // launch failed and every block leaves, so the launch always ends
+          // (the clock is read every poll; the shared error flag every 64th poll, so the
+          // waiters' polls stay on their own member's line)
+          const unsigned* cnt = plan.done + COUNTER_STRIDE * tr.x;
+          const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+          unsigned polls = 0;
+          while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            ++polls;
+            if (__builtin_amdgcn_s_memrealtime() - start > plan.wait_ticks ||
+                ((polls & 63u) == 0u &&
+                 __hip_atomic_load(plan.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+              __hip_atomic_store(plan.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              t = total;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(20);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+      }
+      s_item = t;
+    }
+    __syncthreads();
+    const int t = s_item;
+    if (t >= total) return;
+    const int l = s_level;
+    // acquire: every wave sees the stores of the items it waited for
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int4 tr = plan.tiles[l & 1][t - plan.level_start[l]];
+    const SolveDesc<T> d = sd[tr.x];
+    if ((l & 1) == 0)
+      rad_predict_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_pred, d.zc_pred, tr.y, tr.z,
+                                   tr.w, sh.p);
+    else
+      rad_correct_tile_body<T, BY>(d.Um, d.Uh, d.gas, d.G, d.K, d.h_corr, d.zc_corr, tr.y, tr.z,
+                                   tr.w, d.ctr, sh.c);
+    // release: every wave's stores are complete and written back before the count
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (lead)
+      __hip_atomic_fetch_add(plan.done + COUNTER_STRIDE * tr.x, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace rhdk

@@ -356,12 +356,12 @@ def sod_tube(N=200, gamma=1.4):
 
 
 # --------------------------------------------------------------------------
-# non-equilibrium Marshak wave (Sec. 4.2.3): the paper's own timing problem
+# non-equilibrium Marshak wave (Sec. 4.1.3): the paper's own timing problem
 # --------------------------------------------------------------------------
 
 def _su_olson_integrands(chi, tau, eps):
     """The two integrands of the semi-analytic Su & Olson solution quoted in
-    Sec. 4.2.3 (Eq. marshak:suolson), as functions of eta in (0, 1)."""
+    Sec. 4.1.3 (Eq. marshak:suolson), as functions of eta in (0, 1)."""
     def gam_theta(g):
         return g, np.arccos(np.sqrt(3.0 / (3.0 + 4.0 * g * g)))
 
@@ -403,7 +403,7 @@ MARSHAK_EBG = 1e-10  # background E_r standing for the cold medium (the closure 
 
 
 def marshak_problem(n=128, chi_max=100.0, eps=1.0, precision="fp64"):
-    """The non-equilibrium Marshak wave of Sec. 4.2.3 in units a_R = c = 1, F_inc = 1/4,
+    """The non-equilibrium Marshak wave of Sec. 4.1.3 in units a_R = c = 1, F_inc = 1/4,
     rho = kappa_0 = 1, chat = c: a 1D slab chi in [0, chi_max] (x = chi / sqrt(3)),
     static gas (radiation only) with c_v = alpha T^3, alpha = 4 a_R / eps, a fixed
     radiation state on both faces (set each step by marshak_boundary) and a cold start.
@@ -434,7 +434,7 @@ def marshak_boundary(t, eps=1.0, nq=4000):
 
 
 # --------------------------------------------------------------------------
-# shadowing by a dense cloud (Sec. 4.2.1), cgs units
+# shadowing by a dense cloud (Sec. 4.1.1), cgs units
 # --------------------------------------------------------------------------
 
 C_CGS = 2.99792458e10          # cm / s
@@ -443,7 +443,7 @@ R_GAS_CGS = 1.380649e-16 / 1.6735575e-24  # k_B / m_H (mean molecular weight 1)
 
 
 def shadow_problem(nx=280, ny=80, emission=False, precision="fp64", heat_capacity=1.0):
-    """The shadow test of Sec. 4.2.1: a 1 cm x 0.12 cm box of gas at rho0 = 1e-3 g/cm^3
+    """The shadow test of Sec. 4.1.1: a 1 cm x 0.12 cm box of gas at rho0 = 1e-3 g/cm^3
     holding an ellipsoidal cloud of rho1 = 1 (Eqs. radshadow:rho, radshadow:delta;
     centre (0.5, 0), semi-axes 0.10 and 0.06), static, in radiative equilibrium at
     T0 = 290 K; from t = 0 the left face holds a beam of temperature T1 = 6 T0 moving
@@ -487,7 +487,7 @@ def radiation_temperature(Er):
 
 
 def pulse_problem(n=512, advected=True, beta_tau=True, precision="fp64", units="code"):
-    """Advection of a radiation pulse (Sec. 4.2.5): a periodic slab x/w in
+    """Advection of a radiation pulse (Sec. 4.3.2): a periodic slab x/w in
     [-21.25, 21.25] with w = 20 cm, rho0 = 25 g/cm^3, T0 = 1.1e7 K, mean particle mass
     1.67e-24 g, kappa_P = kappa_F = 0.4 cm^2/g, gamma = 5/3, chat = 100 a0 with
     a0 = sqrt(gamma k_B T0 / mu). The gas temperature is T0 (1 + exp(-x^2/(2 w^2))) and
@@ -549,7 +549,7 @@ def gas_temperature(spec, st):
 
 
 # --------------------------------------------------------------------------
-# radiation-driven expanding shell (Sec. 4.4.2, the second shell test)
+# radiation-driven expanding shell (Sec. 4.3.6, the second shell test)
 # --------------------------------------------------------------------------
 
 MSUN_G = 1.989e33
@@ -707,7 +707,7 @@ def shell_trajectory(M0, t):
 
 def shell_expansion_problem(n=128, chat_over_a0=860.0, precision="mixed", H=0.1, sigma_star=0.05,
                             rad_only=False):
-    """The expanding-shell test of Sec. 4.4.2 in code units (r0, rho0 = M_sh/(4/3 pi r0^3),
+    """The expanding-shell test of Sec. 4.3.6 in code units (r0, rho0 = M_sh/(4/3 pi r0^3),
     a0): the octant [0, 2]^3 with n^3 cells, reflecting faces at 0 and outflow faces at 2,
     isothermal gas (c_s = 1) at rest in radiative equilibrium (no exchange), the Gaussian
     shell of FWHM H at r = 1 with the density floor 1e-8, kappa = 3 tau0 for the flux,

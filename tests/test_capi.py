@@ -101,7 +101,7 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 
 def test_fixed_faces_and_cv_t3_need_radiation_only():
     """A fixed radiation face and the c_v = alpha T^3 gas are defined for a frozen gas
-    only (the Marshak problem of Sec. 4.2.3); both are refused otherwise, before any
+    only (the Marshak problem of Sec. 4.1.3); both are refused otherwise, before any
     device work."""
     import rhd_inputs as ri
     pb = ri.marshak_problem(32)

@@ -206,3 +206,67 @@ def test_concurrent_served_results_equal_one_at_a_time_results():
     for r in reqs:
         for k in ri.FIELDS:
             assert np.array_equal(ra[r["id"]][k], rb[r["id"]][k]), (r["id"], k)
+
+
+def run_batch(pbs, steps, persistent, rows=8, zchunk=16):
+    b = P.rhd_batch_create(8, rows, zchunk)
+    solvers, nsubs = [], []
+    try:
+        P.rhd_batch_set_persistent(b, persistent)
+        for pb in pbs:
+            s = P.Solver(pb["spec"])
+            s.set_state(pb["state"])
+            P.rhd_batch_add(b, s.h, pb["chat"])
+            solvers.append(s)
+        for _ in range(steps):
+            ns, _ = P.rhd_batch_step(b)
+            nsubs.append(list(ns))
+        P.rhd_batch_sync(b)
+        outs = [s.get_state() for s in solvers]
+        for s in solvers:
+            P.rhd_batch_remove(b, s.h)
+    finally:
+        P.rhd_batch_destroy(b)
+        for s in solvers:
+            s.close()
+    return outs, nsubs
+
+
+@pytest.mark.skip(reason="the persistent launch is switched off: twice it did not finish on the "
+                         "GPU (this test's batch, three members; no end within 120-180 s), and its "
+                         "cause is not found; rhd_batch_set_persistent(b, 1) returns RHD_EINVAL")
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_persistent_launch_equals_round_launches(precision):
+    """The persistent launch (one launch for all subcycles of all members, per-member
+    phase counters) computes every tile with the same device code as the round launches:
+    the members' states agree to rounding (the two kernels may contract multiply-adds
+    differently). Members span 5 to ~40 subcycles per gas step and 16^3 to 64x20x30
+    cells, so members finish their subcycles at different levels of the launch."""
+    announce(f"persistent vs rounds {precision}")
+    probs = PROBLEMS + [((16, 16, 16), 1.0, 5.0, 14), ((24, 17, 40), 1000.0, 45.0, 15)]
+    pbs = [problem(*p, precision=precision) for p in probs]
+    per, ns_p = run_batch(pbs, 3, True)
+    rnd, ns_r = run_batch(pbs, 3, False)
+    assert ns_p == ns_r
+    assert len(set(ns_p[0])) >= 3, ns_p
+    for pb, a, r in zip(pbs, per, rnd):
+        assert_parity(pb["spec"], a, r, 1e-13 if precision == "fp64" else 1e-6, "max",
+                      label="persistent vs rounds")
+
+
+def test_persistent_launch_is_refused():
+    """Asking a batch or a server for the switched-off persistent launch is an error that
+    changes nothing; rounds stay available. Host calls only."""
+    b = P.rhd_batch_create(2, 8, 8)
+    try:
+        with pytest.raises(P.RhdError) as e:
+            P.rhd_batch_set_persistent(b, 1)
+        assert e.value.code == P.RHD_EINVAL and "switched off" in str(e.value)
+        P.rhd_batch_set_persistent(b, 0)
+    finally:
+        P.rhd_batch_destroy(b)
+    with P.Server(1 << 30, 2) as srv:
+        with pytest.raises(P.RhdError) as e:
+            P.rhd_server_set_persistent(srv.s, 1)
+        assert e.value.code == P.RHD_EINVAL
+        P.rhd_server_set_persistent(srv.s, 0)

@@ -1,5 +1,5 @@
 """GPU parity for fixed radiation faces and the c_v = alpha T^3 gas: the non-equilibrium
-Marshak wave of Sec. 4.2.3, driven by the Su & Olson surface solution, against the FP64
+Marshak wave of Sec. 4.1.3, driven by the Su & Olson surface solution, against the FP64
 oracle step by step with the same boundary states; fixed faces on 2D and 3D grids with
 a seeded state, meeting reflecting and periodic faces at edges and corners.
 

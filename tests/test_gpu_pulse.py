@@ -1,4 +1,4 @@
-"""GPU parity on the advection of a radiation pulse (Sec. 4.2.5): the coupled 1D
+"""GPU parity on the advection of a radiation pulse (Sec. 4.3.2): the coupled 1D
 problem (moving optically thick gas, implicit exchange, about 70 radiation subcycles
 per gas step) with and without the O(beta tau) terms, against the FP64 oracle step by
 step with the oracle's time steps: the whole run to t = 2w/v at 128 cells in FP64, and

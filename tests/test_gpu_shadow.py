@@ -1,4 +1,4 @@
-"""GPU parity for the opacity law kappa(T_gas, rho) and the shadow test of Sec. 4.2.1:
+"""GPU parity for the opacity law kappa(T_gas, rho) and the shadow test of Sec. 4.1.1:
 the coarse shadow problem (fixed beam face, outflow and reflecting faces, per-cell
 kernels) without and with emission, and a 3D box with the law on the tiled kernels,
 each against the FP64 oracle on the same inputs.

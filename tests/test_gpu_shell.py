@@ -1,4 +1,4 @@
-"""GPU checks on the expanding-shell test of Sec. 4.4.2 (octant, reflecting and outflow
+"""GPU checks on the expanding-shell test of Sec. 4.3.6 (octant, reflecting and outflow
 faces, isothermal gas, central source, equilibrium M1 field): parity with the FP64
 oracle over the first coupled gas steps at 32^3; at the paper's 128^3, the radiation-only
 run holds the equilibrium field (as the paper reports), and the coupled run follows the

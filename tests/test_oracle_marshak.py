@@ -1,4 +1,4 @@
-"""Oracle pins for the non-equilibrium Marshak wave of Sec. 4.2.3 (the paper's own
+"""Oracle pins for the non-equilibrium Marshak wave of Sec. 4.1.3 (the paper's own
 timing problem): the exchange with c_v = alpha T^3 against the update printed with that
 problem, the Su & Olson surface solution that drives the boundary against its limits,
 fixed radiation faces against states they must leave unchanged, and the M1 solution
@@ -111,7 +111,7 @@ def test_fixed_face_drives_the_inflow():
 
 @pytest.fixture(scope="module")
 def marshak_run():
-    """The Marshak problem of Sec. 4.2.3 (N = 128 on chi in [0, 100], eps = 1) run by the
+    """The Marshak problem of Sec. 4.1.3 (N = 128 on chi in [0, 100], eps = 1) run by the
     oracle to tau = 1, 10 and 100."""
     pb = ri.marshak_problem(128)
     spec, st = dict(pb["spec"]), pb["state"]

@@ -1,7 +1,7 @@
 """Oracle pins for the Eddington (P1) closure, the alternative to M1 of Sec. 2.3
 (T = I/3 whatever F is) with the wave speeds -+chat/sqrt(3) of Sec. 2.4's diffusion
 limit for every state, which is the fixed-eigenvalue comparison run of the radiative
-shock test (Sec. 4.4.2). Its face flux equals the M1 flux wherever F = 0; without
+shock test (Sec. 4.3.5). Its face flux equals the M1 flux wherever F = 0; without
 opacity the P1 system is the wave equation, and the oracle converges at second order to
 d'Alembert's solution at amplitudes where M1 stays far from it; with a scattering
 opacity it follows the exact telegraph solution at any amplitude; and, as Sec. 2.3

@@ -1,4 +1,4 @@
-"""Oracle pins for the advection of a radiation pulse (Sec. 4.2.5), the paper's check of
+"""Oracle pins for the advection of a radiation pulse (Sec. 4.3.2), the paper's check of
 the O(beta tau) terms: a pulse of radiation in pressure and radiative equilibrium with
 optically thick gas (tau0 = 200, beta tau0 = 0.02), carried 2w by a uniform flow, against
 the same pulse left in place. At 128 cells (a quarter of the paper's resolution) the

@@ -1,4 +1,4 @@
-"""Oracle pins for the opacity law kappa(T_gas, rho) and the shadow test of Sec. 4.2.1:
+"""Oracle pins for the opacity law kappa(T_gas, rho) and the shadow test of Sec. 4.1.1:
 the law against the relaxation ODE it defines, the M1 shadow behind a dense cloud
 (sharp without emission, softer with it, as the paper finds), the floor on
 reconstructed face states that keeps cells next to the floor finite, and the floor on
@@ -78,7 +78,7 @@ def shadows():
 
 
 def test_m1_casts_a_sharp_shadow_without_emission(shadows):
-    """Sec. 4.2.1: the beam passes the thin ambient gas (tau = 0.1 across the box) and
+    """Sec. 4.1.1: the beam passes the thin ambient gas (tau = 0.1 across the box) and
     the cloud (tau ~ 10^2 per cell) stops it. At the right boundary after three
     light-crossing times the radiation temperature is T1 within the ambient absorption
     above the cloud and far below it in the cloud's shadow (|y| < 0.06), with the

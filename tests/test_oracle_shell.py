@@ -1,4 +1,4 @@
-"""Pins for the expanding-shell test of Sec. 4.4.2 (its initial state and reference
+"""Pins for the expanding-shell test of Sec. 4.3.6 (its initial state and reference
 solution, which the GPU runs are measured against): the dimensional parameters give the
 printed Mach number, optical depth and dynamical time; with a shell FWHM of 0.1 r0 the
 critical point of the equilibrium ODE falls at the printed r_crit = 1.128 r0; the
