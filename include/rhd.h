@@ -444,6 +444,49 @@ long long rhd_device_bytes(const rhd_t* h);
 /* Device bytes a handle with these parameters would hold, without creating it. */
 long long rhd_footprint_bytes(const rhd_params* p);
 
+/* ---- radiation subcycles without allocation ------------------------------------------ */
+
+/* Bytes of device scratch the allocation-free entry point below holds on each device it
+   runs on: a file-scope device array of the library, kept until the process ends. */
+#define RHD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation. It advances nsub radiation Van Leer
+   subcycles of dt_gas/nsub each on caller-owned device arrays, with the gas frozen: the
+   same kernels and arithmetic as the subcycles of rhd_step on a handle with the same
+   parameters and default kernel choice, so the radiation state comes out the same bit
+   for bit. It calls no hipMalloc, hipFree or allocating library routine: the half-step
+   arrays and the clamp and floor counters live in the library's scratch array
+   (RHD_NOALLOC_SCRATCH_BYTES per device, looked up on the first call on each device).
+   Work is enqueued on hip_stream (a hipStream_t, or NULL for the null stream); no
+   synchronisation.
+   Arguments (device pointers of the current device; element type double, or float with
+   RHD_PRECISION_MIXED; N = nx ny nz cells in the usual layout):
+     p        -- parameters as for rhd_create; the exchange, gas and step-size fields are
+                 ignored except theta_F, cfl, er_floor, the closure, RHD_BETA_TAU and
+                 RHD_EXCHANGE_ABSORB_ONLY (kappa_P damping of E_r on each stage);
+     Er, Fr   -- radiation state, N and 3N values, updated in place;
+     rho      -- gas density, N values; mom -- gas momentum, 3N values, read only with
+                 RHD_BETA_TAU (else may be NULL);
+     kappaP, kappaF -- per-cell specific opacities (N each), or both NULL to use the
+                 scalars kappaP_s, kappaF_s;
+     j        -- emissivity, N values, or NULL.
+   Errors: RHD_EINVAL for invalid parameters, RHD_OPACITY_LAW, fixed faces, NULL state
+   arrays, nsub < 1, dt_gas or chat not finite and > 0, or a grid whose half-step arrays
+   exceed the scratch (rhd_subcycles_noalloc_bytes(p) > RHD_NOALLOC_SCRATCH_BYTES: up to
+   157^3 cells in mixed precision, 123^3 in FP64); RHD_ECFL as for rhd_step; RHD_EDEVICE
+   if a launch fails. rhd_last_error(NULL) holds the message. Every call on one device
+   shares the scratch array, so calls that overlap in time on one device (other streams,
+   other host threads) race and give wrong results; serialise them. The counters are
+   cleared at the start of each call and not reported. */
+int rhd_subcycles_noalloc(const rhd_params* p, void* hip_stream, void* Er, void* Fr,
+                          const void* rho, const void* mom, const void* kappaP,
+                          const void* kappaF, double kappaP_s, double kappaF_s, const void* j,
+                          double dt_gas, double chat, int nsub);
+
+/* Scratch bytes rhd_subcycles_noalloc needs for these parameters (-1 if p is invalid). */
+long long rhd_subcycles_noalloc_bytes(const rhd_params* p);
+
 /* Free every device buffer and the owned stream. NULL is ignored. */
 void rhd_destroy(rhd_t* h);
 

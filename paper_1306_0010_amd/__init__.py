@@ -55,8 +55,10 @@ EXPORTED = ("rhd_default_params", "rhd_create", "rhd_set_state", "rhd_set_state_
             "rhd_batch_size", "rhd_batch_sync", "rhd_batch_destroy", "rhd_batch_last_error",
             "rhd_server_create", "rhd_server_submit", "rhd_server_poll", "rhd_server_wait",
             "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats", "rhd_server_destroy",
-            "rhd_server_last_error", "rhd_batch_set_persistent", "rhd_server_set_persistent",
-            "rhd_set_graph", "rhd_get_graph_stats")
+            "rhd_server_last_error", "rhd_subcycles_noalloc", "rhd_subcycles_noalloc_bytes",
+            "rhd_batch_set_persistent", "rhd_server_set_persistent", "rhd_set_graph",
+            "rhd_get_graph_stats")
+RHD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class RhdError(RuntimeError):
@@ -222,6 +224,12 @@ def lib():
     L.rhd_server_destroy.restype = None
     L.rhd_server_last_error.argtypes = [vp]
     L.rhd_server_last_error.restype = ctypes.c_char_p
+    L.rhd_subcycles_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                        ctypes.c_double, vp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int]
+    L.rhd_subcycles_noalloc.restype = ctypes.c_int
+    L.rhd_subcycles_noalloc_bytes.argtypes = [P]
+    L.rhd_subcycles_noalloc_bytes.restype = ctypes.c_longlong
     for name in ("rhd_server_create", "rhd_server_submit", "rhd_server_poll", "rhd_server_wait",
                  "rhd_server_fetch", "rhd_server_cancel", "rhd_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
@@ -505,6 +513,19 @@ def rhd_server_destroy(s):
 
 def rhd_server_last_error(s=None):
     return lib().rhd_server_last_error(s).decode(errors="replace")
+
+
+def rhd_subcycles_noalloc(params, stream, Er, Fr, rho, mom, kappaP, kappaF, kappaP_s, kappaF_s,
+                          j, dt_gas, chat, nsub):
+    """Radiation subcycles on caller-owned device arrays, allocating nothing. Every array
+    argument is a device address (an int, e.g. a torch tensor's data_ptr()) or None."""
+    _check(lib().rhd_subcycles_noalloc(ctypes.byref(params), stream, Er, Fr, rho, mom, kappaP,
+                                       kappaF, float(kappaP_s), float(kappaF_s), j,
+                                       float(dt_gas), float(chat), int(nsub)))
+
+
+def rhd_subcycles_noalloc_bytes(params):
+    return int(lib().rhd_subcycles_noalloc_bytes(ctypes.byref(params)))
 
 
 def rhd_device_bytes(h):

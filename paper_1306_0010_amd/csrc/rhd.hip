@@ -1973,3 +1973,138 @@ void rhd_destroy(rhd_t* h) {
 const char* rhd_last_error(const rhd_t* h) { return h ? h->err : g_create_error; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// radiation subcycles without allocation (rhd_subcycles_noalloc)
+// ---------------------------------------------------------------------------
+//
+// The half-step arrays and the counters live in one file-scope device array. In host
+// code its name is only a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is handed to kernels.
+
+static __device__ __align__(256) unsigned char scratch[RHD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device address of the scratch array on device dev, looked up on the first call there.
+int scratch_on_device(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(nullptr, RHD_EDEVICE, "device %d out of range for the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, RHD_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return RHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+long long rhd_subcycles_noalloc_bytes(const rhd_params* p) {
+  if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
+  long long N, NP;
+  footprint(p, &N, &NP);
+  const size_t es = (p->flags & RHD_PRECISION_MIXED) ? 4 : 8;
+  return (long long)(align256(rhdk::CTR_COUNT * sizeof(unsigned long long)) +
+                     4 * align256(size_t(NP) * es));
+}
+
+int rhd_subcycles_noalloc(const rhd_params* p, void* hip_stream, void* Er, void* Fr,
+                          const void* rho, const void* mom, const void* kappaP,
+                          const void* kappaF, double kappaP_s, double kappaF_s, const void* j,
+                          double dt_gas, double chat, int nsub) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (p->flags & RHD_OPACITY_LAW)
+    return fail(nullptr, RHD_EINVAL, "RHD_OPACITY_LAW is not available without allocation");
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] == RHD_BC_FIXED && (f < 2 ? p->nx : (f < 4 ? p->ny : p->nz)) > 1)
+      return fail(nullptr, RHD_EINVAL, "fixed faces are not available without allocation");
+  const long long need = rhd_subcycles_noalloc_bytes(p);
+  if (need > (long long)RHD_NOALLOC_SCRATCH_BYTES)
+    return fail(nullptr, RHD_EINVAL,
+                "grid %dx%dx%d needs %lld bytes of scratch, above the limit of %lld bytes",
+                p->nx, p->ny, p->nz, need, (long long)RHD_NOALLOC_SCRATCH_BYTES);
+  if (!Er || !Fr || !rho) return fail(nullptr, RHD_EINVAL, "Er, Fr and rho must be non-NULL");
+  if ((p->flags & RHD_BETA_TAU) && !mom)
+    return fail(nullptr, RHD_EINVAL, "RHD_BETA_TAU needs the momentum (mom)");
+  if ((kappaP == nullptr) != (kappaF == nullptr))
+    return fail(nullptr, RHD_EINVAL, "give both per-cell opacity arrays or neither");
+  if (!kappaP && (!(kappaP_s >= 0.0) || !(kappaF_s >= 0.0)))
+    return fail(nullptr, RHD_EINVAL, "scalar opacities must be >= 0");
+  if (!(dt_gas > 0.0) || !std::isfinite(dt_gas))
+    return fail(nullptr, RHD_EINVAL, "dt_gas must be finite and > 0 (got %g)", dt_gas);
+  if (!(chat > 0.0) || !std::isfinite(chat))
+    return fail(nullptr, RHD_EINVAL, "chat must be finite and > 0 (got %g)", chat);
+  if (nsub < 1) return fail(nullptr, RHD_EINVAL, "nsub must be >= 1 (got %d)", nsub);
+  if (chat * dt_gas / nsub > p->cfl * min_width(p) * (1.0 + 1e-12))
+    return fail(nullptr, RHD_ECFL, "chat dt_gas / nsub = %g exceeds K0 dx = %g",
+                chat * dt_gas / nsub, p->cfl * min_width(p));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, RHD_EDEVICE, "no HIP device");
+  unsigned char* base = nullptr;
+  if ((rc = scratch_on_device(dev, &base))) return rc;
+
+  // a handle on the stack: it owns nothing, and points at the caller's arrays and at
+  // the scratch array
+  rhd h;
+  h.p = *p;
+  h.mixed = (p->flags & RHD_PRECISION_MIXED) != 0;
+  h.esize = h.mixed ? 4 : 8;
+  h.stream = static_cast<hipStream_t>(hip_stream);
+  h.device = dev;
+  h.G = make_geom(p);
+  long long N, NP;
+  footprint(p, &N, &NP);
+  h.N = int(N);
+  h.NP = int(NP);
+  h.dxmin = min_width(p);
+  h.tile_ok = true;  // NP * esize is below the scratch limit, far below 4 GiB
+  const size_t es = h.esize;
+  unsigned char* fr = static_cast<unsigned char*>(Fr);
+  h.b.rad[0] = Er;
+  for (int q = 0; q < 3; ++q) h.b.rad[1 + q] = fr + size_t(q) * size_t(N) * es;
+  h.b.gas[0] = const_cast<void*>(rho);
+  for (int q = 0; q < 3; ++q)
+    h.b.gas[1 + q] = mom ? static_cast<unsigned char*>(const_cast<void*>(mom)) + size_t(q) * size_t(N) * es
+                         : nullptr;
+  h.kappa_scalar = kappaP == nullptr;
+  h.b.kP = const_cast<void*>(kappaP);
+  h.b.kF = const_cast<void*>(kappaF);
+  h.kP_s = kappaP_s;
+  h.kF_s = kappaF_s;
+  h.b.j = const_cast<void*>(j);
+  h.b.ctr = reinterpret_cast<unsigned long long*>(base);
+  size_t off = align256(rhdk::CTR_COUNT * sizeof(unsigned long long));
+  for (int q = 0; q < 4; ++q) {
+    h.b.rh[q] = base + off;
+    off += align256(size_t(NP) * es);
+  }
+  // the counters start from zero on every call, with a kernel (a captured memset node
+  // is what this entry point's callers avoid)
+  hipLaunchKernelGGL(rhdk::k_reset_counters, dim3(1), dim3(64), 0, h.stream, h.b.ctr);
+  rc = h.mixed ? enqueue_subcycles<float>(&h, dt_gas, chat, nsub)
+               : enqueue_subcycles<double>(&h, dt_gas, chat, nsub);
+  if (rc == RHD_OK) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      rc = fail(&h, RHD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  if (rc != RHD_OK) snprintf(g_create_error, sizeof(g_create_error), "%s", h.err);
+  return rc;
+}
+
+}  // extern "C"
