@@ -41,9 +41,11 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
-# tile shapes (rows, z chunk) that rhd_autotune picked for the two grids on MI355X
+# tile shapes (rows, z chunk) for the two grid sizes on MI355X: at 128^3 the one
+# rhd_autotune picked; at 256^3 the fastest of a per-kernel sweep of rows 4-16 x chunks
+# 8-32 (4 x 16: predictor 248.6 us, corrector 301.0 us, against 251.9 and 308.1 at 8 x 16)
 TILE_C2 = (8, 8)
-TILE_C3 = (8, 16)
+TILE_C3 = (4, 16)
 
 
 def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):
@@ -99,9 +101,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, tile):
     """HBM bytes per launch from the committed hardware-counter record, if it was taken
-    on the kernel sources as they are now; None otherwise."""
+    on the kernel sources as they are now and with the same tile shape; None otherwise."""
     try:
         with open(TRAFFIC_RECORD) as fh:
             rec = json.load(fh)
@@ -109,7 +111,10 @@ def measured_traffic(kernel, workload):
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    entry = rec.get("kernels", {}).get(workload, {}).get(kernel)
+    wl = rec.get("kernels", {}).get(workload, {})
+    if tuple(wl.get("tile", ())) != tuple(tile):
+        return None
+    entry = wl.get(kernel)
     return None if entry is None else entry.get("bytes_per_launch")
 
 
@@ -131,7 +136,7 @@ def kernel_table(timing, spec, has_j, kappa_field):
     return kernels
 
 
-def roofline(kernels, spec, has_j, kappa_field, workload):
+def roofline(kernels, spec, has_j, kappa_field, workload, tile):
     """The dominant radiation kernel: its algorithmic HBM bandwidth (bytes it must move
     per cell x cells per launch / average launch time) against the 8 TB/s peak, with the
     measured HBM traffic per launch when the counters were taken on the current kernel
@@ -143,7 +148,7 @@ def roofline(kernels, spec, has_j, kappa_field, workload):
     dom = max(rad, key=lambda k: rad[k]["share"])
     k = rad[dom]
     bpc = algorithmic_bytes_per_cell(dom, spec, has_j, kappa_field)
-    traffic = measured_traffic(dom, workload)
+    traffic = measured_traffic(dom, workload, tile)
     slots = k["algorithmic_Tslots_per_s"]
     return {"bound": "hbm", "achieved": k["algorithmic_GBps"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": k["algorithmic_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
@@ -559,7 +564,7 @@ def c3_headline(P, ri, stream, steps, warmup, nsub, tune, graph=False):
         timing = P.rhd_get_timing(s.h)
         P.rhd_set_timing(s.h, 0)
     kernels = kernel_table(timing, spec, True, False)
-    rl = roofline(kernels, spec, True, False, pb["name"])
+    rl = roofline(kernels, spec, True, False, pb["name"], tile[1:3])
     sub_bytes = sum(algorithmic_bytes_per_cell(k, spec, True, False) * kernels[k]["cells_per_launch"]
                     for k in ("rad_predict", "rad_correct"))
     sub_us = kernels["rad_predict"]["avg_us"] + kernels["rad_correct"]["avg_us"]
@@ -611,7 +616,7 @@ def c2_measurement(P, ri, stream, steps=10, warmup=3, precision="mixed", n=128):
             "gas_steps": steps, "subcycles_per_step": sub / steps,
             "value": ncell * sub / el, "unit": "zone-updates/s",
             "gas_step_zone_updates_per_s": ncell * steps / el, "ms_per_gas_step": 1e3 * el / steps,
-            "roofline": roofline(kernels, spec, False, False, pb["name"]), "kernels": kernels,
+            "roofline": roofline(kernels, spec, False, False, pb["name"], TILE_C2), "kernels": kernels,
             "kernel_ms_per_step": sum(t["total_ms"] for t in timing.values()) / steps,
             "nonfinite": diag["nonfinite"], "cache_note": "the 128^3 working set (~80 MB) fits "
             "in the 256 MB memory-side cache: its HBM figures are cache-resident"}

@@ -341,11 +341,16 @@ __global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_F
 // As in the predictor, the x faces inside a row use cross-lane shifts: lane i limits its
 // own cell only and takes the high-side state of lane i - 1 and the flux of lane i + 1,
 // so every x slope is evaluated once; the two faces on the row's ends go through LDS.
+//
+// One barrier per plane: the LDS arrays come in two copies, one per plane parity. The
+// barrier of plane t both publishes plane t's states and closes the flux writes of plane
+// t - 1, whose divergence and update are finished right after it; a copy is written
+// again only two planes later, after the next barrier has ordered every read of it.
 template <typename T, int BY>
 struct CorrectShared {
-  V4<T> U[BY + 4][TILE_BX + 4];  // [r][c]: U^{m+1/2} of cell (x0 - 2 + c, y0 - 2 + r)
-  V4<T> fxe[BY][2];              // [r][k]: flux through the x face x0 (k = 0), x0 + 64 (1)
-  V4<T> fy[BY + 1][TILE_BX];     // [j][c]: flux through the low y face of (x0 + c, y0 + j)
+  V4<T> U[2][BY + 4][TILE_BX + 4];  // [b][r][c]: U^{m+1/2} of cell (x0 - 2 + c, y0 - 2 + r)
+  V4<T> fxe[2][BY][2];              // [b][r][k]: flux through the x face x0 (k = 0), x0 + 64 (1)
+  V4<T> fy[2][BY + 1][TILE_BX];     // [b][j][c]: flux through the low y face of (x0 + c, y0 + j)
 };
 
 template <int BY>
@@ -428,7 +433,6 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
       rcol[s] = padded_cell(G, clamp_i(x0 - 2 + cc, -2, n0 + 1), clamp_i(y0 - 2 + r, -2, n1 + 1), 0);
     }
   }
-  V4<T>* const sUf = &sh.U[0][0];
   T ring[RP][4];
 #pragma unroll
   for (int s = 0; s < RP; ++s)
@@ -448,12 +452,16 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   T Uon[4] = {T(0), T(0), T(0), T(0)};
   FaceSide<T> zplus;  // high-z face data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
-  T divprev[4] = {T(0), T(0), T(0), T(0)};
+  // fluxes through the low x and y faces of the own cell in plane t-1 (lane 0's x face
+  // is replaced by the row-end item)
+  T flp[4] = {T(0), T(0), T(0), T(0)}, fbp[4] = {T(0), T(0), T(0), T(0)};
   unsigned long long nef = 0, nfc = 0;
   for (int t = z0 - 1; t <= z1; ++t) {
     const bool plane = t >= z0 && t < z1;  // planes whose x and y faces are needed
+    const int b = t & 1;
     if (plane) {
-      put4(sh.U[ty + 2][tx + 2], Uz0);
+      V4<T>* const sUf = &sh.U[b][0][0];
+      put4(sh.U[b][ty + 2][tx + 2], Uz0);
 #pragma unroll
       for (int s = 0; s < RP; ++s)
         if (rpos[s] >= 0) put4(sUf[rpos[s]], ring[s]);
@@ -465,16 +473,32 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
     }
     if (t < z1) load_padded4<T, true>(Uh, pcol + (t + 2) * zs, Upp);
     // z: limited states of the own cell; the low z face pairs them with plane t-1
-    {
-      T mz[4], pz[4];
-      mc_states(Uzm, Uz0, Uzp, mz, pz, ef);
-      T fz[4] = {T(0), T(0), T(0), T(0)};
-      if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, fc, chat), fz);
-      if (t > z0 && out_xy) {
-        // plane t-1 is complete: its z faces are t-3/2 (fzprev) and t-1/2 (fz)
+    T mz[4], pz[4];
+    mc_states(Uzm, Uz0, Uzp, mz, pz, ef);
+    T fz[4] = {T(0), T(0), T(0), T(0)};
+    if (t > z0 - 1) hll(zplus, face_side(mz, 2, c, ic, fc, chat), fz);
+    if (t >= z0) __syncthreads();
+    if (t > z0) {
+      // plane t-1 is complete: its x and y fluxes are in LDS copy (t-1) & 1, its z faces
+      // are t-3/2 (fzprev) and t-1/2 (fz)
+      const int pb = b ^ 1;
+      T fr[4], ft[4], fe[4], f0[4];
+      get4(sh.fxe[pb][ty][1], fe);
+      get4(sh.fxe[pb][ty][0], f0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fr[q] = lane_from_right(flp[q], fe[q]);
+      if (tx == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) flp[q] = f0[q];
+      }
+      get4(sh.fy[pb][ty + 1][tx], ft);
+      if (out_xy) {
         T d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = divprev[q] + (fz[q] - fzprev[q]) * K.inv_w[2];
+        for (int q = 0; q < 4; ++q) {
+          const T dxy = (fr[q] - flp[q]) * K.inv_w[0] + (ft[q] - fbp[q]) * K.inv_w[1];
+          d[q] = dxy + (fz[q] - fzprev[q]) * K.inv_w[2];
+        }
         const int a = x + n0 * (y + n1 * (t - 1));
         const Frozen<T> gz = frozen_make(gn, need_v);
         T out[4];
@@ -487,75 +511,59 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         elem<true>(Um.F[1], a) = out[2];
         elem<true>(Um.F[2], a) = out[3];
       }
-      if (t >= z0 && t < z1 && out_xy) {
-        const int a = x + n0 * (y + n1 * t);
-        gn = frozen_load<T, true>(gas, a, s1, need_v);
-        Uon[0] = elem<true>(Um.E, a);
-        Uon[1] = elem<true>(Um.F[0], a);
-        Uon[2] = elem<true>(Um.F[1], a);
-        Uon[3] = elem<true>(Um.F[2], a);
-      }
-      if (t < z1) zplus = face_side(pz, 2, c, ic, fc, chat);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     }
+    if (plane && out_xy) {
+      const int a = x + n0 * (y + n1 * t);
+      gn = frozen_load<T, true>(gas, a, s1, need_v);
+      Uon[0] = elem<true>(Um.E, a);
+      Uon[1] = elem<true>(Um.F[0], a);
+      Uon[2] = elem<true>(Um.F[1], a);
+      Uon[3] = elem<true>(Um.F[2], a);
+    }
+    if (t < z1) zplus = face_side(pz, 2, c, ic, fc, chat);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     if (plane) {
-      __syncthreads();
-      T fl[4], fb[4];
       {
         // lane 0's low x face is replaced by the row-end item below
-        T b[4], d[4], lo[4], hi[4], bh[4];
-        get4(sh.U[ty + 2][tx + 1], b);
-        get4(sh.U[ty + 2][tx + 3], d);
-        mc_states(b, Uz0, d, lo, hi, ef);
+        T bb[4], d[4], lo[4], hi[4], bh[4];
+        get4(sh.U[b][ty + 2][tx + 1], bb);
+        get4(sh.U[b][ty + 2][tx + 3], d);
+        mc_states(bb, Uz0, d, lo, hi, ef);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bh[q] = lane_from_left(hi[q], hi[q]);
-        hll(face_side(bh, 0, c, ic, fc, chat), face_side(lo, 0, c, ic, fc, chat), fl);
+        hll(face_side(bh, 0, c, ic, fc, chat), face_side(lo, 0, c, ic, fc, chat), flp);
       }
       {
-        T a[4], b[4], d[4];
-        get4(sh.U[ty][tx + 2], a);
-        get4(sh.U[ty + 1][tx + 2], b);
-        get4(sh.U[ty + 3][tx + 2], d);
-        face_flux4(a, b, Uz0, d, 1, c, ic, fc, chat, ef, fb);
+        T a[4], bb[4], d[4];
+        get4(sh.U[b][ty][tx + 2], a);
+        get4(sh.U[b][ty + 1][tx + 2], bb);
+        get4(sh.U[b][ty + 3][tx + 2], d);
+        face_flux4(a, bb, Uz0, d, 1, c, ic, fc, chat, ef, fbp);
       }
-      put4(sh.fy[ty][tx], fb);
+      put4(sh.fy[b][ty][tx], fbp);
       // extra items on waves of different SIMDs (wave w runs on SIMD w mod 4)
       if (ty == 0 && tx < 2 * BY) {
         // x face x0 (lanes < BY: cells x0 - 2 ... x0 + 1) or x0 + 64 (lanes BY .. 2 BY - 1:
         // cells x0 + 62 ... x0 + 65) of row lane mod BY
         const int r = tx % BY, k = tx < BY ? 0 : 1, c0 = k ? TILE_BX : 0;
-        T a[4], b[4], cc[4], d[4], f[4];
-        get4(sh.U[r + 2][c0], a);
-        get4(sh.U[r + 2][c0 + 1], b);
-        get4(sh.U[r + 2][c0 + 2], cc);
-        get4(sh.U[r + 2][c0 + 3], d);
-        face_flux4(a, b, cc, d, 0, c, ic, fc, chat, ef, f);
-        put4(sh.fxe[r][k], f);
+        T a[4], bb[4], cc[4], d[4], f[4];
+        get4(sh.U[b][r + 2][c0], a);
+        get4(sh.U[b][r + 2][c0 + 1], bb);
+        get4(sh.U[b][r + 2][c0 + 2], cc);
+        get4(sh.U[b][r + 2][c0 + 3], d);
+        face_flux4(a, bb, cc, d, 0, c, ic, fc, chat, ef, f);
+        put4(sh.fxe[b][r][k], f);
       }
       if (ty == BY - 1) {
         // high y face of column tx: rows y0 + BY - 2 ... y0 + BY + 1
         T a[4], cc[4], d[4], f[4];
-        get4(sh.U[BY][tx + 2], a);
-        get4(sh.U[BY + 2][tx + 2], cc);
-        get4(sh.U[BY + 3][tx + 2], d);
+        get4(sh.U[b][BY][tx + 2], a);
+        get4(sh.U[b][BY + 2][tx + 2], cc);
+        get4(sh.U[b][BY + 3][tx + 2], d);
         face_flux4(a, Uz0, cc, d, 1, c, ic, fc, chat, ef, f);
-        put4(sh.fy[BY][tx], f);
+        put4(sh.fy[b][BY][tx], f);
       }
-      __syncthreads();
-      T fr[4], ft[4], fe[4], f0[4];
-      get4(sh.fxe[ty][1], fe);
-      get4(sh.fxe[ty][0], f0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) fr[q] = lane_from_right(fl[q], fe[q]);
-      if (tx == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fl[q] = f0[q];
-      }
-      get4(sh.fy[ty + 1][tx], ft);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        divprev[q] = (fr[q] - fl[q]) * K.inv_w[0] + (ft[q] - fb[q]) * K.inv_w[1];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
