@@ -505,6 +505,83 @@ def cpu_baseline_c3(ri, cut=64, subcycles=20, max_threads=16):
             "single_core_value": zu / el1, **info}
 
 
+def cpu_baseline_c4(ri, cut=48, gas_steps=3, max_threads=16):
+    """The FP64 oracle (as it stands) on a bounded sample of the dusty shell: a cut^3
+    block of the 256^3 input centred on the shell where it crosses the +x axis (dense
+    lognormal shell and ambient gas, outflow faces), `gas_steps` full operator-split gas
+    steps at chat = 20 v_max(t=0) with the oracle's CFL subcycle counts. Timed once on
+    one thread, then with one copy per thread on up to max_threads threads."""
+    import numpy as np
+    import oracle
+    pb = ri.c4_dusty_shell(256, precision="fp64")
+    n = pb["spec"]["nx"]
+    xc = int(round((0.3 + 0.5) * n - 0.5))
+    lo_x, lo_yz = xc - cut // 2, (n - cut) // 2
+    sl = (slice(lo_yz, lo_yz + cut), slice(lo_yz, lo_yz + cut), slice(lo_x, lo_x + cut))
+    spec = dict(pb["spec"], nx=cut, ny=cut, nz=cut, precision="fp64")
+    st0 = {k: (np.ascontiguousarray(v[sl]) if isinstance(v, np.ndarray) and v.ndim == 3 else v)
+           for k, v in pb["state"].items()}
+    chat = pb["chat_over_vmax"] * oracle.suggest_dt(spec, st0, 1.0)[2]
+    info = host_info()
+    threads = max(1, min(max_threads, info["usable_cpus"]))
+    subs = []
+
+    def one(_):
+        st, ns_all = st0, []
+        for _ in range(gas_steps):
+            dt, ns, _ = oracle.suggest_dt(spec, st, chat)
+            st, _ = oracle.step(spec, st, dt, chat, ns)
+            ns_all.append(ns)
+        subs.append(sum(ns_all))
+
+    el1 = oracle_threads(one, [0], 1)
+    elp = oracle_threads(one, list(range(threads)), threads)
+    zu = cut ** 3 * subs[0]
+    return {"value": threads * zu / elp, "unit": "zone-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"a {cut}^3 block of the 256^3 dusty-shell input centred on the shell at "
+                      f"x = +0.3 (outflow faces), {gas_steps} gas steps at chat = "
+                      f"{chat:.3g} ({subs[0]} radiation subcycles in all), FP64; one copy per "
+                      f"thread on {threads} threads ({elp:.1f} s wall), and one thread alone "
+                      f"({el1:.1f} s)",
+            "gas_step_zone_updates_per_s": threads * cut ** 3 * gas_steps / elp,
+            "single_core_value": zu / el1, **info}
+
+
+def cpu_baseline_c5(ri, pert, requests=16, nz_slab=8, max_threads=16):
+    """The FP64 oracle (as it stands) on a bounded sample of the served stream: its
+    first `requests` requests (the same seeded boxes and perturbations as the GPU's
+    stream), each cut to its first nz_slab z-planes as a periodic slab and advanced by
+    one gas step (exchange, gas VL, its CFL radiation subcycles, correction). One
+    request per thread on up to max_threads threads; the rate is all zone-updates over
+    the wall time."""
+    import numpy as np
+    import oracle
+    reqs = ri.c5_requests(count=requests)
+    info = host_info()
+    threads = max(1, min(max_threads, info["usable_cpus"], requests))
+    done = {}
+
+    def one(r):
+        pb = ri.c5_problem(r, precision="fp64", perturbations=pert[r["id"]])
+        nz = min(nz_slab, r["nz"])
+        spec = dict(pb["spec"], nz=nz, precision="fp64")
+        st = {k: (np.ascontiguousarray(v[:nz]) if isinstance(v, np.ndarray) and v.ndim == 3 else v)
+              for k, v in pb["state"].items()}
+        dt, ns, _ = oracle.suggest_dt(spec, st, pb["chat"])
+        t0 = time.perf_counter()
+        oracle.step(spec, st, dt, pb["chat"], ns)
+        done[r["id"]] = (r["nx"] * r["ny"] * nz * ns, time.perf_counter() - t0)
+
+    el = oracle_threads(one, reqs, threads)
+    zu = sum(v[0] for v in done.values())
+    return {"value": zu / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"the stream's first {requests} requests, each its first {nz_slab} z-planes "
+                      f"as a periodic slab, one gas step with its CFL subcycles, FP64; one "
+                      f"request per thread on {threads} threads ({el:.1f} s wall)",
+            "per_thread_value": zu / sum(v[1] for v in done.values()), **info}
+
+
 def cpu_baseline_c2(pb, nz_slab=32):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the 128^3
     box: its first nz_slab z-planes as a periodic slab, one full gas step with its CFL
@@ -891,6 +968,9 @@ def main():
         progress("256^3 dusty shell timed")
     if pert is not None:
         out["serving"] = serving(args.serve_requests, args.serve_load, pert, modes)
+        if not args.no_cpu_baseline:
+            out["serving"]["cpu_baseline"] = cpu_baseline_c5(ri, pert)
+            progress("oracle timed on the served stream's sample")
         del pert
     if not args.no_marshak:
         out["marshak"] = marshak_timing(P, ri, stream)
@@ -904,6 +984,8 @@ def main():
     if not args.no_cpu_baseline:
         if not args.no_c2:
             out["c2_linear_box"]["cpu_baseline"] = cpu_baseline_c2(ri.c2_linear_box(128))
+        if args.c4_steps > 0:
+            out["c4_dusty_shell"]["cpu_baseline"] = cpu_baseline_c4(ri)
         if not args.no_marshak:
             out["marshak"]["cpu_baseline"] = cpu_baseline_marshak(ri)
             out["shadow"]["cpu_baseline"] = cpu_baseline_shadow(ri)
