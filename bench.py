@@ -42,10 +42,11 @@ FP32_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 # tile shapes (rows, z chunk) for the two grid sizes on MI355X: at 128^3 the one
-# rhd_autotune picked; at 256^3 the fastest of a per-kernel sweep of rows 4-16 x chunks
-# 8-32 (4 x 16: predictor 248.6 us, corrector 301.0 us, against 251.9 and 308.1 at 8 x 16)
+# rhd_autotune picked; at 256^3 the fastest subcycle of a sweep of rows 4-16 x chunks
+# 8-32 (8 x 16: predictor 252.7 us, corrector 285.2 us; at 4 rows the corrector's
+# unrolled plane loop spills and takes 343 us)
 TILE_C2 = (8, 8)
-TILE_C3 = (4, 16)
+TILE_C3 = (8, 16)
 
 
 def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):

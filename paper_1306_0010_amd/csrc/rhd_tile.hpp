@@ -19,9 +19,11 @@
 namespace rhdk {
 
 constexpr int TILE_BX = 64;
-// Minimum wavefronts per SIMD the FP32 predictor is compiled for (HIP's second launch
-// bound): 4 leaves it 128 VGPRs; more waves spill.
+// Minimum wavefronts per SIMD the FP32 stages are compiled for (HIP's second launch
+// bound): 4 leaves each 128 VGPRs; more waves spill. Unbounded, the corrector's
+// four-plane unrolled loop takes up to 140 and would drop to three waves.
 constexpr int PREDICT_WAVES_FP32 = 4;
+constexpr int CORRECT_WAVES_FP32 = 4;
 
 __host__ __device__ __forceinline__ int clamp_i(int q, int lo, int hi) {
   return q < lo ? lo : (q > hi ? hi : q);
@@ -441,10 +443,13 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   const int x = x0 + tx, y = y0 + ty;
   const bool out_xy = x < n0 && y < n1;
   const int pcol = padded_cell(G, clamp_i(x, -2, n0 + 1), clamp_i(y, -2, n1 + 1), 0);
-  T Uzm[4], Uz0[4], Uzp[4], Upp[4];
-  load_padded4<T, true>(Uh, pcol + (z0 - 2) * zs, Uzm);
-  load_padded4<T, true>(Uh, pcol + (z0 - 1) * zs, Uz0);
-  load_padded4<T, true>(Uh, pcol + z0 * zs, Uzp);
+  // the own column of U^{m+1/2}: planes t-1, t, t+1 and t+2 of plane step t, held in
+  // four arrays whose roles rotate by one each step (the plane loop is unrolled by four,
+  // so the rotation is a renaming and costs no moves)
+  T Ua[4], Ub[4], Uc[4], Ud[4];
+  load_padded4<T, true>(Uh, pcol + (z0 - 2) * zs, Ua);
+  load_padded4<T, true>(Uh, pcol + (z0 - 1) * zs, Ub);
+  load_padded4<T, true>(Uh, pcol + z0 * zs, Uc);
   // U^m and the gas data of the cell updated at the next plane, loaded one plane ahead
   const bool need_v = K.beta != 0;
   const int s1[3] = {1, 1, 1};
@@ -456,7 +461,8 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
   // is replaced by the row-end item)
   T flp[4] = {T(0), T(0), T(0), T(0)}, fbp[4] = {T(0), T(0), T(0), T(0)};
   unsigned long long nef = 0, nfc = 0;
-  for (int t = z0 - 1; t <= z1; ++t) {
+  auto plane_step = [&](const int t, T (&Uzm)[4], T (&Uz0)[4], T (&Uzp)[4],
+                        T (&Upp)[4]) __attribute__((always_inline)) {
     const bool plane = t >= z0 && t < z1;  // planes whose x and y faces are needed
     const int b = t & 1;
     if (plane) {
@@ -565,19 +571,22 @@ __device__ __forceinline__ void rad_correct_tile_body(const RadPtrs<T>& Um, cons
         put4(sh.fy[b][BY][tx], f);
       }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Uzm[q] = Uz0[q];
-      Uz0[q] = Uzp[q];
-      Uzp[q] = Upp[q];
-    }
+  };
+  for (int t = z0 - 1; t <= z1; t += 4) {
+    plane_step(t, Ua, Ub, Uc, Ud);
+    if (t + 1 > z1) break;
+    plane_step(t + 1, Ub, Uc, Ud, Ua);
+    if (t + 2 > z1) break;
+    plane_step(t + 2, Uc, Ud, Ua, Ub);
+    if (t + 3 > z1) break;
+    plane_step(t + 3, Ud, Ua, Ub, Uc);
   }
   wave_add(ctr + CTR_RAD_EFLOOR, nef);
   wave_add(ctr + CTR_RAD_FCLAMP, nfc);
 }
 
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? CORRECT_WAVES_FP32 : 1) k_rad_correct_tile(RadPtrs<T> Um, RadPtrs<T> Uh,
                                                                    GasView<T> gas, Geom G,
                                                                    RadConst<T> K, T h, int zc,
                                                                    unsigned long long* ctr) {
@@ -643,7 +652,7 @@ __global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_F
 }
 
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY) k_rad_correct_batch(const SolveDesc<T>* __restrict__ sd,
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? CORRECT_WAVES_FP32 : 1) k_rad_correct_batch(const SolveDesc<T>* __restrict__ sd,
                                                                     const int4* __restrict__ tiles,
                                                                     const int* __restrict__ ntiles) {
   const int nt = *ntiles;
