@@ -260,7 +260,9 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
 
 /* Select the kernels of the radiation subcycle: variant RHD_KERNELS_*, tile_rows the
    rows of a 64-wide tile (4, 8 or 16; FP64 handles 4 or 8), zchunk the z-planes one tile
-   walks (>= 1). Defaults after rhd_create: tiled, 8 rows, 8 planes. Results do not
+   walks (>= 1). In mixed precision the predictor stage always runs 4-row tiles (its
+   fastest shape on every grid measured) and tile_rows sets the corrector's and the gas
+   stages'. Defaults after rhd_create: tiled, 8 rows, 8 planes. Results do not
    depend on the choice beyond rounding. RHD_EINVAL for values outside these sets. The
    tiled kernels address with 32-bit byte offsets: a grid whose padded arrays
    ((nx + 4)(ny + 4)(nz + 4) cells) exceed 4 GiB each (beyond ~1000^3 cells in mixed

@@ -372,22 +372,32 @@ int enqueue_ledger(rhd_t* h, double chat) {
   return RHD_OK;
 }
 
+// Tile rows of the predictor for corrector tiles of BY rows: the FP32 predictor always
+// runs 4-row tiles (five blocks per CU), the FP64 one the corrector's.
+template <typename T, int BY>
+constexpr int predict_rows() {
+  return sizeof(T) == 4 ? rhdk::PREDICT_ROWS_FP32 : BY;
+}
+
+int predict_rows(bool mixed, int rows) { return mixed ? rhdk::PREDICT_ROWS_FP32 : rows; }
+
 // One radiation subcycle with the tiled kernels (3D grids).
 template <typename T, int BY>
 void launch_tiled_rows(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasView<T> view,
                        const rhdk::RadConst<T>& RK, T h_pred, T h_corr) {
+  constexpr int PBY = predict_rows<T, BY>();
   const rhdk::Geom& G = h->G;
+  const rhdk::TileGrid tp = rhdk::tile_grid<PBY>(G.n, h->zchunk);
   const rhdk::TileGrid tg = rhdk::tile_grid<BY>(G.n, h->zchunk);
-  const dim3 block(rhdk::TILE_BX, BY, 1);
-  const dim3 gp(tg.pred[0], tg.pred[1], tg.pred[2]);
+  const dim3 gp(tp.pred[0], tp.pred[1], tp.pred[2]);
   const dim3 gc(tg.corr[0], tg.corr[1], tg.corr[2]);
   int ti = tbegin(h, KC_RAD_PREDICT, h->NP);
-  hipLaunchKernelGGL((rhdk::k_rad_predict_tile<T, BY>), gp, block, 0, h->stream, rad, rh, view, G,
-                     RK, h_pred, tg.zc_pred);
+  hipLaunchKernelGGL((rhdk::k_rad_predict_tile<T, PBY>), gp, dim3(rhdk::TILE_BX, PBY, 1), 0,
+                     h->stream, rad, rh, view, G, RK, h_pred, tp.zc_pred);
   tend(h, ti);
   ti = tbegin(h, KC_RAD_CORRECT, h->N);
-  hipLaunchKernelGGL((rhdk::k_rad_correct_tile<T, BY>), gc, block, 0, h->stream, rad, rh, view, G,
-                     RK, h_corr, tg.zc_corr, h->b.ctr);
+  hipLaunchKernelGGL((rhdk::k_rad_correct_tile<T, BY>), gc, dim3(rhdk::TILE_BX, BY, 1), 0,
+                     h->stream, rad, rh, view, G, RK, h_corr, tg.zc_corr, h->b.ctr);
   tend(h, ti);
 }
 
@@ -1605,12 +1615,14 @@ int batch_reserve(rhd_batch_t* b, int need_pred, int need_corr) {
 
 template <typename T, int BY>
 void launch_batch_round(rhd_batch_t* b, int total_pred, int total_corr, int r) {
-  const dim3 block(rhdk::TILE_BX, BY, 1);
+  constexpr int PBY = predict_rows<T, BY>();
   const auto* sd = static_cast<const rhdk::SolveDesc<T>*>(b->d_desc);
-  hipLaunchKernelGGL((rhdk::k_rad_predict_batch<T, BY>), dim3(total_pred), block, 0, b->stream, sd,
-                     b->d_tiles_pred, b->d_counts + 2 * r);
-  hipLaunchKernelGGL((rhdk::k_rad_correct_batch<T, BY>), dim3(total_corr), block, 0, b->stream, sd,
-                     b->d_tiles_corr, b->d_counts + 2 * r + 1);
+  hipLaunchKernelGGL((rhdk::k_rad_predict_batch<T, PBY>), dim3(total_pred),
+                     dim3(rhdk::TILE_BX, PBY, 1), 0, b->stream, sd, b->d_tiles_pred,
+                     b->d_counts + 2 * r);
+  hipLaunchKernelGGL((rhdk::k_rad_correct_batch<T, BY>), dim3(total_corr),
+                     dim3(rhdk::TILE_BX, BY, 1), 0, b->stream, sd, b->d_tiles_corr,
+                     b->d_counts + 2 * r + 1);
 }
 
 // After a synchronisation: the error flag of the last persistent launch, if one ran.
@@ -1729,15 +1741,18 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
     d.h_pred = T(0.5 * hr);
     d.h_corr = T(hr);
     d.ctr = h->b.ctr;
+    // the persistent launch runs both stages at the batch's rows
+    const rhdk::TileGrid tp =
+        tile_counts(h, b->persistent ? b->rows : predict_rows(h->mixed, b->rows), b->zchunk);
     const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
-    d.zc_pred = tg.zc_pred;
+    d.zc_pred = tp.zc_pred;
     d.zc_corr = tg.zc_corr;
-    d.tiles_pred = tg.pred[0] * tg.pred[1] * tg.pred[2];
+    d.tiles_pred = tp.pred[0] * tp.pred[1] * tp.pred[2];
     d.tiles_corr = tg.corr[0] * tg.corr[1] * tg.corr[2];
     desc[k] = d;
-    for (int z = 0; z < tg.pred[2]; ++z)
-      for (int y = 0; y < tg.pred[1]; ++y)
-        for (int x = 0; x < tg.pred[0]; ++x) b->h_tiles_pred[np++] = make_int4(k, x, y, z);
+    for (int z = 0; z < tp.pred[2]; ++z)
+      for (int y = 0; y < tp.pred[1]; ++y)
+        for (int x = 0; x < tp.pred[0]; ++x) b->h_tiles_pred[np++] = make_int4(k, x, y, z);
     for (int z = 0; z < tg.corr[2]; ++z)
       for (int y = 0; y < tg.corr[1]; ++y)
         for (int x = 0; x < tg.corr[0]; ++x) b->h_tiles_corr[nc++] = make_int4(k, x, y, z);
@@ -1869,11 +1884,18 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   if (b->precision >= 0 && prec != b->precision)
     return bfail(b, RHD_EINVAL, "member precision differs from the batch's");
   if (!h->mixed && b->rows == 16) return bfail(b, RHD_EINVAL, "16-row tiles need mixed precision");
+  // room for the predictor's tiles at either row count (the persistent launch uses the
+  // batch's rows, the round launches the predictor's own)
+  auto pred_tiles = [&](const rhd_t* m) {
+    const rhdk::TileGrid a = tile_counts(m, b->rows, b->zchunk);
+    const rhdk::TileGrid c = tile_counts(m, predict_rows(m->mixed, b->rows), b->zchunk);
+    return std::max(a.pred[0] * a.pred[1] * a.pred[2], c.pred[0] * c.pred[1] * c.pred[2]);
+  };
   const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
-  int need_p = tg.pred[0] * tg.pred[1] * tg.pred[2], need_c = tg.corr[0] * tg.corr[1] * tg.corr[2];
+  int need_p = pred_tiles(h), need_c = tg.corr[0] * tg.corr[1] * tg.corr[2];
   for (rhd_t* m : b->members) {
     const rhdk::TileGrid t2 = tile_counts(m, b->rows, b->zchunk);
-    need_p += t2.pred[0] * t2.pred[1] * t2.pred[2];
+    need_p += pred_tiles(m);
     need_c += t2.corr[0] * t2.corr[1] * t2.corr[2];
   }
   BHIP_TRY(b, hipStreamSynchronize(b->stream));

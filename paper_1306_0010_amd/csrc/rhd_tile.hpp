@@ -20,9 +20,13 @@ namespace rhdk {
 
 constexpr int TILE_BX = 64;
 // Minimum wavefronts per SIMD the FP32 stages are compiled for (HIP's second launch
-// bound): 4 leaves each 128 VGPRs; more waves spill. Unbounded, the corrector's
-// four-plane unrolled loop takes up to 140 and would drop to three waves.
-constexpr int PREDICT_WAVES_FP32 = 4;
+// bound). The predictor keeps the z data of its previous plane in LDS instead of ten
+// registers and fits 96 VGPRs, so five 4-row blocks share a CU (five waves per SIMD;
+// their LDS, 31 KB each, fills 155 of its 160 KB); the FP32 predictor therefore always
+// runs 4-row tiles, whatever the corrector's. The corrector gets 128 VGPRs: unbounded,
+// its four-plane unrolled loop takes up to 140 and would drop to three waves.
+constexpr int PREDICT_WAVES_FP32 = 5;
+constexpr int PREDICT_ROWS_FP32 = 4;
 constexpr int CORRECT_WAVES_FP32 = 4;
 
 __host__ __device__ __forceinline__ int clamp_i(int q, int lo, int hi) {
@@ -138,6 +142,7 @@ struct PredictShared {
   SideTile<T, BY, 4> sxe;           // [r][k]: x data of cells x0 - 1, x0, x0 + 63, x0 + 64
   V4<T> fxe[BY][2];                 // [r][k]: flux through the x face x0 (k = 0), x0 + 64 (1)
   V4<T> fy[BY + 1][TILE_BX];        // [j][c]: flux through the low y face of (x0 + c, y0 + j)
+  SideTile<T, BY, TILE_BX> zp;      // [r][c]: z data of cell (x0 + c, y0 + r) in plane t-1
 };
 
 // Cross-lane shifts within a wavefront (DPP wave_shr:1 / wave_shl:1): lane i receives
@@ -232,10 +237,11 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
   if (hrole) load_rad_raw<T, true>(Um, G, hx, hy, z0, Hn, nH);
   FrozenRaw<T> gn = {};
 
-  FaceSide<T> zprev;  // z data of plane t-1
   T fzprev[4] = {T(0), T(0), T(0), T(0)};
   T divprev[4] = {T(0), T(0), T(0), T(0)};
   for (int t = z0 - 1; t <= z1; ++t) {
+    // z data of plane t-1, kept in the thread's own LDS slot between planes
+    const FaceSide<T> zprev = sh.zp.get(ty, tx);
     T U[4] = {Un[0], Un[1], Un[2], Un[3]};
     unflip_rad(U, nU);
     if (t < z1) load_rad_raw<T, true>(Um, G, xl, yl, t + 1, Un, nU);
@@ -262,7 +268,7 @@ __device__ __forceinline__ void rad_predict_tile_body(const RadPtrs<T>& Um, cons
       int s[3];
       gn = frozen_load<T, true>(gas, mapped_cell(G, xl, yl, t, s), s, need_v);
     }
-    zprev = fzs;
+    sh.zp.put(ty, tx, fzs);
 #pragma unroll
     for (int q = 0; q < 4; ++q) fzprev[q] = fz[q];
     if (t >= z0 && t < z1) {
@@ -716,7 +722,7 @@ union BatchShared {
 };
 
 template <typename T, int BY>
-__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? PREDICT_WAVES_FP32 : 2)
+__global__ void __launch_bounds__(TILE_BX * BY, sizeof(T) == 4 ? CORRECT_WAVES_FP32 : 2)
     k_rad_batch_persistent(const SolveDesc<T>* __restrict__ sd, PersistentPlan plan) {
   __shared__ BatchShared<T, BY> sh;
   __shared__ int s_item, s_level;
