@@ -17,6 +17,7 @@ import oracle
 import paper_1306_0010_amd as P
 import rhd_inputs as ri
 from parity import assert_parity, field_errors, window
+from bench import TILE_C3  # the 256^3 workloads' tile shape, as the benchmark times them
 
 pytestmark = pytest.mark.gpu
 
@@ -528,13 +529,15 @@ def test_full_size_box_one_step_windows(precision):
 
 
 def test_full_size_point_source_subcycle_windows():
-    """The 256^3 concentrated-source workload (mixed precision, outflow faces, emission),
-    one radiation subcycle, sampled around the source and at a domain corner."""
+    """The 256^3 concentrated-source workload (mixed precision, outflow faces, emission)
+    in the benchmark's launch configuration, one radiation subcycle, sampled around the
+    source and at a domain corner."""
     announce("256^3 point source windows")
     pb = ri.c3_point_source(256)
     spec, st = pb["spec"], pb["state"]
     # let the source run for a while first so the windows see a radiation field
     with P.Solver(spec) as s:
+        s.set_kernel_variant(P.RHD_KERNELS_TILED, *TILE_C3)
         s.set_state(st)
         for _ in range(20):
             s.step(pb["dt"], pb["chat"], 1)
@@ -548,6 +551,28 @@ def test_full_size_point_source_subcycle_windows():
     centres = [(128, 128, 128), (120, 131, 126), (4, 4, 251)]
     window_check(spec, mid_full, gpu, pb["chat"], pb["dt"], 1, centres, 8, 6, ("edge",) * 3,
                  1e-5, "l1")
+
+
+def test_full_size_dusty_shell_step_windows():
+    """The 256^3 dusty shell (isothermal gas, outflow faces, lognormal shell, central
+    source, no exchange) in the benchmark's launch configuration: one full gas step
+    (isothermal gas Van Leer, one radiation subcycle, source correction) at
+    chat = 20 v_max(t=0), sampled at the source, on the shell where it crosses the x
+    axis and the y axis, and at a corner."""
+    announce("256^3 dusty shell windows")
+    pb = ri.c4_dusty_shell(256)
+    spec, st = pb["spec"], pb["state"]
+    spec64 = dict(spec, precision="fp64")
+    chat = pb["chat_over_vmax"] * oracle.suggest_dt(spec64, st, 1.0)[2]
+    dt, ns, _ = oracle.suggest_dt(spec64, st, chat)
+    dt1 = dt / ns  # one subcycle of the right size; the gas step shrinks with it
+    gpu, diag = run_gpu(spec, st, 1, chat, dt1, 1, variant=(P.RHD_KERNELS_TILED, *TILE_C3))
+    assert diag["nonfinite"] == 0
+    n = spec["nx"]
+    shell = int(round((0.3 + 0.5) * n - 0.5))  # cell index where r = 0.3 on an axis
+    centres = [(128, 128, 128), (shell, 128, 128), (128, n - 1 - shell, 128), (4, 251, 4)]
+    window_check(spec, st, gpu, chat, dt1, 1, centres, 8, 8, ("edge",) * 3, TOL["mixed"],
+                 NORM["mixed"])
 
 
 def test_full_size_box_bench_run_properties():
