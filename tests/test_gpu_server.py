@@ -3,7 +3,9 @@ its results equal those of the same solves in a batch bit for bit and those of l
 handles to rounding; a request larger than the memory budget is refused at submission
 and the others run within the budget; cancelling a running or queued request frees its
 slot and leaves every other result unchanged bit for bit; a failing request fails alone;
-waiting with a time limit and destroying a busy server both return."""
+waiting with a time limit and destroying a busy server both return; the benchmark's own
+stream, at full size, equals its requests run alone, and one served gas step of its
+smallest request matches the oracle."""
 import sys
 import time
 
@@ -61,6 +63,32 @@ def test_native_server_results_equal_batch_results():
             assert np.array_equal(ra[r["id"]][k], rb[r["id"]][k]), (r["id"], k)
         assert_parity(make(r)["spec"], ra[r["id"]], rc[r["id"]], 1e-6, "max",
                       label=f"request {r['id']} native server vs one at a time")
+
+
+def test_served_stream_at_full_size():
+    """The served-batch workload's own requests (the benchmark's stream: seeds, grids up
+    to 192^3, 20 gas steps each) through the native server as the benchmark runs it, all
+    queued at once: every result equals the same request run alone to FP32 rounding. The
+    smallest of them, one gas step served, matches the FP64 oracle on its whole box."""
+    import oracle
+    announce("served stream at full size")
+    reqs = [dict(r, arrival=0.0) for r in ri.c5_requests(count=8)]
+    make = lambda r: ri.c5_problem(r)
+    a, ra = serve.serve_native(reqs, make, keep_results=True)
+    c, rc = serve.serve_serial(reqs, make, keep_results=True, variant=serve.DEFAULT_VARIANT)
+    assert a["requests"] == c["requests"] == 8 and a["zone_updates"] == c["zone_updates"]
+    assert max(r["nx"] * r["ny"] * r["nz"] for r in reqs) >= 128 ** 3
+    for r in reqs:
+        assert_parity(make(r)["spec"], ra[r["id"]], rc[r["id"]], 1e-6, "max",
+                      label=f"request {r['id']} ({r['nx']}x{r['ny']}x{r['nz']}) native vs alone")
+    small = dict(min(reqs, key=lambda r: r["nx"] * r["ny"] * r["nz"]), steps=1)
+    pb = make(small)
+    _, rs = serve.serve_native([small], make, keep_results=True)
+    spec64 = dict(pb["spec"], precision="fp64")
+    dt, ns, _ = oracle.suggest_dt(spec64, pb["state"], pb["chat"])
+    ref, _ = oracle.step(spec64, pb["state"], dt, pb["chat"], ns)
+    assert_parity(pb["spec"], rs[small["id"]], ref, 1e-5, "l1",
+                  label=f"request {small['id']} one gas step vs oracle")
 
 
 def test_over_budget_request_is_refused_and_the_rest_run_within_budget():
