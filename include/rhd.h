@@ -187,7 +187,7 @@ int rhd_set_boundary(rhd_t* h, int face, const double U[4]);
 /* Advance one gas step of dt_gas with nsub radiation subcycles of dt_gas/nsub each
    (Sec. 3.1 steps 2-6, Eq. algorithm:radtimestep). chat is the reduced speed of light
    of this step (Sec. 3.2). nsub = 0 advances the exchange and the gas only.
-   RHD_EINVAL for dt_gas <= 0, chat <= 0 or nsub < 0; RHD_ECFL when
+   RHD_EINVAL for dt_gas <= 0, chat <= 0 or nsub outside [0, 2^20]; RHD_ECFL when
    chat * dt_gas / nsub > K0 * min(dx, dy, dz) (relative slack 1e-12); RHD_ESTATE
    before rhd_set_state. Asynchronous: errors found on the GPU (non-finite values)
    are reported by rhd_sync and rhd_get_diagnostics. */
@@ -437,7 +437,9 @@ int rhd_server_get_stats(rhd_server_t* s, rhd_server_stats* out);
    No other call on this server may be in progress or follow. NULL is ignored. */
 void rhd_server_destroy(rhd_server_t* s);
 
-/* Message of the last failure of a server call (s may be NULL for rhd_server_create). */
+/* Message of the last failure of a call on this server or of its worker (s may be NULL
+   for rhd_server_create). The text is copied for the calling thread: it stays valid
+   until that thread's next call of this function. */
 const char* rhd_server_last_error(const rhd_server_t* s);
 
 /* Device bytes the handle holds (state, opacities, emission and scratch). */
@@ -489,7 +491,8 @@ int rhd_subcycles_noalloc(const rhd_params* p, void* hip_stream, void* Er, void*
 /* Scratch bytes rhd_subcycles_noalloc needs for these parameters (-1 if p is invalid). */
 long long rhd_subcycles_noalloc_bytes(const rhd_params* p);
 
-/* Free every device buffer and the owned stream. NULL is ignored. */
+/* Free every device buffer and the owned stream. A batch member leaves its batch first
+   (as with rhd_batch_remove). NULL is ignored. */
 void rhd_destroy(rhd_t* h);
 
 /* Message of the last failure on this handle (or of the last failed rhd_create when h

@@ -105,6 +105,7 @@ struct rhd {
   double vmax_last = 0.0;
   long long bytes = 0;
   bool in_batch = false;
+  rhd_batch* batch = nullptr;  // the batch this handle is a member of, if in_batch
   int variant = RHD_KERNELS_TILED;
   bool tile_ok = true;         // every array the tiled radiation kernels touch holds <= 4 GiB
   bool law_fresh = false;      // the opacity law's kappa arrays match the current gas state
@@ -1302,7 +1303,8 @@ int rhd_step(rhd_t* h, double dt_gas, double chat, int nsub) {
     return fail(h, RHD_EINVAL, "dt_gas must be finite and > 0 (got %g)", dt_gas);
   if (!(chat > 0.0) || !std::isfinite(chat))
     return fail(h, RHD_EINVAL, "chat must be finite and > 0 (got %g)", chat);
-  if (nsub < 0) return fail(h, RHD_EINVAL, "nsub must be >= 0 (got %d)", nsub);
+  if (nsub < 0 || nsub > (1 << 20))
+    return fail(h, RHD_EINVAL, "nsub must be in [0, 2^20] (got %d)", nsub);
   if (nsub > 0 && chat * dt_gas / nsub > h->p.cfl * h->dxmin * (1.0 + 1e-12))
     return fail(h, RHD_ECFL, "chat dt_gas / nsub = %g exceeds K0 dx = %g",
                 chat * dt_gas / nsub, h->p.cfl * h->dxmin);
@@ -1907,6 +1909,7 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   b->saved_streams.push_back(h->stream);
   h->stream = b->stream;
   h->in_batch = true;
+  h->batch = b;
   return RHD_OK;
 }
 
@@ -1917,6 +1920,7 @@ int rhd_batch_remove(rhd_batch_t* b, rhd_t* h) {
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     h->stream = b->saved_streams[i];
     h->in_batch = false;
+    h->batch = nullptr;
     b->members.erase(b->members.begin() + long(i));
     b->chat.erase(b->chat.begin() + long(i));
     b->saved_streams.erase(b->saved_streams.begin() + long(i));
@@ -1955,6 +1959,7 @@ void rhd_batch_destroy(rhd_batch_t* b) {
   for (size_t i = 0; i < b->members.size(); ++i) {
     b->members[i]->stream = b->saved_streams[i];
     b->members[i]->in_batch = false;
+    b->members[i]->batch = nullptr;
   }
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->h_desc) (void)hipHostFree(b->h_desc);
@@ -1977,6 +1982,8 @@ const char* rhd_batch_last_error(const rhd_batch_t* b) { return b ? b->err : g_b
 
 void rhd_destroy(rhd_t* h) {
   if (!h) return;
+  // a member leaves its batch first, so the batch holds no pointer to freed buffers
+  if (h->in_batch && h->batch) (void)rhd_batch_remove(h->batch, h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->timer.start) {
     for (int i = 0; i < Timer::POOL; ++i) {

@@ -69,6 +69,9 @@ struct rhd_server {
   bool stop = false;
   Clock::time_point t0;
   rhd_server_stats stats{};
+  // the last failure's message: written by API calls (with or without mu held) and by
+  // the worker, so it has a lock of its own
+  std::mutex err_mu;
   char err[256] = "";
   // worker-only state: one batch per precision (0 FP64, 1 mixed) and its members in
   // batch order
@@ -87,7 +90,12 @@ int sfail(rhd_server* s, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   std::vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
-  std::snprintf(s ? s->err : g_server_error, 256, "%s", buf);
+  if (s) {
+    std::lock_guard<std::mutex> lk(s->err_mu);
+    std::snprintf(s->err, sizeof(s->err), "%s", buf);
+  } else {
+    std::snprintf(g_server_error, sizeof(g_server_error), "%s", buf);
+  }
   return code;
 }
 
@@ -551,6 +559,14 @@ void rhd_server_destroy(rhd_server_t* s) {
   delete s;
 }
 
-const char* rhd_server_last_error(const rhd_server_t* s) { return s ? s->err : g_server_error; }
+const char* rhd_server_last_error(const rhd_server_t* s) {
+  if (!s) return g_server_error;
+  // a copy for the calling thread, taken under the message's lock
+  thread_local char copy[256];
+  auto* m = const_cast<rhd_server_t*>(s);
+  std::lock_guard<std::mutex> lk(m->err_mu);
+  std::snprintf(copy, sizeof(copy), "%s", m->err);
+  return copy;
+}
 
 }  // extern "C"

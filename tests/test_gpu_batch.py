@@ -163,6 +163,32 @@ def test_batch_rejects_bad_members():
             s.close()
 
 
+def test_destroying_a_member_removes_it_from_its_batch():
+    """rhd_destroy on a batch member takes it out of the batch first: the batch shrinks
+    and steps its remaining member, whose result still equals its lone run."""
+    announce("destroy a batch member")
+    pa, pb_ = problem(*PROBLEMS[0]), problem(*PROBLEMS[2])
+    b = P.rhd_batch_create(2, 8, 16)
+    sa, sb = P.Solver(pa["spec"]), P.Solver(pb_["spec"])
+    try:
+        sa.set_state(pa["state"])
+        sb.set_state(pb_["state"])
+        P.rhd_batch_add(b, sa.h, pa["chat"])
+        P.rhd_batch_add(b, sb.h, pb_["chat"])
+        assert P.rhd_batch_size(b) == 2
+        sb.close()  # rhd_destroy of a member
+        assert P.rhd_batch_size(b) == 1
+        for _ in range(2):
+            P.rhd_batch_step(b)
+        P.rhd_batch_sync(b)
+        got = sa.get_state()
+    finally:
+        P.rhd_batch_destroy(b)
+        sa.close()
+    ref = alone(pa, 2)
+    assert_parity(pa["spec"], got, ref, 1e-6, "max", label="remaining member vs alone")
+
+
 def test_served_results_equal_one_at_a_time_results():
     """Continuous batching with staggered arrivals and a memory budget that admits only
     part of the stream at once gives every request its one-at-a-time result (to FP32
