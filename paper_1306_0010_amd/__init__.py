@@ -255,6 +255,22 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+# cells of every live handle, recorded at rhd_create: the C functions read and write
+# that many values (three per cell for momentum and flux) through the pointers passed
+_CELLS = {}
+
+
+def _check_len(name, a, n):
+    if a is not None and a.size != n:
+        raise ValueError(f"{name} holds {a.size} values, the grid needs {n}")
+
+
+def _cells(h):
+    if h not in _CELLS:
+        raise ValueError("unknown or destroyed handle")
+    return _CELLS[h]
+
+
 # ---------------------------------------------------------------------------
 # the C functions, same names
 # ---------------------------------------------------------------------------
@@ -271,12 +287,18 @@ def rhd_create(params, stream=None):
     h = ctypes.c_void_p()
     _check(lib().rhd_create(ctypes.byref(params), ctypes.c_void_p(stream) if stream else None,
                             ctypes.byref(h)))
+    _CELLS[h.value] = int(params.nx) * int(params.ny) * int(params.nz)
     return h.value
 
 
 def rhd_set_state(h, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scalar):
     arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
             for a in (rho, mom, E, Er, Fr, kappaP, kappaF)]
+    n = _cells(h)
+    nk = 1 if kappa_scalar else n
+    for name, a, m in zip(("rho", "mom", "E", "Er", "Fr", "kappaP", "kappaF"), arrs,
+                          (n, 3 * n, n, n, 3 * n, nk, nk)):
+        _check_len(name, a, m)
     ptrs = [_dptr(a) if a is not None else None for a in arrs]
     _check(lib().rhd_set_state(h, *ptrs, int(kappa_scalar)), h)
 
@@ -291,6 +313,7 @@ def rhd_set_emission(h, j):
         _check(lib().rhd_set_emission(h, None), h)
         return
     a = np.ascontiguousarray(j, dtype=np.float64)
+    _check_len("j", a, _cells(h))
     _check(lib().rhd_set_emission(h, _dptr(a)), h)
 
 
@@ -334,6 +357,8 @@ def rhd_ledger(h, chat):
 
 
 def rhd_get_state(h, N):
+    if N != _cells(h):
+        raise ValueError(f"the handle's grid has {_cells(h)} cells, not {N}")
     out = {"rho": np.empty(N), "mom": np.empty(3 * N), "E": np.empty(N), "Er": np.empty(N),
            "Fr": np.empty(3 * N)}
     _check(lib().rhd_get_state(h, _dptr(out["rho"]), _dptr(out["mom"]), _dptr(out["E"]),
@@ -457,6 +482,11 @@ def rhd_server_submit(s, params, rho, mom, E, Er, Fr, kappaP, kappaF, kappa_scal
     """Queue a request; returns its id. The arrays are copied before the call returns."""
     arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
             for a in (rho, mom, E, Er, Fr, kappaP, kappaF, j)]
+    n = int(params.nx) * int(params.ny) * int(params.nz)
+    nk = 1 if kappa_scalar else n
+    for name, a, m in zip(("rho", "mom", "E", "Er", "Fr", "kappaP", "kappaF", "j"), arrs,
+                          (n, 3 * n, n, n, 3 * n, nk, nk, n)):
+        _check_len(name, a, m)
     ptrs = [_dptr(a) if a is not None else None for a in arrs]
     rid = ctypes.c_longlong()
     _scheck(lib().rhd_server_submit(s, ctypes.byref(params), *ptrs[:7], int(kappa_scalar), ptrs[7],
@@ -539,6 +569,7 @@ def rhd_footprint_bytes(params):
 def rhd_destroy(h):
     if h:
         lib().rhd_destroy(h)
+        _CELLS.pop(h, None)
 
 
 def rhd_last_error(h=None):

@@ -4,6 +4,8 @@ the per-cell kernels, while one just below the limit accepts them. (FP64, radiat
 only: about 60 GB of device memory per handle, nothing stepped.)"""
 import sys
 
+import numpy as np
+
 import pytest
 
 import paper_1306_0010_amd as P
@@ -35,3 +37,35 @@ def test_tiled_kernels_need_arrays_below_4_gib(n, tiled_ok):
             assert e.value.code == P.RHD_EINVAL
     finally:
         P.rhd_destroy(h)
+
+
+def test_binding_checks_array_sizes_before_the_call():
+    """The binding knows each handle's cell count and refuses arrays of another size
+    before the C function could read or write past them."""
+    print("[gpu case] binding array sizes", flush=True)
+    spec = ri.default_spec(nx=8, ny=6, nz=4, dx=1 / 8, dy=1 / 6, dz=1 / 4)
+    st = ri.smooth_random_state(spec, seed=3)
+    h = P.rhd_create(P.params_from_spec(spec))
+    n = 8 * 6 * 4
+    try:
+        flat = lambda k: st[k].ravel()
+        mom = lambda: np.stack([st["mx"], st["my"], st["mz"]]).ravel()
+        fr = lambda: np.stack([st["Fx"], st["Fy"], st["Fz"]]).ravel()
+        with pytest.raises(ValueError):
+            P.rhd_set_state(h, flat("rho")[:-1], mom(), flat("E"), flat("Er"), fr(),
+                            flat("kP"), flat("kF"), 0)
+        with pytest.raises(ValueError):
+            P.rhd_set_state(h, flat("rho"), mom(), flat("E"), flat("Er"), fr()[: 3 * n - 3],
+                            flat("kP"), flat("kF"), 0)
+        with pytest.raises(ValueError):
+            P.rhd_get_state(h, n + 1)
+        with pytest.raises(ValueError):
+            P.rhd_set_emission(h, np.ones(n - 1))
+        P.rhd_set_state(h, flat("rho"), mom(), flat("E"), flat("Er"), fr(), flat("kP"),
+                        flat("kF"), 0)
+        out = P.rhd_get_state(h, n)
+        assert np.allclose(out["rho"], flat("rho"))
+    finally:
+        P.rhd_destroy(h)
+    with pytest.raises(ValueError):
+        P.rhd_get_state(h, n)  # destroyed
