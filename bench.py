@@ -857,7 +857,7 @@ def main():
     ap.add_argument("--c4-steps", type=int, default=100,
                     help="gas steps of the 256^3 dusty-shell measurement (0 skips it)")
     ap.add_argument("--no-c2", action="store_true", help="skip the 128^3 coupled box")
-    ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell", "c2", "c4"),
+    ap.add_argument("--only", choices=("marshak", "shadow", "pulse", "shell", "c2", "c4", "c5"),
                     help="run only this workload's timing and print its record (for "
                          "profiling one workload)")
     ap.add_argument("--graph", type=int, default=0,
@@ -890,7 +890,7 @@ def main():
     for m in modes:
         if m not in SERVE_MODES:
             raise SystemExit(f"unknown served mode {m!r}")
-    if args.serve_requests > 0 and not only:
+    if args.serve_requests > 0 and (not only or args.only == "c5"):
         pert, el = c5_prepare(args.serve_requests, max(1, min(16, host_info()["usable_cpus"])))
         progress(f"served stream synthesised ({el:.1f} s)")
 
@@ -907,7 +907,9 @@ def main():
     if args.only:
         fn = {"marshak": marshak_timing, "shadow": shadow_timing, "pulse": pulse_timing,
               "shell": shell_timing, "c2": c2_measurement,
-              "c4": lambda P_, ri_, st_: c4_measurement(P_, ri_, st_, args.c4_steps)}[args.only]
+              "c4": lambda P_, ri_, st_: c4_measurement(P_, ri_, st_, args.c4_steps),
+              "c5": lambda P_, ri_, st_: serving(args.serve_requests, args.serve_load, pert,
+                                                 modes)}[args.only]
         print(json.dumps({args.only: fn(P, ri, stream)}), flush=True)
         return
 

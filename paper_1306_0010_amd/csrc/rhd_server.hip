@@ -1,6 +1,8 @@
 // Served form: a worker thread that admits independent 3D solves under a device-memory
-// budget and a slot limit, advances every running solve one gas step per round through
-// the batch interface, and hands results back in host memory. The server is a client of
+// budget and a slot limit and advances every running solve one gas step per round through
+// the batch interface, and two transfer threads, one that sets solves up (handle, state
+// upload) and one that takes them down (result read back to host memory, handle freed),
+// while the worker keeps the device busy with the others. The server is a client of
 // the public C interface (include/rhd.h) and owns no kernels; every solve still takes the
 // step of Sec. 3.1 (gas CFL step of Eq. algorithm:gastimestep, subcycle count of
 // Eq. algorithm:radtimestep at the request's reduced speed of light).
@@ -73,11 +75,25 @@ struct rhd_server {
   // the worker, so it has a lock of its own
   std::mutex err_mu;
   char err[256] = "";
+  // work for the transfer threads (guarded by mu): queue 0 sets requests up, queue 1
+  // reads results back or frees requests; and the requests set up, waiting to join a
+  // batch
+  struct Job {
+    ReqPtr r;
+    int kind = 0;       // JOB_PREPARE, JOB_COLLECT or JOB_DISCARD
+    int status = 0;     // JOB_DISCARD: the final status; JOB_COLLECT: 0 or the failure code
+    int error = 0;
+    std::string why;    // message of a failure
+  };
+  std::deque<Job> jobs[2];
+  std::vector<ReqPtr> ready;
+  bool xstop = false;  // the transfer threads drain their jobs and end
+  std::condition_variable cv_xfer[2];
   // worker-only state: one batch per precision (0 FP64, 1 mixed) and its members in
   // batch order
   rhd_batch_t* batch[2] = {nullptr, nullptr};
   std::vector<ReqPtr> members[2];
-  std::thread worker;
+  std::thread worker, xfer[2];
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -129,7 +145,10 @@ void drop_all(Request& r) {
   std::vector<double>().swap(r.Fr);
 }
 
-// Called with the lock held: the request leaves the running set with a final status.
+enum { JOB_PREPARE = 0, JOB_COLLECT = 1, JOB_DISCARD = 2 };
+
+// Called with the lock held: the request leaves the running set with a final status,
+// and its budget and slot go to the next ones.
 void retire(rhd_server* s, Request& r, int status, int error) {
   r.status = status;
   r.error = error;
@@ -142,24 +161,25 @@ void retire(rhd_server* s, Request& r, int status, int error) {
   else s->stats.cancelled += 1;
   if (status == RHD_REQ_CANCELLED) drop_all(r);
   s->cv_done.notify_all();
+  s->cv_work.notify_one();
 }
 
-// Worker: leave the batch and free the handle (no lock held).
-void release_handle(rhd_server* s, Request& r, int prec) {
-  if (!r.h) return;
-  auto& m = s->members[prec];
-  for (size_t i = 0; i < m.size(); ++i)
-    if (m[i].get() == &r) {
-      (void)rhd_batch_remove(s->batch[prec], r.h);
-      m.erase(m.begin() + long(i));
-      break;
-    }
-  rhd_destroy(r.h);
-  r.h = nullptr;
+// Called with the lock held: hand a job to its transfer thread.
+void post(rhd_server* s, rhd_server::Job job) {
+  const int q = job.kind == JOB_PREPARE ? 0 : 1;
+  s->jobs[q].push_back(std::move(job));
+  s->cv_xfer[q].notify_one();
 }
 
-// Worker: create, fill and enrol one admitted request. Returns an RHD_* code.
-int start_request(rhd_server* s, Request& r, char* msg) {
+// Called with the lock held: the oldest queued request fits the budget and a slot.
+bool can_admit(const rhd_server* s) {
+  return !s->queue.empty() && s->stats.running < s->max_slots &&
+         s->used + s->queue.front()->footprint <= s->budget;
+}
+
+// Transfer thread: create the handle and upload the state of an admitted request (the
+// handle's own stream; no batch involved). Returns an RHD_* code.
+int prepare_request(Request& r, char* msg) {
   rhd_t* h = nullptr;
   int rc = rhd_create(&r.p, nullptr, &h);
   if (rc) {
@@ -174,95 +194,173 @@ int start_request(rhd_server* s, Request& r, char* msg) {
     rhd_destroy(h);
     return rc;
   }
-  const int prec = r.mixed ? 1 : 0;
-  if (!s->batch[prec]) {
-    rc = rhd_batch_create(nullptr, s->max_slots, s->rows, s->zchunk, &s->batch[prec]);
-    if (rc) {
-      std::snprintf(msg, 256, "rhd_batch_create: %s", rhd_batch_last_error(nullptr));
-      rhd_destroy(h);
-      return rc;
-    }
-    if (s->persistent) (void)rhd_batch_set_persistent(s->batch[prec], 1);
-  }
-  rc = rhd_batch_add(s->batch[prec], h, r.chat);
-  if (rc) {
-    std::snprintf(msg, 256, "rhd_batch_add: %s", rhd_batch_last_error(s->batch[prec]));
-    rhd_destroy(h);
-    return rc;
-  }
   r.h = h;
   drop_inputs(r);
   return RHD_OK;
 }
 
-// Worker: copy the final state and diagnostics of a request that took its steps.
-int finish_request(rhd_server* s, Request& r, int prec) {
-  auto& m = s->members[prec];
-  for (size_t i = 0; i < m.size(); ++i)
-    if (m[i].get() == &r) {
-      (void)rhd_batch_remove(s->batch[prec], r.h);
-      m.erase(m.begin() + long(i));
-      break;
-    }
+// Transfer thread: copy the final state and diagnostics of a request out of its handle
+// (which has left its batch) and free the handle. fail is the code of a failure already
+// known (the state is still copied, as computed); returns the request's final code.
+int collect_request(Request& r, int fail) {
   int rc = rhd_get_state(r.h, r.rho.data(), r.mom.data(), r.have_E ? r.E.data() : nullptr,
                          r.Er.data(), r.Fr.data());
-  if (!rc) rc = rhd_get_diagnostics(r.h, &r.diag);
+  rhd_diag d{};
+  const int rd = rhd_get_diagnostics(r.h, &d);
+  if (rd == RHD_OK) r.diag = d;
+  if (!rc) rc = rd;
   if (!rc && r.diag.nonfinite > 0) rc = RHD_ENONFINITE;
   rhd_destroy(r.h);
   r.h = nullptr;
-  return rc;
+  return fail ? fail : rc;
+}
+
+// Transfer thread q: 0 takes the set-up jobs, 1 the read-back and free jobs.
+void xfer_main(rhd_server* s, int q) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    rhd_server::Job job;
+    bool cleanup;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_xfer[q].wait(lk, [&] { return s->xstop || !s->jobs[q].empty(); });
+      if (s->jobs[q].empty()) break;
+      job = std::move(s->jobs[q].front());
+      s->jobs[q].pop_front();
+      cleanup = s->stop;
+    }
+    Request& r = *job.r;
+    if (job.kind == JOB_PREPARE) {
+      bool skip;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        skip = cleanup || r.cancel;
+      }
+      char msg[256] = "";
+      const int rc = skip ? RHD_OK : prepare_request(r, msg);
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (skip) {
+        retire(s, r, RHD_REQ_CANCELLED, RHD_OK);
+      } else if (rc) {
+        sfail(s, rc, "request %lld: %s", r.id, msg);
+        retire(s, r, RHD_REQ_FAILED, rc);
+      } else {
+        s->ready.push_back(job.r);
+        s->cv_work.notify_one();
+      }
+    } else if (job.kind == JOB_COLLECT) {
+      const int rc = collect_request(r, job.status);
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (rc) {
+        if (!job.why.empty()) sfail(s, rc, "request %lld: %s", r.id, job.why.c_str());
+        else sfail(s, rc, "request %lld: final state: code %d", r.id, rc);
+        retire(s, r, RHD_REQ_FAILED, rc);
+      } else {
+        retire(s, r, RHD_REQ_DONE, RHD_OK);
+      }
+    } else {
+      if (r.h) rhd_destroy(r.h);
+      r.h = nullptr;
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (job.status == RHD_REQ_FAILED) sfail(s, job.error, "request %lld: %s", r.id, job.why.c_str());
+      retire(s, r, job.status, job.error);
+    }
+  }
+}
+
+// Worker: take a member out of its batch (no lock held); the handle stays alive.
+void leave_batch(rhd_server* s, const ReqPtr& r, int prec) {
+  auto& m = s->members[prec];
+  for (size_t i = 0; i < m.size(); ++i)
+    if (m[i] == r) {
+      (void)rhd_batch_remove(s->batch[prec], r->h);
+      m.erase(m.begin() + long(i));
+      return;
+    }
 }
 
 void worker_main(rhd_server* s) {
   (void)hipSetDevice(s->device);
   std::vector<int> nsub;
   for (;;) {
-    std::vector<ReqPtr> admit, cancelled;
+    std::vector<ReqPtr> enrol, cancelled;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] {
-        return s->stop || !s->queue.empty() || !s->members[0].empty() || !s->members[1].empty();
+        return s->stop || !s->ready.empty() || !s->members[0].empty() ||
+               !s->members[1].empty() || can_admit(s);
       });
       if (s->stop) break;
       for (int prec = 0; prec < 2; ++prec)
         for (auto& r : s->members[prec])
           if (r->cancel) cancelled.push_back(r);
-      // admission in submission order: stop at the first request that does not fit
-      int slots = int(s->members[0].size() + s->members[1].size() - cancelled.size());
-      long long used = s->used;
-      for (const auto& r : cancelled) used -= r->footprint;
-      while (!s->queue.empty() && slots < s->max_slots &&
-             used + s->queue.front()->footprint <= s->budget) {
+      // admission in submission order: stop at the first request that does not fit; an
+      // admitted request holds its budget and slot from here until it is retired
+      while (can_admit(s)) {
         ReqPtr r = s->queue.front();
         s->queue.pop_front();
-        used += r->footprint;
         s->used += r->footprint;
-        ++slots;
+        s->stats.running += 1;
         r->status = RHD_REQ_RUNNING;
         r->t_start = s->now();
-        admit.push_back(r);
+        rhd_server::Job job;
+        job.r = r;
+        job.kind = JOB_PREPARE;
+        post(s, std::move(job));
       }
       s->stats.queued = int(s->queue.size());
-      s->stats.running += int(admit.size());
       s->stats.peak_running = std::max(s->stats.peak_running, s->stats.running);
       s->stats.bytes_in_use = s->used;
-      s->stats.peak_bytes = std::max(s->stats.peak_bytes, used);
+      s->stats.peak_bytes = std::max(s->stats.peak_bytes, s->used);
+      // requests the transfer thread has set up join their batch below; one cancelled
+      // meanwhile is freed instead
+      for (auto& r : s->ready) {
+        if (r->cancel) {
+          rhd_server::Job job;
+          job.r = r;
+          job.kind = JOB_DISCARD;
+          job.status = RHD_REQ_CANCELLED;
+          post(s, std::move(job));
+        } else {
+          enrol.push_back(r);
+        }
+      }
+      s->ready.clear();
     }
     for (auto& r : cancelled) {
-      release_handle(s, *r, r->mixed ? 1 : 0);
+      leave_batch(s, r, r->mixed ? 1 : 0);
       std::lock_guard<std::mutex> lk(s->mu);
-      retire(s, *r, RHD_REQ_CANCELLED, RHD_OK);
+      rhd_server::Job job;
+      job.r = r;
+      job.kind = JOB_DISCARD;
+      job.status = RHD_REQ_CANCELLED;
+      post(s, std::move(job));
     }
-    for (auto& r : admit) {
-      char msg[256] = "";
-      const int rc = start_request(s, *r, msg);
+    for (auto& r : enrol) {
+      const int prec = r->mixed ? 1 : 0;
+      int rc = RHD_OK;
+      std::string why;
+      if (!s->batch[prec]) {
+        rc = rhd_batch_create(nullptr, s->max_slots, s->rows, s->zchunk, &s->batch[prec]);
+        if (rc) why = std::string("rhd_batch_create: ") + rhd_batch_last_error(nullptr);
+        else if (s->persistent) (void)rhd_batch_set_persistent(s->batch[prec], 1);
+      }
+      if (!rc) {
+        rc = rhd_batch_add(s->batch[prec], r->h, r->chat);
+        if (rc) why = std::string("rhd_batch_add: ") + rhd_batch_last_error(s->batch[prec]);
+      }
       std::lock_guard<std::mutex> lk(s->mu);
       if (rc) {
-        sfail(s, rc, "request %lld: %s", r->id, msg);
-        retire(s, *r, RHD_REQ_FAILED, rc);
+        rhd_server::Job job;
+        job.r = r;
+        job.kind = JOB_DISCARD;
+        job.status = RHD_REQ_FAILED;
+        job.error = rc;
+        job.why = why;
+        post(s, std::move(job));
       } else {
-        // a request cancelled while it was set up leaves at the top of the next round
-        s->members[r->mixed ? 1 : 0].push_back(r);
+        // a request cancelled while it joined leaves at the top of the next round
+        s->members[prec].push_back(r);
       }
     }
     // one round: every running request takes one gas step
@@ -292,32 +390,26 @@ void worker_main(rhd_server* s) {
         for (size_t i = 0; i < m.size(); ++i)
           if (nsub[i] == -1) bad = int(i);
         const std::string why = rhd_batch_last_error(s->batch[prec]);
-        if (bad >= 0) {
-          ReqPtr r = m[size_t(bad)];
-          rhd_diag d{};
-          if (rhd_get_diagnostics(r->h, &d) == RHD_OK) r->diag = d;
-          (void)rhd_get_state(r->h, r->rho.data(), r->mom.data(),
-                              r->have_E ? r->E.data() : nullptr, r->Er.data(), r->Fr.data());
-          release_handle(s, *r, prec);
-          std::lock_guard<std::mutex> lk(s->mu);
-          sfail(s, rc, "request %lld: %s", r->id, why.c_str());
-          retire(s, *r, RHD_REQ_FAILED, rc);
-          continue;
-        }
-        // a device failure: every member of this batch fails, with its state as it is
-        std::vector<ReqPtr> gone(m.begin(), m.end());
-        for (auto& r : gone) {
-          (void)rhd_get_state(r->h, r->rho.data(), r->mom.data(),
-                              r->have_E ? r->E.data() : nullptr, r->Er.data(), r->Fr.data());
-          release_handle(s, *r, prec);
-        }
+        std::vector<ReqPtr> gone;
+        if (bad >= 0) gone.push_back(m[size_t(bad)]);
+        else gone.assign(m.begin(), m.end());  // a device failure: the whole batch fails
+        for (auto& r : gone) leave_batch(s, r, prec);
         std::lock_guard<std::mutex> lk(s->mu);
-        sfail(s, rc, "batch step: %s", why.c_str());
-        for (auto& r : gone) retire(s, *r, RHD_REQ_FAILED, rc);
+        if (bad < 0) sfail(s, rc, "batch step: %s", why.c_str());
+        for (auto& r : gone) {
+          // the state is still copied out, as computed
+          rhd_server::Job job;
+          job.r = r;
+          job.kind = JOB_COLLECT;
+          job.status = rc;
+          job.why = why;
+          post(s, std::move(job));
+        }
       }
     }
-    // requests that took all their steps leave and hand their slot on; one cancelled
-    // during its last round counts as cancelled
+    // requests that took all their steps leave their batch and go to the transfer
+    // thread, which copies their results out; one cancelled during its last round counts
+    // as cancelled
     for (int prec = 0; prec < 2; ++prec) {
       std::vector<ReqPtr> done;
       std::vector<bool> dropped;
@@ -330,26 +422,17 @@ void worker_main(rhd_server* s) {
           }
       }
       for (size_t k = 0; k < done.size(); ++k) {
-        Request& r0 = *done[k];
-        if (dropped[k]) {
-          release_handle(s, r0, prec);
-          std::lock_guard<std::mutex> lk(s->mu);
-          retire(s, r0, RHD_REQ_CANCELLED, RHD_OK);
-          continue;
-        }
-        auto& r = done[k];
-        const int rc = finish_request(s, *r, prec);
+        leave_batch(s, done[k], prec);
         std::lock_guard<std::mutex> lk(s->mu);
-        if (rc) {
-          sfail(s, rc, "request %lld: final state: code %d", r->id, rc);
-          retire(s, *r, RHD_REQ_FAILED, rc);
-        } else {
-          retire(s, *r, RHD_REQ_DONE, RHD_OK);
-        }
+        rhd_server::Job job;
+        job.r = done[k];
+        job.kind = dropped[k] ? JOB_DISCARD : JOB_COLLECT;
+        job.status = dropped[k] ? RHD_REQ_CANCELLED : 0;
+        post(s, std::move(job));
       }
     }
   }
-  // stopping: free every handle and batch
+  // stopping: free every member's handle and every batch
   for (int prec = 0; prec < 2; ++prec) {
     for (auto& r : s->members[prec]) {
       if (r->h) rhd_destroy(r->h);
@@ -384,11 +467,24 @@ int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int 
   s->zchunk = zchunk;
   s->device = dev;
   s->t0 = Clock::now();
+  auto stop_transfers = [](rhd_server* sv) {
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->xstop = true;
+      sv->cv_xfer[0].notify_all();
+      sv->cv_xfer[1].notify_all();
+    }
+    for (auto& t : sv->xfer)
+      if (t.joinable()) t.join();
+  };
   try {
+    s->xfer[0] = std::thread(xfer_main, s, 0);
+    s->xfer[1] = std::thread(xfer_main, s, 1);
     s->worker = std::thread(worker_main, s);
   } catch (...) {
+    stop_transfers(s);
     delete s;
-    return sfail(nullptr, RHD_EDEVICE, "cannot start the worker thread");
+    return sfail(nullptr, RHD_EDEVICE, "cannot start the server's threads");
   }
   *out = s;
   return RHD_OK;
@@ -556,6 +652,22 @@ void rhd_server_destroy(rhd_server_t* s) {
     s->cv_work.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  // the worker has freed its members; the transfer threads free what they still hold
+  // (jobs queued after stop skip their uploads) and end
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->xstop = true;
+    s->cv_xfer[0].notify_all();
+    s->cv_xfer[1].notify_all();
+  }
+  for (auto& t : s->xfer)
+    if (t.joinable()) t.join();
+  for (auto& r : s->ready)
+    if (r->h) {
+      rhd_destroy(r->h);
+      r->h = nullptr;
+    }
+  s->ready.clear();
   delete s;
 }
 
