@@ -358,9 +358,9 @@ const char* rhd_batch_last_error(const rhd_batch_t* b);
    admits the oldest ones while the sum of their rhd_footprint_bytes stays within the
    budget and at most max_slots run, and advances every running request one gas step per
    round through batches (rhd_batch_*, one per precision) with tiles of tile_rows x zchunk.
-   Two transfer threads work beside it: one creates an admitted request's handle and
-   uploads its state, the other copies a finished request's state to host memory and frees
-   its handle, so the batch keeps stepping meanwhile. A request leaves as soon as it has
+   Transfer threads work beside it (six for each direction): they create admitted
+   requests' handles and upload their states, and copy finished requests' states to host
+   memory and free their handles, so the batch keeps stepping meanwhile. A request leaves as soon as it has
    taken its steps: its state is copied to host memory, its device memory and slot are
    freed and the next requests are admitted. Every call
    below may come from any host thread. None of this is from the paper: it serves many

@@ -1,7 +1,7 @@
 // Served form: a worker thread that admits independent 3D solves under a device-memory
 // budget and a slot limit and advances every running solve one gas step per round through
-// the batch interface, and two transfer threads, one that sets solves up (handle, state
-// upload) and one that takes them down (result read back to host memory, handle freed),
+// the batch interface, and transfer threads, some that set solves up (handle, state
+// upload) and some that take them down (result read back to host memory, handle freed),
 // while the worker keeps the device busy with the others. The server is a client of
 // the public C interface (include/rhd.h) and owns no kernels; every solve still takes the
 // step of Sec. 3.1 (gas CFL step of Eq. algorithm:gastimestep, subcycle count of
@@ -93,7 +93,10 @@ struct rhd_server {
   // batch order
   rhd_batch_t* batch[2] = {nullptr, nullptr};
   std::vector<ReqPtr> members[2];
-  std::thread worker, xfer[2];
+  // transfer threads per queue: host-device copies from pageable memory are staged by the
+  // runtime through the CPU, so several threads in parallel move more bytes per second
+  static constexpr int XFER_THREADS = 6;
+  std::thread worker, xfer[2 * XFER_THREADS];
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -215,7 +218,7 @@ int collect_request(Request& r, int fail) {
   return fail ? fail : rc;
 }
 
-// Transfer thread q: 0 takes the set-up jobs, 1 the read-back and free jobs.
+// A transfer thread of queue q: 0 takes the set-up jobs, 1 the read-back and free jobs.
 void xfer_main(rhd_server* s, int q) {
   (void)hipSetDevice(s->device);
   for (;;) {
@@ -478,8 +481,8 @@ int rhd_server_create(long long budget_bytes, int max_slots, int tile_rows, int 
       if (t.joinable()) t.join();
   };
   try {
-    s->xfer[0] = std::thread(xfer_main, s, 0);
-    s->xfer[1] = std::thread(xfer_main, s, 1);
+    for (int t = 0; t < 2 * rhd_server::XFER_THREADS; ++t)
+      s->xfer[t] = std::thread(xfer_main, s, t % 2);
     s->worker = std::thread(worker_main, s);
   } catch (...) {
     stop_transfers(s);
