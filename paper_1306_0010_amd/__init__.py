@@ -620,20 +620,42 @@ def params_from_spec(spec):
 
 
 def _flat_state(st, shape):
-    """The flat host arrays of a state dict, as rhd_set_state takes them."""
-    flat = lambda k: np.ascontiguousarray(np.broadcast_to(st[k], shape), dtype=np.float64).ravel()
+    """The flat host arrays of a state dict, as rhd_set_state takes them. A field may be a
+    full (nz, ny, nx) array or a uniform value (a scalar or a one-element array)."""
+    n = int(np.prod(shape))
+
+    def uniform(v):
+        return v.size == 1
+
+    def fill(out, k):
+        v = np.asarray(st[k], dtype=np.float64)
+        if uniform(v):
+            out.fill(float(v.reshape(-1)[0]))
+        else:
+            out[:] = np.broadcast_to(v, shape).reshape(-1)
+
+    def flat(k):
+        out = np.empty(n)
+        fill(out, k)
+        return out
+
+    def flat3(keys):
+        out = np.empty(3 * n)
+        for i, k in enumerate(keys):
+            fill(out[i * n:(i + 1) * n], k)
+        return out
+
     kP = np.asarray(st["kP"], dtype=np.float64)
     kF = np.asarray(st["kF"], dtype=np.float64)
-    scalar = kP.size == 1 or (np.all(kP == kP.flat[0]) and np.all(kF == kF.flat[0]))
+    scalar = ((uniform(kP) or bool(np.all(kP == kP.flat[0]))) and
+              (uniform(kF) or bool(np.all(kF == kF.flat[0]))))
     if scalar:
         kPa, kFa = np.array([kP.flat[0]]), np.array([kF.flat[0]])
     else:
         kPa, kFa = flat("kP"), flat("kF")
-    return {"rho": flat("rho"), "mom": np.concatenate([flat("mx"), flat("my"), flat("mz")]),
-            "E": flat("E"), "Er": flat("Er"),
-            "Fr": np.concatenate([flat("Fx"), flat("Fy"), flat("Fz")]),
-            "kP": kPa, "kF": kFa, "scalar": int(scalar),
-            "j": flat("j") if st.get("j") is not None else None}
+    return {"rho": flat("rho"), "mom": flat3(("mx", "my", "mz")), "E": flat("E"),
+            "Er": flat("Er"), "Fr": flat3(("Fx", "Fy", "Fz")), "kP": kPa, "kF": kFa,
+            "scalar": int(scalar), "j": flat("j") if st.get("j") is not None else None}
 
 
 def _shaped_state(raw, shape):

@@ -212,6 +212,7 @@ def serve_native(requests, make_problem, budget_bytes=16 << 30, max_slots=64, ti
             pb = problems[req["id"]]
             late = (time.perf_counter() - t0) - req["arrival"]
             ids.append((srv.submit(pb["spec"], pb["state"], pb["chat"], req["steps"]), req, late))
+        submitted = time.perf_counter() - t0
         for rid, req, late in ids:
             info = srv.wait(rid)
             out, _, rc = srv.fetch(rid)
@@ -228,7 +229,8 @@ def serve_native(requests, make_problem, budget_bytes=16 << 30, max_slots=64, ti
                "elapsed_s": elapsed, "zone_updates_per_s": zone_updates / elapsed,
                "p50_latency_s": p50, "p99_latency_s": p99, "peak_active": st["peak_running"],
                "batch_steps": st["rounds"], "peak_bytes": st["peak_bytes"],
-               "budget_bytes": budget_bytes, "max_slots": max_slots}
+               "budget_bytes": budget_bytes, "max_slots": max_slots,
+               "last_submission_s": submitted}
     return summary, results
 
 
