@@ -310,10 +310,13 @@ int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk
    other batch; RHD_EINVAL otherwise, or when the batch is full. While it is a member its
    work runs on the batch's stream; on the handle itself only rhd_get_state,
    rhd_get_diagnostics, rhd_ledger and rhd_sync may be called (they wait for that stream).
-   Grows the batch's tile lists (device allocation). */
+   The batch's stream waits, on the device, for the work the handle's own stream holds; the
+   host does not wait, except when the batch's tile lists must grow (device allocation),
+   where it first waits for the batch's stream. */
 int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat);
 
-/* Remove a member: waits for the batch's stream and gives the handle its own stream back. */
+/* Remove a member and give the handle its own stream back. That stream waits, on the
+   device, for the batch's work enqueued so far; the host does not wait. */
 int rhd_batch_remove(rhd_batch_t* b, rhd_t* h);
 
 /* Advance every member by one gas step with its own CFL step and subcycle count
@@ -445,10 +448,12 @@ void rhd_server_destroy(rhd_server_t* s);
    until that thread's next call of this function. */
 const char* rhd_server_last_error(const rhd_server_t* s);
 
-/* Device bytes the handle holds (state, opacities, emission and scratch). */
+/* Device bytes the handle holds (state, opacities, emission and scratch). The state and
+   scratch buffers share one allocation, each rounded up to 4 KiB. */
 long long rhd_device_bytes(const rhd_t* h);
 
-/* Device bytes a handle with these parameters would hold, without creating it. */
+/* Device bytes a handle with these parameters holds when created, before per-cell
+   opacities or an emissivity are set; equal to rhd_device_bytes of such a handle. */
 long long rhd_footprint_bytes(const rhd_params* p);
 
 /* ---- radiation subcycles without allocation ------------------------------------------ */

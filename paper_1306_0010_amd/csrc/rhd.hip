@@ -32,6 +32,9 @@ constexpr int VMAX_BLOCKS = 1024;
 constexpr int EXCH_BLOCKS = 2048;  // grid-stride exchange: 8 waves per SIMD
 
 struct Buffers {
+  // one device allocation holds every buffer below up to ctr (created with the handle);
+  // kP, kF, j and the run tables are allocated on their own when first needed
+  void* slab = nullptr;
   void* gas[5] = {};   // rho, mx, my, mz, E
   void* rad[4] = {};   // Er, Fx, Fy, Fz
   void* kP = nullptr;  // per-cell opacities (null when scalar)
@@ -252,6 +255,10 @@ rhdk::Geom make_geom(const rhd_params* p) {
   return G;
 }
 
+// A handle's buffers share one allocation, each starting on a page boundary.
+constexpr long long SLAB_ALIGN = 4096;
+constexpr long long slab_round(long long bytes) { return (bytes + SLAB_ALIGN - 1) / SLAB_ALIGN * SLAB_ALIGN; }
+
 long long footprint(const rhd_params* p, long long* N_out, long long* NP_out) {
   const bool mixed = (p->flags & RHD_PRECISION_MIXED) != 0;
   const long long es = mixed ? 4 : 8;
@@ -264,13 +271,15 @@ long long footprint(const rhd_params* p, long long* N_out, long long* NP_out) {
   if (N_out) *N_out = N;
   if (NP_out) *NP_out = NP;
   const bool gas = !(p->flags & RHD_RAD_ONLY);
+  const long long cell = slab_round(N * es), pad = slab_round(NP * es);
   long long bytes = 0;
-  bytes += 9 * N * es;                  // state
-  bytes += 4 * NP * es;                 // radiation half step
-  if (gas) bytes += 5 * NP * es + 8 * N * es;  // gas half step, s_n, W_1/2
-  bytes += N * 8;                       // staging
-  bytes += 5 * LEDGER_BLOCKS * 8 + 5 * 8 + VMAX_BLOCKS * 8 + 8 + rhdk::CTR_COUNT * 8;
-  bytes += rhdk::EXCH_STATS * EXCH_BLOCKS * 8;
+  bytes += 9 * cell;                    // state
+  bytes += 4 * pad;                     // radiation half step
+  if (gas) bytes += 5 * pad + 8 * cell; // gas half step, s_n, W_1/2
+  bytes += slab_round(N * 8);           // staging
+  bytes += slab_round(5 * LEDGER_BLOCKS * 8) + slab_round(5 * 8) + slab_round(VMAX_BLOCKS * 8) +
+           slab_round(8) + slab_round(rhdk::EXCH_STATS * EXCH_BLOCKS * 8) +
+           slab_round(rhdk::CTR_COUNT * 8);
   return bytes;
 }
 
@@ -1002,22 +1011,10 @@ void free_buffers(rhd_t* h) {
   auto fr = [](void* p) {
     if (p) (void)hipFree(p);
   };
-  for (auto& q : h->b.gas) fr(q);
-  for (auto& q : h->b.rad) fr(q);
+  fr(h->b.slab);
   fr(h->b.kP);
   fr(h->b.kF);
   fr(h->b.j);
-  for (auto& q : h->b.gh) fr(q);
-  for (auto& q : h->b.rh) fr(q);
-  for (auto& q : h->b.sn) fr(q);
-  for (auto& q : h->b.wh) fr(q);
-  fr(h->b.staging);
-  fr(h->b.ledger_partials);
-  fr(h->b.ledger);
-  fr(h->b.vmax_partials);
-  fr(h->b.vmax);
-  fr(h->b.exch_partials);
-  fr(h->b.ctr);
   fr(h->b.run_dev);
   if (h->b.run_host) (void)hipHostFree(h->b.run_host);
   for (auto& e : h->b.run_ev)
@@ -1195,16 +1192,11 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
     h->own_stream = true;
   }
   const size_t es = h->esize;
-  bool ok = true;
-  auto alloc = [&](void** ptr, size_t bytes) {
-    if (!ok) return;
-    if (hipMalloc(ptr, bytes) != hipSuccess) {
-      ok = false;
-      *ptr = nullptr;
-      return;
-    }
-    h->bytes += (long long)bytes;
-  };
+  // the handle's buffers are carved out of one allocation, each on a page boundary: a
+  // handle is then freed with one hipFree (each of which waits for the device) instead
+  // of one per buffer, which matters where solves come and go while others run
+  std::vector<std::pair<void**, size_t>> parts;
+  auto alloc = [&](void** ptr, size_t bytes) { parts.emplace_back(ptr, bytes); };
   for (auto& q : h->b.gas) alloc(&q, N * es);
   for (auto& q : h->b.rad) alloc(&q, N * es);
   for (auto& q : h->b.rh) alloc(&q, NP * es);
@@ -1221,6 +1213,20 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
   alloc(reinterpret_cast<void**>(&h->b.exch_partials),
         rhdk::EXCH_STATS * EXCH_BLOCKS * sizeof(unsigned long long));
   alloc(reinterpret_cast<void**>(&h->b.ctr), rhdk::CTR_COUNT * sizeof(unsigned long long));
+  size_t slab_bytes = 0;
+  for (const auto& pr : parts) slab_bytes += size_t(slab_round((long long)pr.second));
+  bool ok = hipMalloc(&h->b.slab, slab_bytes) == hipSuccess;
+  if (ok) {
+    char* base = static_cast<char*>(h->b.slab);
+    size_t off = 0;
+    for (const auto& pr : parts) {
+      *pr.first = base + off;
+      off += size_t(slab_round((long long)pr.second));
+    }
+    h->bytes += (long long)slab_bytes;
+  } else {
+    h->b.slab = nullptr;
+  }
   if (!ok) {
     free_buffers(h);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
@@ -1542,6 +1548,9 @@ struct rhd_batch {
   int* h_counts = nullptr;
   double* h_vmax = nullptr;
   int cap_pred = 0, cap_corr = 0;
+  // orders a joining member's stream before the batch stream, and the batch stream before
+  // a leaving member's own stream, on the device (the host does not wait)
+  hipEvent_t order_ev = nullptr;
   // persistent launch: level table and per-member counters + ticket. Switched off: the
   // launch did not finish on the GPU (rhd_batch_set_persistent refuses to enable it)
   bool persistent = false;
@@ -1592,6 +1601,9 @@ rhdk::TileGrid tile_counts(const rhd_t* h, int rows, int zc) {
 }
 
 int batch_reserve(rhd_batch_t* b, int need_pred, int need_corr) {
+  // the tile lists are read by the copies and kernels of a step still in flight
+  if (need_pred > b->cap_pred || need_corr > b->cap_corr)
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
   if (need_pred > b->cap_pred) {
     int cap = std::max(need_pred, 2 * b->cap_pred);
     if (b->d_tiles_pred) BHIP_TRY(b, hipFree(b->d_tiles_pred));
@@ -1863,6 +1875,7 @@ int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk
   ok = ok && hipMalloc(&b->d_done, size_t(max_solves + 2) * rhdk::COUNTER_STRIDE * sizeof(unsigned)) ==
                    hipSuccess;
   ok = ok && hipHostMalloc(&b->h_err, sizeof(unsigned), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     rhd_batch_destroy(b);
     return bfail(nullptr, RHD_ENOMEM, "batch allocation failed");
@@ -1900,9 +1913,11 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
     need_p += pred_tiles(m);
     need_c += t2.corr[0] * t2.corr[1] * t2.corr[2];
   }
-  BHIP_TRY(b, hipStreamSynchronize(b->stream));
-  BHIP_TRY(b, hipStreamSynchronize(h->stream));
   if (int rc = batch_reserve(b, need_p, need_c)) return rc;
+  // the batch stream takes over the member: its work waits for what the member's own
+  // stream holds (the state upload, for instance)
+  BHIP_TRY(b, hipEventRecord(b->order_ev, h->stream));
+  BHIP_TRY(b, hipStreamWaitEvent(b->stream, b->order_ev, 0));
   b->precision = prec;
   b->members.push_back(h);
   b->chat.push_back(chat);
@@ -1917,7 +1932,9 @@ int rhd_batch_remove(rhd_batch_t* b, rhd_t* h) {
   if (!b || !h) return bfail(b, RHD_EINVAL, "batch or handle is NULL");
   for (size_t i = 0; i < b->members.size(); ++i) {
     if (b->members[i] != h) continue;
-    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    // the member's own stream takes over after the batch's work enqueued so far
+    BHIP_TRY(b, hipEventRecord(b->order_ev, b->stream));
+    BHIP_TRY(b, hipStreamWaitEvent(b->saved_streams[i], b->order_ev, 0));
     h->stream = b->saved_streams[i];
     h->in_batch = false;
     h->batch = nullptr;
@@ -1974,6 +1991,7 @@ void rhd_batch_destroy(rhd_batch_t* b) {
   if (b->h_level) (void)hipHostFree(b->h_level);
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->h_err) (void)hipHostFree(b->h_err);
+  if (b->order_ev) (void)hipEventDestroy(b->order_ev);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

@@ -20,8 +20,9 @@ gas step each in turn, so the steps of different solves run on the device at the
 time and a solve with few subcycles is not held back by one with many.
 
 ``serve_native`` hands the same stream to the native server (``rhd_server_*``): the
-client only submits each request at its arrival and collects the results, while the
-server's own worker thread admits, batches, steps and retires the solves. The initial
+client only submits each request at its arrival and a few client threads collect the
+results, while the server's own worker thread admits, batches, steps and retires the
+solves. The initial
 states are synthesised before the clock starts.
 
 ``serve_serial`` runs the same requests one at a time with one handle each, for
@@ -30,6 +31,7 @@ comparison.
 from __future__ import annotations
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -195,33 +197,44 @@ def serve_concurrent(requests, make_problem, budget_bytes=16 << 30, max_slots=16
 
 
 def serve_native(requests, make_problem, budget_bytes=16 << 30, max_slots=64, tile_rows=8,
-                 zchunk=8, keep_results=False):
+                 zchunk=8, keep_results=False, collectors=4):
     """Serve ``requests`` through the native server. A request's latency runs from its
     arrival to the moment the server holds its final state in host memory (its
-    ``t_done``). Returns a summary dict and, with keep_results, the final states by id."""
+    ``t_done``). The calling thread submits each request at its arrival; ``collectors``
+    client threads wait for the results and copy them out meanwhile, as separate clients
+    would (a single thread that also copies every result out falls behind the server).
+    Returns a summary dict and, with keep_results, the final states by id."""
     order = sorted(requests, key=lambda r: r["arrival"])
     problems = {r["id"]: make_problem(r) for r in order}
-    lat, results, zone_updates = {}, {}, 0
-    with Server(budget_bytes, max_slots, tile_rows, zchunk) as srv:
+    lat, results = {}, {}
+
+    def collect(srv, rid, req, late):
+        info = srv.wait(rid)
+        out, _, rc = srv.fetch(rid)
+        if rc:
+            raise RhdError(rc, f"request {req['id']} failed")
+        return req["id"], late + info["t_done"] - info["t_submit"], info["zone_updates"], out
+
+    with Server(budget_bytes, max_slots, tile_rows, zchunk) as srv, \
+            ThreadPoolExecutor(max_workers=max(1, collectors)) as pool:
         t0 = time.perf_counter()
-        ids = []
+        futures = []
         for req in order:
             wait = req["arrival"] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
             pb = problems[req["id"]]
             late = (time.perf_counter() - t0) - req["arrival"]
-            ids.append((srv.submit(pb["spec"], pb["state"], pb["chat"], req["steps"]), req, late))
+            rid = srv.submit(pb["spec"], pb["state"], pb["chat"], req["steps"])
+            futures.append(pool.submit(collect, srv, rid, req, late))
         submitted = time.perf_counter() - t0
-        for rid, req, late in ids:
-            info = srv.wait(rid)
-            out, _, rc = srv.fetch(rid)
-            if rc:
-                raise RhdError(rc, f"request {req['id']} failed")
-            lat[req["id"]] = late + info["t_done"] - info["t_submit"]
-            zone_updates += info["zone_updates"]
+        zone_updates = 0
+        for f in futures:  # in submission order; the first failure is raised
+            i, latency, zu, out = f.result()
+            lat[i] = latency
+            zone_updates += zu
             if keep_results:
-                results[req["id"]] = out
+                results[i] = out
         elapsed = time.perf_counter() - t0
         st = srv.stats()
     p50, p99 = _percentiles(list(lat.values()))

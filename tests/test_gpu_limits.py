@@ -69,3 +69,32 @@ def test_binding_checks_array_sizes_before_the_call():
         P.rhd_destroy(h)
     with pytest.raises(ValueError):
         P.rhd_get_state(h, n)  # destroyed
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,rad_only", [((24, 20, 12), False), ((24, 20, 12), True),
+                                            ((40, 18, 1), False), ((100, 1, 1), True)])
+def test_footprint_equals_a_new_handles_device_bytes(precision, shape, rad_only):
+    """rhd_footprint_bytes, which the server's budget counts, is what a created handle
+    holds; per-cell opacities and an emissivity add their own arrays on top."""
+    print(f"[gpu case] footprint {shape} {precision} rad_only={rad_only}", flush=True)
+    nx, ny, nz = shape
+    spec = ri.default_spec(nx=nx, ny=ny, nz=nz, dx=1 / nx, dy=1 / max(ny, 1), dz=1 / max(nz, 1),
+                           rad_only=rad_only, exchange="none" if rad_only else "full",
+                           precision=precision)
+    p = P.params_from_spec(spec)
+    h = P.rhd_create(p)
+    try:
+        assert P.rhd_device_bytes(h) == P.rhd_footprint_bytes(p)
+        st = ri.smooth_random_state(spec, seed=5)
+        n = nx * ny * nz
+        es = 4 if precision == "mixed" else 8
+        mom = np.stack([st["mx"], st["my"], st["mz"]]).ravel()
+        fr = np.stack([st["Fx"], st["Fy"], st["Fz"]]).ravel()
+        P.rhd_set_state(h, st["rho"].ravel(), mom, st["E"].ravel(), st["Er"].ravel(), fr,
+                        st["kP"].ravel(), st["kF"].ravel(), 0)
+        assert P.rhd_device_bytes(h) == P.rhd_footprint_bytes(p) + 2 * n * es
+        P.rhd_set_emission(h, np.full(n, 0.5))
+        assert P.rhd_device_bytes(h) == P.rhd_footprint_bytes(p) + 3 * n * es
+    finally:
+        P.rhd_destroy(h)
