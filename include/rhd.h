@@ -159,7 +159,9 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out);
    Planck-mean and flux-mean specific opacities: N values each, or one value each when
    kappa_scalar is 1. kappa_P multiplies the exchange term (a_R T^4 - E_r) and kappa_F
    every F and v term (Sec. 2.1, Eq. mixedframe:kappas). In mixed precision the values
-   are rounded to FP32. Synchronises. */
+   are rounded to FP32 (to nearest) on the host. Host arrays travel through pinned host
+   chunks the library shares among all handles (two of 4 MiB per transfer in progress,
+   kept until the process ends). Synchronises. */
 int rhd_set_state(rhd_t* h, const double* rho, const double* mom, const double* E,
                   const double* Er, const double* Fr, const double* kappaP,
                   const double* kappaF, int kappa_scalar);
@@ -219,8 +221,8 @@ int rhd_suggest_dt(rhd_t* h, double chat, double* dt_gas, int* nsub);
    this itself with its own chat). Asynchronous; read it with rhd_get_diagnostics. */
 int rhd_ledger(rhd_t* h, double chat);
 
-/* Copy the state out into host FP64 arrays laid out as for rhd_set_state. Any pointer
-   may be NULL to skip that field. Synchronises. */
+/* Copy the state out into host FP64 arrays laid out as for rhd_set_state (through the
+   same pinned chunks). Any pointer may be NULL to skip that field. Synchronises. */
 int rhd_get_state(rhd_t* h, double* rho, double* mom, double* E, double* Er, double* Fr);
 
 /* Same as rhd_get_state into device FP64 arrays. Enqueued, no synchronisation. */

@@ -44,7 +44,6 @@ struct Buffers {
   void* rh[4] = {};    // padded radiation half-step
   void* sn[4] = {};    // saved gas sources s_n
   void* wh[4] = {};    // saved (rho, v) at the gas half step
-  double* staging = nullptr;         // N doubles for host transfers
   double* ledger_partials = nullptr; // 5 x LEDGER_BLOCKS
   double* ledger = nullptr;          // 5
   void* vmax_partials = nullptr;     // VMAX_BLOCKS of T
@@ -276,7 +275,6 @@ long long footprint(const rhd_params* p, long long* N_out, long long* NP_out) {
   bytes += 9 * cell;                    // state
   bytes += 4 * pad;                     // radiation half step
   if (gas) bytes += 5 * pad + 8 * cell; // gas half step, s_n, W_1/2
-  bytes += slab_round(N * 8);           // staging
   bytes += slab_round(5 * LEDGER_BLOCKS * 8) + slab_round(5 * 8) + slab_round(VMAX_BLOCKS * 8) +
            slab_round(8) + slab_round(rhdk::EXCH_STATS * EXCH_BLOCKS * 8) +
            slab_round(rhdk::CTR_COUNT * 8);
@@ -870,31 +868,136 @@ int run_impl(rhd_t* h, int nsteps, const double* dt, const int* nsub, double cha
   return enqueue_ledger<T>(h, chat);
 }
 
+// Host transfers go through pairs of pinned chunks: the host converts (FP32 state) or
+// copies one chunk while the copy engine moves the other, so a transfer needs no device
+// staging array, no conversion kernel and no pageable copy (which the runtime stages with
+// copy kernels that compete with other work for the compute units). The pairs are shared
+// by every handle and kept until the process ends; a transfer holds one for its duration.
+struct Stager {
+  int device = 0;
+  void* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+};
+constexpr size_t STAGE_BYTES = size_t(4) << 20;
+std::mutex g_stage_mutex;
+std::vector<Stager*> g_stage_free;
+
+// A stager of the handle's device for the current transfer; null when pinned memory or
+// events cannot be had. Its chunks' copies have finished when it is returned.
+class StagerLease {
+ public:
+  explicit StagerLease(int device) {
+    {
+      std::lock_guard<std::mutex> lock(g_stage_mutex);
+      for (size_t i = 0; i < g_stage_free.size(); ++i)
+        if (g_stage_free[i]->device == device) {
+          st_ = g_stage_free[i];
+          g_stage_free.erase(g_stage_free.begin() + long(i));
+          return;
+        }
+    }
+    Stager* st = new (std::nothrow) Stager();
+    if (!st) return;
+    st->device = device;
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k) {
+      ok = hipHostMalloc(&st->buf[k], STAGE_BYTES, hipHostMallocDefault) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&st->ev[k], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+      for (int k = 0; k < 2; ++k) {
+        if (st->buf[k]) (void)hipHostFree(st->buf[k]);
+        if (st->ev[k]) (void)hipEventDestroy(st->ev[k]);
+      }
+      delete st;
+      return;
+    }
+    st_ = st;
+  }
+  ~StagerLease() {
+    if (!st_) return;
+    for (int k = 0; k < 2; ++k)
+      if (st_->pending[k]) {
+        (void)hipEventSynchronize(st_->ev[k]);
+        st_->pending[k] = false;
+      }
+    std::lock_guard<std::mutex> lock(g_stage_mutex);
+    g_stage_free.push_back(st_);
+  }
+  StagerLease(const StagerLease&) = delete;
+  StagerLease& operator=(const StagerLease&) = delete;
+  Stager* operator->() const { return st_; }
+  explicit operator bool() const { return st_ != nullptr; }
+
+ private:
+  Stager* st_ = nullptr;
+};
+
+// Host FP64 values into a device array of T (rounded to nearest in FP32); from device
+// FP64 values when from_host is false. The host array has been read when this returns.
 template <typename T>
 int upload_field(rhd_t* h, const double* src, void* dst, int n, bool from_host) {
-  const double* dsrc = src;
-  if (from_host) {
-    HIP_TRY(h, hipMemcpyAsync(h->b.staging, src, size_t(n) * sizeof(double), hipMemcpyHostToDevice,
-                              h->stream));
-    dsrc = h->b.staging;
+  if (!from_host) {
+    hipLaunchKernelGGL(rhdk::k_from_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream,
+                       src, as<T>(dst), n);
+    HIP_TRY(h, hipGetLastError());
+    return RHD_OK;
   }
-  hipLaunchKernelGGL(rhdk::k_from_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream, dsrc,
-                     as<T>(dst), n);
-  HIP_TRY(h, hipGetLastError());
-  if (from_host) HIP_TRY(h, hipStreamSynchronize(h->stream));
+  StagerLease st(h->device);
+  if (!st) return fail(h, RHD_ENOMEM, "pinned host staging could not be allocated");
+  constexpr size_t per = STAGE_BYTES / sizeof(T);
+  T* d = as<T>(dst);
+  int k = 0;
+  for (size_t o = 0; o < size_t(n); o += per, k ^= 1) {
+    const size_t c = std::min(per, size_t(n) - o);
+    if (st->pending[k]) {
+      HIP_TRY(h, hipEventSynchronize(st->ev[k]));
+      st->pending[k] = false;
+    }
+    T* q = static_cast<T*>(st->buf[k]);
+    for (size_t i = 0; i < c; ++i) q[i] = T(src[o + i]);
+    HIP_TRY(h, hipMemcpyAsync(d + o, q, c * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipEventRecord(st->ev[k], h->stream));
+    st->pending[k] = true;
+  }
   return RHD_OK;
 }
 
+// A device array of T into host FP64 values (or into device FP64 values when to_host is
+// false); the host array holds them when this returns.
 template <typename T>
 int download_field(rhd_t* h, const void* src, double* dst, int n, bool to_host) {
-  double* ddst = to_host ? h->b.staging : dst;
-  hipLaunchKernelGGL(rhdk::k_to_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream,
-                     as<T>(const_cast<void*>(src)), ddst, n);
-  HIP_TRY(h, hipGetLastError());
-  if (to_host) {
-    HIP_TRY(h, hipMemcpyAsync(dst, h->b.staging, size_t(n) * sizeof(double), hipMemcpyDeviceToHost,
+  const T* s = as<T>(const_cast<void*>(src));
+  if (!to_host) {
+    hipLaunchKernelGGL(rhdk::k_to_f64<T>, dim3(blocks_for(n, 256)), dim3(256), 0, h->stream, s,
+                       dst, n);
+    HIP_TRY(h, hipGetLastError());
+    return RHD_OK;
+  }
+  StagerLease st(h->device);
+  if (!st) return fail(h, RHD_ENOMEM, "pinned host staging could not be allocated");
+  constexpr size_t per = STAGE_BYTES / sizeof(T);
+  const size_t chunks = (size_t(n) + per - 1) / per;
+  // chunk j travels through buffer j mod 2; chunk j + 1 is on its way while j is converted
+  auto issue = [&](size_t j) -> int {
+    const size_t o = j * per, c = std::min(per, size_t(n) - o);
+    HIP_TRY(h, hipMemcpyAsync(st->buf[j & 1], s + o, c * sizeof(T), hipMemcpyDeviceToHost,
                               h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipEventRecord(st->ev[j & 1], h->stream));
+    st->pending[j & 1] = true;
+    return RHD_OK;
+  };
+  if (chunks > 0)
+    if (int rc = issue(0)) return rc;
+  for (size_t j = 0; j < chunks; ++j) {
+    if (j + 1 < chunks)
+      if (int rc = issue(j + 1)) return rc;
+    HIP_TRY(h, hipEventSynchronize(st->ev[j & 1]));
+    st->pending[j & 1] = false;
+    const size_t o = j * per, c = std::min(per, size_t(n) - o);
+    const T* q = static_cast<const T*>(st->buf[j & 1]);
+    for (size_t i = 0; i < c; ++i) dst[o + i] = double(q[i]);
   }
   return RHD_OK;
 }
@@ -1205,7 +1308,6 @@ int rhd_create(const rhd_params* p, void* hip_stream, rhd_t** out) {
     for (auto& q : h->b.sn) alloc(&q, N * es);
     for (auto& q : h->b.wh) alloc(&q, N * es);
   }
-  alloc(reinterpret_cast<void**>(&h->b.staging), N * sizeof(double));
   alloc(reinterpret_cast<void**>(&h->b.ledger_partials), 5 * LEDGER_BLOCKS * sizeof(double));
   alloc(reinterpret_cast<void**>(&h->b.ledger), 5 * sizeof(double));
   alloc(&h->b.vmax_partials, VMAX_BLOCKS * sizeof(double));
