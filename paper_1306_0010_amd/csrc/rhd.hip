@@ -389,13 +389,25 @@ constexpr int predict_rows() {
 
 int predict_rows(bool mixed, int rows) { return mixed ? rhdk::PREDICT_ROWS_FP32 : rows; }
 
+// Planes per z chunk of the predictor for a corrector chunk of zchunk planes: the FP32
+// predictor takes chunks of 11 whatever the corrector's (at 256^3 its launches took
+// 224-227 us at chunks of 8 to 13 against 235 us at 16, where the corrector is fastest;
+// the finer chunks leave a shorter tail of blocks), the FP64 one the corrector's.
+constexpr int PREDICT_ZCHUNK_FP32 = 11;
+template <typename T>
+constexpr int predict_chunk(int zchunk) {
+  return sizeof(T) == 4 ? PREDICT_ZCHUNK_FP32 : zchunk;
+}
+
+int predict_chunk(bool mixed, int zchunk) { return mixed ? PREDICT_ZCHUNK_FP32 : zchunk; }
+
 // One radiation subcycle with the tiled kernels (3D grids).
 template <typename T, int BY>
 void launch_tiled_rows(rhd_t* h, rhdk::RadPtrs<T> rad, rhdk::RadPtrs<T> rh, rhdk::GasView<T> view,
                        const rhdk::RadConst<T>& RK, T h_pred, T h_corr) {
   constexpr int PBY = predict_rows<T, BY>();
   const rhdk::Geom& G = h->G;
-  const rhdk::TileGrid tp = rhdk::tile_grid<PBY>(G.n, h->zchunk);
+  const rhdk::TileGrid tp = rhdk::tile_grid<PBY>(G.n, predict_chunk<T>(h->zchunk));
   const rhdk::TileGrid tg = rhdk::tile_grid<BY>(G.n, h->zchunk);
   const dim3 gp(tp.pred[0], tp.pred[1], tp.pred[2]);
   const dim3 gc(tg.corr[0], tg.corr[1], tg.corr[2]);
@@ -1859,7 +1871,8 @@ int batch_step_impl(rhd_batch_t* b, int* nsub_out, double* dt_out) {
     d.ctr = h->b.ctr;
     // the persistent launch runs both stages at the batch's rows
     const rhdk::TileGrid tp =
-        tile_counts(h, b->persistent ? b->rows : predict_rows(h->mixed, b->rows), b->zchunk);
+        b->persistent ? tile_counts(h, b->rows, b->zchunk)
+                      : tile_counts(h, predict_rows(h->mixed, b->rows), predict_chunk(h->mixed, b->zchunk));
     const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
     d.zc_pred = tp.zc_pred;
     d.zc_corr = tg.zc_corr;
@@ -2005,7 +2018,8 @@ int rhd_batch_add(rhd_batch_t* b, rhd_t* h, double chat) {
   // batch's rows, the round launches the predictor's own)
   auto pred_tiles = [&](const rhd_t* m) {
     const rhdk::TileGrid a = tile_counts(m, b->rows, b->zchunk);
-    const rhdk::TileGrid c = tile_counts(m, predict_rows(m->mixed, b->rows), b->zchunk);
+    const rhdk::TileGrid c =
+        tile_counts(m, predict_rows(m->mixed, b->rows), predict_chunk(m->mixed, b->zchunk));
     return std::max(a.pred[0] * a.pred[1] * a.pred[2], c.pred[0] * c.pred[1] * c.pred[2]);
   };
   const rhdk::TileGrid tg = tile_counts(h, b->rows, b->zchunk);
