@@ -42,7 +42,7 @@ FP32_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ("paper_1306_0010_amd/csrc/rhd_device.hpp", "paper_1306_0010_amd/csrc/rhd_tile.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 # tile shapes (rows, z chunk) of the corrector and the gas stages for the two grid sizes
-# on MI355X (the FP32 predictor takes 4 x 11 tiles on every grid): at 128^3 the one
+# on MI355X (the FP32 predictor takes 4-row tiles of at most 11 planes): at 128^3 the one
 # rhd_autotune picked; at 256^3 the fastest corrector of a sweep of rows 4-16 x chunks
 # 8-32 (8 x 16: 283-288 us; at 4 rows its unrolled plane loop spills and takes 343 us)
 TILE_C2 = (8, 8)

@@ -262,8 +262,8 @@ int rhd_get_timing(rhd_t* h, rhd_timing* out);
 
 /* Select the kernels of the radiation subcycle: variant RHD_KERNELS_*, tile_rows the
    rows of a 64-wide tile (4, 8 or 16; FP64 handles 4 or 8), zchunk the z-planes one tile
-   walks (>= 1). In mixed precision the predictor stage always runs 4-row tiles of 11
-   planes (its fastest shape on every grid measured) and tile_rows and zchunk set the
+   walks (>= 1). In mixed precision the predictor stage always runs 4-row tiles of at most
+   11 planes (its fastest shape on every grid measured) and tile_rows and zchunk set the
    corrector's and the gas stages'. Defaults after rhd_create: tiled, 8 rows, 8 planes. Results do not
    depend on the choice beyond rounding. RHD_EINVAL for values outside these sets. The
    tiled kernels address with 32-bit byte offsets: a grid whose padded arrays
@@ -303,8 +303,8 @@ typedef struct rhd_batch rhd_batch_t;
 /* Create a batch that advances up to max_solves independent 3D handles together: every
    radiation Van Leer stage of all members goes out as one launch over a packed list of
    tiles (64 x tile_rows cells, zchunk planes; tile_rows 4, 8 or 16 in mixed precision,
-   4 or 8 in FP64; in mixed precision the predictor's tiles are 4 rows by 11 planes, as
-   for a lone handle). hip_stream is a hipStream_t or NULL for an owned stream. */
+   4 or 8 in FP64; in mixed precision the predictor's tiles are 4 rows by at most 11
+   planes, as for a lone handle). hip_stream is a hipStream_t or NULL for an owned stream. */
 int rhd_batch_create(void* hip_stream, int max_solves, int tile_rows, int zchunk,
                      rhd_batch_t** out);
 

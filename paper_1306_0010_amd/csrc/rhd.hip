@@ -390,16 +390,19 @@ constexpr int predict_rows() {
 int predict_rows(bool mixed, int rows) { return mixed ? rhdk::PREDICT_ROWS_FP32 : rows; }
 
 // Planes per z chunk of the predictor for a corrector chunk of zchunk planes: the FP32
-// predictor takes chunks of 11 whatever the corrector's (at 256^3 its launches took
-// 224-227 us at chunks of 8 to 13 against 235 us at 16, where the corrector is fastest;
-// the finer chunks leave a shorter tail of blocks), the FP64 one the corrector's.
+// predictor takes at most 11 (at 256^3 its launches took 224-229 us at chunks of 8 to 14
+// against 235 us at 16, where the corrector is fastest; at 128^3 it is fastest at the
+// corrector's 8, 42.5 against 43.8 us at 11, where fewer blocks than the chip holds at
+// once would run), the FP64 one the corrector's.
 constexpr int PREDICT_ZCHUNK_FP32 = 11;
 template <typename T>
 constexpr int predict_chunk(int zchunk) {
-  return sizeof(T) == 4 ? PREDICT_ZCHUNK_FP32 : zchunk;
+  return sizeof(T) == 4 ? std::min(zchunk, PREDICT_ZCHUNK_FP32) : zchunk;
 }
 
-int predict_chunk(bool mixed, int zchunk) { return mixed ? PREDICT_ZCHUNK_FP32 : zchunk; }
+int predict_chunk(bool mixed, int zchunk) {
+  return mixed ? std::min(zchunk, PREDICT_ZCHUNK_FP32) : zchunk;
+}
 
 // One radiation subcycle with the tiled kernels (3D grids).
 template <typename T, int BY>
