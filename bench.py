@@ -44,9 +44,10 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 # tile shapes (rows, z chunk) of the corrector and the gas stages for the two grid sizes
 # on MI355X (the FP32 predictor takes 4-row tiles of at most 11 planes): at 128^3 the one
 # rhd_autotune picked; at 256^3 the fastest corrector of a sweep of rows 4-16 x chunks
-# 8-32 (8 x 16: 283-288 us; at 4 rows its unrolled plane loop spills and takes 343 us)
+# 8-256: 16 x 64, one block per CU (277-281 us; 8 x 16 and 8 x 32 take 283-288, 16 x 16
+# 299; at 4 rows its unrolled plane loop spills and takes 343 us)
 TILE_C2 = (8, 8)
-TILE_C3 = (8, 16)
+TILE_C3 = (16, 64)
 
 
 def algorithmic_bytes_per_cell(kernel, spec, has_j, kappa_field):
