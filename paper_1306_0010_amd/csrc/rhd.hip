@@ -391,9 +391,9 @@ int predict_rows(bool mixed, int rows) { return mixed ? rhdk::PREDICT_ROWS_FP32 
 
 // Planes per z chunk of the predictor for a corrector chunk of zchunk planes: the FP32
 // predictor takes at most 11 (at 256^3 its launches took 224-229 us at chunks of 8 to 14
-// against 235 us at 16, where the corrector is fastest; at 128^3 it is fastest at the
-// corrector's 8, 42.5 against 43.8 us at 11, where fewer blocks than the chip holds at
-// once would run), the FP64 one the corrector's.
+// against 235 us at 16 and 245 at 32, while the corrector is fastest at 64; at 128^3 it
+// is fastest at the corrector's 8, 42.5 against 43.8 us at 11, where fewer blocks than
+// the chip holds at once would run), the FP64 one the corrector's.
 constexpr int PREDICT_ZCHUNK_FP32 = 11;
 template <typename T>
 constexpr int predict_chunk(int zchunk) {
