@@ -176,7 +176,7 @@ def replay(n, bc, BY, zc):
     ((64, 16, 9), (2, 2, 1, 1, 0, 0)),
     ((130, 4, 3), (1, 1, 0, 0, 2, 2)),
 ])
-@pytest.mark.parametrize("BY,zc", [(4, 16), (8, 16), (16, 5), (8, 1), (4, 7)])
+@pytest.mark.parametrize("BY,zc", [(4, 16), (8, 16), (16, 5), (8, 1), (4, 7), (4, 11), (16, 64)])
 def test_tiled_kernel_indexing(n, bc, BY, zc):
     replay(n, bc, BY, zc)
 
