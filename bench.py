@@ -880,8 +880,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: a run on several GPUs is not "
-                                   "implemented (the one-GPU path is --gpus 1)",
+        print(json.dumps({"error": "the benchmark runs on one GPU: a run on several GPUs is "
+                                   "not implemented (the one-GPU path is --gpus 1)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
